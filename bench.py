@@ -1,0 +1,227 @@
+"""Benchmark: sparse triangular solves on one MI355X.
+
+Workload (default): lower and upper triangles (diagonal included) of the 3-D
+7-point Laplacian on a 128^3 grid, natural order, FP64 CSR, one right-hand
+side.  One step is the paper's experiment (Sec. 5, eq. (3)): the lower solve
+followed by the upper solve, y = U^{-1} (L^{-1} b), with the self-scheduled
+solver (the schedule under test) -- and the same step is timed with the
+level-scheduled solver for the speedup.
+
+Metric: effective HBM GB/s = algorithmic bytes / time, with the bytes lower
+bound of one solve nnz*(vb+4) + (n+1)*4 + 3*n*vb (matrix values and indices
+once, row pointers once, b read, x written, x read once by dependents),
+summed over the two triangles of a step; also solves/s.  Inputs are resident
+in HBM before the timed region.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Prints one JSON line.  --suite also writes per-configuration lines for the
+other workloads to gpurun_out/bench_suite.jsonl.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "SpTRSV effective HBM GB/s + solves/s (FP64, 1e-12 rel) vs level-scheduled"
+
+
+def lb_bytes(n, nnz, vb=8, k=1):
+    return nnz * (vb + 4) + (n + 1) * 4 + 3 * n * vb * k
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--side", type=int, default=128)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--suite", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_info():
+    model = platform.processor()
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def cpu_baseline(TL, TU, bL, seconds):
+    """The oracle (plain C, FP64, one thread) on the same L+U step, repeated
+    for about `seconds` of CPU time."""
+    import oracle
+    o = oracle.get()
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        y = o.solve(TL.row_ptr, TL.col_idx, TL.vals, bL, False)
+        o.solve(TU.row_ptr, TU.col_idx, TU.vals, y, True)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    return el / reps, reps
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import workloads as W
+    import paper_1710_04985_amd as sp
+
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    side = args.side
+    TL, xsL, bL = W.c2_lap3d(side=side, upper=False)
+    TU = W.laplacian_triangle((side,) * 3, upper=True, diag=6.0)
+
+    def to_dev(T):
+        return (torch.from_numpy(T.row_ptr).to(dev), torch.from_numpy(T.col_idx).to(dev),
+                torch.from_numpy(T.vals).to(dev))
+
+    dL, dU = to_dev(TL), to_dev(TU)
+    b = torch.from_numpy(bL).to(dev)
+    torch.cuda.synchronize()
+
+    t0 = time.perf_counter()
+    hL = sp.Handle(*dL, uplo="L")
+    analysis_ms = (time.perf_counter() - t0) * 1e3
+    hU = sp.Handle(*dU, uplo="U")
+    lvL = sp.Handle(*dL, uplo="L").configure(algo=sp.ALGO_LEVEL)
+    lvU = sp.Handle(*dU, uplo="U").configure(algo=sp.ALGO_LEVEL)
+    nlev = hL.info()["nlev"]
+
+    # the self-scheduled solver: the library's autotuner picks lanes per row
+    # and the readiness signal among the self-scheduled candidates; the
+    # level-scheduled baseline is tuned the same way among its own
+    tuned = {}
+    if not args.no_tune:
+        for name, h in (("L", hL), ("U", hU), ("L_level", lvL), ("U_level", lvU)):
+            if h in (hL, hU):
+                h.set_option("algo", sp.ALGO_SELF)
+            tuned[name] = h.tune(b)
+    else:
+        hL.set_option("algo", sp.ALGO_SELF)
+        hU.set_option("algo", sp.ALGO_SELF)
+
+    def step(hl, hu, out1, out2):
+        hl.solve(b, out=out1)
+        hu.solve(out1, out=out2)
+
+    y1 = torch.empty_like(b)
+    y2 = torch.empty_like(b)
+
+    # parity of the timed configuration against the oracle at full size
+    import oracle
+    o = oracle.get()
+    step(hL, hU, y1, y2)
+    hL.status()
+    hU.status()
+    xo1 = o.solve(TL.row_ptr, TL.col_idx, TL.vals, bL, False)
+    xo2 = o.solve(TU.row_ptr, TU.col_idx, TU.vals, xo1, True)
+    r1 = y1.cpu().numpy()
+    r2 = y2.cpu().numpy()
+    err = max(np.abs(r1 - xo1).max() / np.abs(xo1).max(), np.abs(r2 - xo2).max() / np.abs(xo2).max())
+    step(lvL, lvU, y1, y2)
+    err_level = max(np.abs(y1.cpu().numpy() - xo1).max() / np.abs(xo1).max(),
+                    np.abs(y2.cpu().numpy() - xo2).max() / np.abs(xo2).max())
+    if err > 1e-12 or err_level > 1e-12:
+        print("parity failure: self %.3e level %.3e" % (err, err_level), file=sys.stderr)
+        sys.exit(1)
+
+    def timed(hl, hu, steps, warmup):
+        for _ in range(warmup):
+            step(hl, hu, y1, y2)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            step(hl, hu, y1, y2)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    ms_self = timed(hL, hU, args.steps, args.warmup)
+    ms_level = timed(lvL, lvU, args.steps, args.warmup)
+
+    # per-kernel durations of the self-scheduled solve kernel (HIP events the
+    # library records on the solve stream around the kernel launch)
+    for h in (hL, hU):
+        h.set_option("timing", 1)
+        h.kernel_time(reset=True)
+    timed(hL, hU, args.steps, 2)
+    kmsL, kcL = hL.kernel_time()
+    kmsU, kcU = hU.kernel_time()
+    for h in (hL, hU):
+        h.set_option("timing", 0)
+    kernel_ms = (kmsL + kmsU) / max(1, kcL + kcU)
+
+    lbL = lb_bytes(TL.n, TL.nnz)
+    lbU = lb_bytes(TU.n, TU.nnz)
+    step_bytes = lbL + lbU
+    gbs = step_bytes / (ms_self * 1e-3) / 1e9
+    gbs_level = step_bytes / (ms_level * 1e-3) / 1e9
+    achieved = lbL / (kernel_ms * 1e-3) / 1e9
+
+    out = {
+        "metric": METRIC,
+        "value": round(gbs, 3),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_self, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic: 3-D 7-point Laplacian triangles (diag 6, off-diag -1), b = L x*, x* ~ U[-1,1] seed 2",
+        "config": {"workload": "lap3d_7pt_%d^3_lower_then_upper" % side, "n": TL.n,
+                   "nnz_per_triangle": TL.nnz, "nlev": nlev, "rhs": 1,
+                   "solver": "self-scheduled", "tuned": tuned},
+        "solves_per_s": round(2.0 / (ms_self * 1e-3), 2),
+        "level_scheduled": {"ms_per_step": round(ms_level, 5), "gbs": round(gbs_level, 3),
+                            "solves_per_s": round(2.0 / (ms_level * 1e-3), 2)},
+        "speedup_self_vs_level": round(ms_level / ms_self, 3),
+        "max_rel_err_vs_oracle": float("%.3e" % err),
+        "analysis_ms": round(analysis_ms, 2),
+        "bytes_per_step": step_bytes,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                     "kernel": "k_self_flag<double>" if hL.info()["sync"] == sp.SYNC_FLAG
+                     else "k_self_value<double>",
+                     "kernel_ms": round(kernel_ms, 5), "bytes_per_launch": lbL},
+    }
+    if not args.no_cpu_baseline:
+        t_cpu, reps = cpu_baseline(TL, TU, bL, args.cpu_seconds)
+        model, ncpu = cpu_info()
+        out["cpu_baseline"] = {"value": round(step_bytes / t_cpu / 1e9, 4), "unit": "GB/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": "%d full L+U steps of the same workload (%.1f ms each) on %s, "
+                                         "%d host CPUs visible" % (reps, t_cpu * 1e3, model, ncpu)}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

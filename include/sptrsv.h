@@ -1,0 +1,236 @@
+/*
+ * sptrsv.h -- C ABI of libsptrsv, sparse triangular solves on MI355X (gfx950).
+ *
+ * Method: R. Li, "On Parallel Solution of Sparse Triangular Linear Systems in
+ * CUDA" (arXiv:1710.04985).  The library solves  T x = b  with T a sparse
+ * lower or upper triangle in CSR form (Sec. 3, eq. (1)), after a setup
+ * ("analysis") phase that computes the level sets of the dependency DAG
+ * (Sec. 4.1, Sec. 4.4).  Two solve schedules are provided:
+ *   - level-scheduled (Sec. 4.1, Algorithm LEVR): one kernel launch per level;
+ *   - self-scheduled (Sec. 4.2, Algorithm SLFR): one persistent launch whose
+ *     waves take rows in level order and wait on per-row readiness instead of
+ *     a global synchronisation between levels.
+ *
+ * Conventions shared by every entry point
+ *   - Indices are int32, 0-based.  The diagonal is stored INSIDE each row
+ *     (the paper keeps it in a separate vector d); its position in the row is
+ *     free.  Columns need not be sorted.
+ *   - Matrix arrays (row_ptr, col_idx, vals) and vectors (b, x, B, X, ...)
+ *     are DEVICE pointers owned by the caller.  row_ptr and col_idx are read
+ *     during analysis only.  vals is gathered into the handle's own level-
+ *     ordered copy during analysis and by sptrsv_update_values; the solves
+ *     never read the caller's vals, so the caller must call
+ *     sptrsv_update_values after changing them.
+ *   - Every function returns an int status: SPTRSV_OK (0) or a negative
+ *     sptrsv_status.  Handles are opaque and owned by the library until
+ *     sptrsv_destroy.
+ *   - Solves are asynchronous on the given HIP stream (NULL = default stream)
+ *     and perform no allocation, host synchronisation or memset, so they can
+ *     be captured in a HIP graph once the handle has been prepared (first
+ *     transpose solve or explicit sptrsv_prepare_transpose; option changes
+ *     made before capture).  Calls on one handle must be issued on one stream
+ *     at a time: the handle's scratch (ticket, flags, epoch) is shared.
+ *   - n = 0 is valid and every solve on it is a no-op.
+ *   - Dependencies are taken from the pattern (Sec. 4.4): an explicitly
+ *     stored zero off-diagonal still counts as a dependency.
+ */
+#ifndef SPTRSV_H_
+#define SPTRSV_H_
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sptrsv_handle_s *sptrsv_handle_t;
+typedef struct sptrsv_graph_s *sptrsv_graph_t;
+
+typedef enum {
+    SPTRSV_OK = 0,
+    SPTRSV_ERR_INVALID_ARG = -1,    /* null pointer, n < 0, bad enum, bad option */
+    SPTRSV_ERR_BAD_ROWPTR = -2,     /* row_ptr[0] != 0, row_ptr[n] != nnz, or decreasing */
+    SPTRSV_ERR_BAD_COLIDX = -3,     /* column index outside [0, n) */
+    SPTRSV_ERR_NOT_TRIANGULAR = -4, /* entry on the wrong side of the diagonal */
+    SPTRSV_ERR_DUPLICATE = -5,      /* a column appears twice in one row */
+    SPTRSV_ERR_MISSING_DIAG = -6,   /* no stored diagonal (and unit_diag == 0) */
+    SPTRSV_ERR_ZERO_PIVOT = -7,     /* stored diagonal exactly 0.0 (and unit_diag == 0) */
+    SPTRSV_ERR_HIP = -8,            /* a HIP runtime call failed */
+    SPTRSV_ERR_OOM = -9,            /* device or host allocation failed */
+    SPTRSV_ERR_TIMEOUT = -10,       /* self-scheduled wait exceeded its spin limit */
+    SPTRSV_ERR_NOT_SUPPORTED = -11  /* valid request this build does not implement */
+} sptrsv_status;
+
+typedef enum { SPTRSV_F64 = 0, SPTRSV_F32 = 1 } sptrsv_dtype;
+typedef enum { SPTRSV_LOWER = 0, SPTRSV_UPPER = 1 } sptrsv_uplo;
+
+typedef enum {
+    SPTRSV_ALGO_AUTO = 0,   /* autotuner's choice (heuristic, or timed by sptrsv_tune) */
+    SPTRSV_ALGO_LEVEL = 1,  /* level-scheduled: one launch per level (Sec. 4.1) */
+    SPTRSV_ALGO_SELF = 2,   /* self-scheduled: one persistent launch (Sec. 4.2) */
+    SPTRSV_ALGO_BLOCK = 3   /* level-scheduled inside one workgroup per independent
+                               system (block-diagonal batches, small n): the level
+                               barrier is a workgroup barrier, not a launch */
+} sptrsv_algo;
+
+typedef enum {
+    SPTRSV_SYNC_VALUE = 0,  /* self-scheduled readiness carried by x itself: x is
+                               pre-filled with a signalling-NaN sentinel and each
+                               x_i is published by one agent-scope atomic store */
+    SPTRSV_SYNC_FLAG = 1    /* per-row ready flags stamped with a per-solve epoch,
+                               agent-scope release/acquire (Sec. 4.2 counters,
+                               without the per-solve reset) */
+} sptrsv_sync;
+
+typedef enum {
+    SPTRSV_OPT_ALGO = 0,          /* sptrsv_algo */
+    SPTRSV_OPT_GROUP = 1,         /* lanes per row G in {1,2,4,...,64}; 0 = by row length */
+    SPTRSV_OPT_ENTRIES_PER_LANE = 2, /* target entries per lane when GROUP = 0 (default 4) */
+    SPTRSV_OPT_SYNC = 3,          /* sptrsv_sync (self-scheduled only) */
+    SPTRSV_OPT_SPIN_LIMIT = 4,    /* max polls of one dependency before TIMEOUT (>= 1) */
+    SPTRSV_OPT_GRID = 5,          /* persistent workgroups; 0 = sized from occupancy */
+    SPTRSV_OPT_TIMING = 6,        /* 1 = record HIP events around the main solve kernel */
+    SPTRSV_OPT_WG = 7             /* threads per workgroup for the row kernels (64..1024) */
+} sptrsv_option;
+
+/* ---------------------------------------------------------------------- */
+/* Analysis (setup phase, Sec. 4.4): validates the triangle, computes the
+ * levels lev(i) = 1 + max lev(j) over stored off-diagonals j of row i
+ * (0-based: rows without dependencies are level 0), the level sets
+ * (jlev = rows ordered by (level, row), ilev = level pointers) and the
+ * dependency counts, and builds the level-ordered device copy of the
+ * matrix the kernels stream.
+ *   n, nnz     matrix order and stored entries (diagonal included)
+ *   row_ptr    device int32[n+1];  col_idx device int32[nnz]
+ *   vals       device double[nnz] (F64) or float[nnz] (F32)
+ *   uplo       SPTRSV_LOWER: forward substitution; SPTRSV_UPPER: backward
+ *   unit_diag  nonzero: the diagonal is 1, stored diagonal entries ignored
+ *              (and may be absent)
+ *   stream     stream for the device copies; the call synchronises it
+ *   out        receives the new handle (NULL on failure)
+ * Errors: INVALID_ARG, BAD_ROWPTR, BAD_COLIDX, NOT_TRIANGULAR, DUPLICATE,
+ * MISSING_DIAG, ZERO_PIVOT, HIP, OOM.  Blocking: copies the pattern to the
+ * host, computes there, uploads the result. */
+int sptrsv_analyze(int32_t n, int32_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                   const void *vals, sptrsv_dtype dtype, sptrsv_uplo uplo, int unit_diag,
+                   hipStream_t stream, sptrsv_handle_t *out);
+
+/* Batched analysis of `count` independent triangles of one dtype/uplo, solved
+ * together as their block-diagonal concatenation (rows and columns of system
+ * s offset by the sizes of systems 0..s-1).  n, nnz: host int32[count];
+ * row_ptr, col_idx, vals: host arrays of device pointers, one per system.
+ * The solves take b and x as the concatenation of the systems' vectors.
+ * The concatenation shares one level structure, so one launch serves all
+ * systems (levels of different systems interleave).  Errors as for
+ * sptrsv_analyze, reported for the first failing system. */
+int sptrsv_analyze_batched(int32_t count, const int32_t *n, const int32_t *nnz,
+                           const int32_t *const *row_ptr, const int32_t *const *col_idx,
+                           const void *const *vals, sptrsv_dtype dtype, sptrsv_uplo uplo,
+                           int unit_diag, hipStream_t stream, sptrsv_handle_t *out);
+
+/* Re-gather new values for the same pattern (the caller's vals, device).
+ * Asynchronous on `stream`; a zero pivot is reported through
+ * sptrsv_get_status after the stream has been synchronised. */
+int sptrsv_update_values(sptrsv_handle_t h, const void *vals, hipStream_t stream);
+
+/* Batched form: vals is a host array of `count` device pointers. */
+int sptrsv_update_values_batched(sptrsv_handle_t h, const void *const *vals, hipStream_t stream);
+
+/* ---------------------------------------------------------------------- */
+/* Solve T x = b (forward for lower, backward for upper; Sec. 3).
+ * b, x: device vectors of n elements of the handle's dtype.  b == x (in
+ * place) is allowed; partial overlap is not.  Asynchronous. */
+int sptrsv_solve(sptrsv_handle_t h, const void *b, void *x, hipStream_t stream);
+
+/* Solve T^T x = b.  Uses the analysis of T^T (the column-wise view of
+ * Sec. 3.2: rows of T^T are the columns of T, levels from the reversed
+ * sweep); built on first use, which then blocks, or in advance by
+ * sptrsv_prepare_transpose. */
+int sptrsv_solve_transpose(sptrsv_handle_t h, const void *b, void *x, hipStream_t stream);
+
+/* Build the analysis of T^T now (blocking). */
+int sptrsv_prepare_transpose(sptrsv_handle_t h, hipStream_t stream);
+
+/* Several right-hand sides, column-major: column r of B starts at B + r*ld.
+ * nrhs >= 1, ld >= n.  Each row of T is read once for all columns.  B == X
+ * allowed.  transpose != 0 solves T^T X = B. */
+int sptrsv_solve_multi(sptrsv_handle_t h, int32_t nrhs, int32_t ld, const void *B, void *X,
+                       int transpose, hipStream_t stream);
+
+/* Gradient of the solve with respect to the stored values (the adjoint of
+ * x = T^{-1} b on the pattern): grad_vals[k] = -grad_b[i] * x[j] for each
+ * stored entry k = (i, j) of the caller's CSR, in the caller's entry order;
+ * 0 for stored diagonal entries when unit_diag.  grad_b = T^{-T} g comes from
+ * sptrsv_solve_transpose.  row_ptr / col_idx are the caller's device arrays
+ * given to sptrsv_analyze (for a batched handle: NULL, the concatenated
+ * pattern kept by the handle is used and grad_vals is concatenated). */
+int sptrsv_grad_vals(sptrsv_handle_t h, const int32_t *row_ptr, const int32_t *col_idx,
+                     const void *grad_b, const void *x, void *grad_vals, hipStream_t stream);
+
+/* ---------------------------------------------------------------------- */
+/* Options and information */
+int sptrsv_set_option(sptrsv_handle_t h, sptrsv_option key, int64_t value);
+int sptrsv_get_option(sptrsv_handle_t h, sptrsv_option key, int64_t *value);
+
+/* Time short trials of the candidate schedules on (b, x) -- both device
+ * vectors of n elements, x overwritten -- and keep the fastest (ALGO, GROUP,
+ * SYNC).  Results are cached per pattern hash in the process. */
+int sptrsv_tune(sptrsv_handle_t h, const void *b, void *x, hipStream_t stream);
+
+/* n, nnz, nlev of T; the algorithm and lanes per row the next solve uses
+ * (resolved if AUTO); any pointer may be NULL. */
+int sptrsv_get_info(sptrsv_handle_t h, int32_t *n, int64_t *nnz, int32_t *nlev,
+                    int32_t *algo, int32_t *group);
+
+/* The schedule the next solve will use (resolved: the autotuner's choice if
+ * current, else the options): sptrsv_algo, lanes per row (0 = by row
+ * length), entries per lane of the length rule, sptrsv_sync.  Any pointer
+ * may be NULL. */
+int sptrsv_get_schedule(sptrsv_handle_t h, int32_t *algo, int32_t *group,
+                        int32_t *entries_per_lane, int32_t *sync);
+
+/* Copy the analysis to HOST buffers (any may be NULL): level int32[n],
+ * ilev int32[nlev+1], jlev int32[n] (rows by (level, row)), depcnt int32[n]
+ * (stored off-diagonals per row).  transpose != 0 exports the analysis of
+ * T^T (built if needed). */
+int sptrsv_export_analysis(sptrsv_handle_t h, int transpose, int32_t *level, int32_t *ilev,
+                           int32_t *jlev, int32_t *depcnt);
+
+/* Device-side status of the last solves: synchronises the handle's last
+ * stream, returns SPTRSV_OK, SPTRSV_ERR_TIMEOUT or SPTRSV_ERR_ZERO_PIVOT,
+ * and clears it. */
+int sptrsv_get_status(sptrsv_handle_t h);
+
+/* Accumulated duration of the main solve kernels recorded while
+ * SPTRSV_OPT_TIMING = 1 (milliseconds, HIP events on the solve stream) and
+ * the number of launches timed; synchronises.  reset != 0 clears both. */
+int sptrsv_kernel_time(sptrsv_handle_t h, double *ms, int64_t *count, int reset);
+
+const char *sptrsv_status_string(int status);
+
+int sptrsv_destroy(sptrsv_handle_t h);
+
+/* ---------------------------------------------------------------------- */
+/* HIP graph of one solve (or transposed solve) on fixed b/x pointers:
+ * captured once on `stream`, replayed by sptrsv_graph_launch.  The handle's
+ * options are frozen into the graph. */
+int sptrsv_graph_capture(sptrsv_handle_t h, const void *b, void *x, int transpose,
+                         hipStream_t stream, sptrsv_graph_t *out);
+int sptrsv_graph_launch(sptrsv_graph_t g, hipStream_t stream);
+int sptrsv_graph_destroy(sptrsv_graph_t g);
+
+/* ---------------------------------------------------------------------- */
+/* Host-only analysis (no device memory, no GPU needed): the same validation,
+ * levels, level sets and dependency counts sptrsv_analyze computes, on HOST
+ * arrays.  level/jlev/depcnt: int32[n]; ilev: int32[n+1] capacity (nlev+1
+ * used); nlev: out.  Returns the validation status (vals not inspected, so
+ * no ZERO_PIVOT). */
+int sptrsv_analyze_host(int32_t n, int32_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                        sptrsv_uplo uplo, int unit_diag, int32_t *level, int32_t *ilev,
+                        int32_t *jlev, int32_t *depcnt, int32_t *nlev);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPTRSV_H_ */

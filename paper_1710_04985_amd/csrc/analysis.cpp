@@ -1,0 +1,218 @@
+// Host-side setup phase: validation, levels, level sets, layout, chunks.
+// Section references are to Li, arXiv:1710.04985.
+#include "analysis.hpp"
+
+#include <algorithm>
+#include <cstring>
+
+namespace sptrsv {
+
+int validate_pattern(int n, int64_t nnz, const int* row_ptr, const int* col, bool upper,
+                     bool unit_diag, std::vector<int>* diag_pos) {
+  if (n < 0 || nnz < 0) return kErrInvalidArg;
+  if (n == 0) return nnz == 0 ? kOk : kErrBadRowPtr;
+  if (row_ptr[0] != 0 || row_ptr[n] != nnz) return kErrBadRowPtr;
+  for (int i = 0; i < n; ++i)
+    if (row_ptr[i + 1] < row_ptr[i]) return kErrBadRowPtr;
+  // last_seen[j] == i marks column j as already present in row i
+  std::vector<int> last_seen(n, -1);
+  std::vector<int> dpos(n, -1);
+  int status = kOk;
+  for (int i = 0; i < n; ++i) {
+    for (int k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+      const int j = col[k];
+      if (j < 0 || j >= n) return kErrBadColIdx;
+      if (upper ? (j < i) : (j > i)) status = status ? status : kErrNotTriangular;
+      if (last_seen[j] == i) status = status ? status : kErrDuplicate;
+      last_seen[j] = i;
+      if (j == i) dpos[i] = k;
+    }
+  }
+  if (status) return status;
+  if (!unit_diag) {
+    for (int i = 0; i < n; ++i)
+      if (dpos[i] < 0) return kErrMissingDiag;
+  }
+  if (diag_pos) diag_pos->swap(dpos);
+  return kOk;
+}
+
+int compute_levels(int n, const int* row_ptr, const int* col, bool upper, int* level) {
+  int nlev = 0;
+  for (int s = 0; s < n; ++s) {
+    const int i = upper ? n - 1 - s : s;
+    int lv = 0;
+    for (int k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+      const int j = col[k];
+      if (j != i) lv = std::max(lv, level[j] + 1);
+    }
+    level[i] = lv;
+    nlev = std::max(nlev, lv + 1);
+  }
+  return nlev;
+}
+
+void level_sets(int n, const int* level, int nlev, int* ilev, int* jlev) {
+  std::vector<int> count(nlev + 1, 0);
+  for (int i = 0; i < n; ++i) count[level[i]]++;
+  ilev[0] = 0;
+  for (int m = 0; m < nlev; ++m) ilev[m + 1] = ilev[m] + count[m];
+  std::vector<int> fill(ilev, ilev + nlev);
+  for (int i = 0; i < n; ++i) jlev[fill[level[i]]++] = i;
+}
+
+void dependency_counts(int n, const int* row_ptr, const int* col, int* depcnt) {
+  for (int i = 0; i < n; ++i) {
+    int c = row_ptr[i + 1] - row_ptr[i];
+    for (int k = row_ptr[i]; k < row_ptr[i + 1]; ++k) c -= (col[k] == i);
+    depcnt[i] = c;
+  }
+}
+
+void transpose_pattern(int n, const int* row_ptr, const int* col, std::vector<int>& rowT,
+                       std::vector<int>& colT, std::vector<int>& srcT) {
+  const int64_t nnz = row_ptr[n];
+  rowT.assign(n + 1, 0);
+  colT.resize(nnz);
+  srcT.resize(nnz);
+  for (int64_t k = 0; k < nnz; ++k) rowT[col[k] + 1]++;
+  for (int j = 0; j < n; ++j) rowT[j + 1] += rowT[j];
+  std::vector<int> next(rowT.begin(), rowT.end() - 1);
+  for (int i = 0; i < n; ++i)
+    for (int k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+      const int d = next[col[k]]++;
+      colT[d] = i;
+      srcT[d] = k;
+    }
+}
+
+static inline int bit_length(unsigned v) { return v ? 32 - __builtin_clz(v) : 0; }
+
+void build_plan(int n, const int* row_ptr, const int* col, const int* src, bool upper,
+                bool unit_diag, HostPlan& p) {
+  p = HostPlan();
+  p.n = n;
+  p.upper = upper;
+  p.unit_diag = unit_diag;
+  p.nnz = n ? row_ptr[n] : 0;
+  p.level.resize(n);
+  p.jlev.resize(n);
+  p.depcnt.resize(n);
+  p.nlev = compute_levels(n, row_ptr, col, upper, p.level.data());
+  p.ilev.resize(p.nlev + 1);
+  if (n) level_sets(n, p.level.data(), p.nlev, p.ilev.data(), p.jlev.data());
+  else p.ilev[0] = 0;
+  dependency_counts(n, row_ptr, col, p.depcnt.data());
+
+  // positions: inside each level, group rows by the bit length of their
+  // dependency count (stable, so ascending row inside a group)
+  p.pos_ilev = p.ilev;
+  p.pos_row.resize(n);
+  int max_len = 0;
+  for (int i = 0; i < n; ++i) max_len = std::max(max_len, p.depcnt[i]);
+  p.max_row_len = max_len;
+  const int nclass = bit_length(static_cast<unsigned>(max_len)) + 1;
+  std::vector<int> cls_count(nclass);
+  for (int m = 0; m < p.nlev; ++m) {
+    const int a = p.ilev[m], b = p.ilev[m + 1];
+    std::fill(cls_count.begin(), cls_count.end(), 0);
+    for (int t = a; t < b; ++t) cls_count[bit_length(p.depcnt[p.jlev[t]])]++;
+    int acc = a;
+    for (int c = 0; c < nclass; ++c) {
+      const int cnt = cls_count[c];
+      cls_count[c] = acc;
+      acc += cnt;
+    }
+    for (int t = a; t < b; ++t) {
+      const int i = p.jlev[t];
+      p.pos_row[cls_count[bit_length(p.depcnt[i])]++] = i;
+    }
+  }
+
+  // off-diagonal CSR in position order, value sources, diagonal sources
+  p.off_ptr.resize(n + 1);
+  p.off_ptr[0] = 0;
+  for (int k = 0; k < n; ++k) p.off_ptr[k + 1] = p.off_ptr[k] + p.depcnt[p.pos_row[k]];
+  p.noff = p.off_ptr[n];
+  p.off_col.resize(p.noff);
+  p.off_src.resize(p.noff);
+  p.diag_src.assign(n, -1);
+  for (int k = 0; k < n; ++k) {
+    const int i = p.pos_row[k];
+    int o = p.off_ptr[k];
+    for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+      const int s = src ? src[e] : e;
+      if (col[e] == i) {
+        if (!unit_diag) p.diag_src[k] = s;
+        continue;
+      }
+      p.off_col[o] = col[e];
+      p.off_src[o] = s;
+      ++o;
+    }
+  }
+}
+
+void build_chunks(const HostPlan& p, int group, int entries_per_lane, int rows_fixed,
+                  ChunkTable& t) {
+  t = ChunkTable();
+  t.level_chunk.resize(p.nlev + 1);
+  if (entries_per_lane < 1) entries_per_lane = 1;
+  // log2 of the lanes a row of `len` off-diagonals gets under the length rule
+  auto lanes_for = [&](int len) -> int {
+    int lg = 0;
+    while (lg < 6 && (len + (1 << lg) - 1) / (1 << lg) > entries_per_lane) ++lg;
+    return lg;
+  };
+  int fixed_lg = 0;
+  if (group > 0) {
+    while ((1 << fixed_lg) < group) ++fixed_lg;
+  }
+  if (rows_fixed > 0) {
+    fixed_lg = 0;
+    while ((64 >> fixed_lg) > rows_fixed) ++fixed_lg;
+  }
+  for (int m = 0; m < p.nlev; ++m) {
+    t.level_chunk[m] = static_cast<int>(t.start.size());
+    int k = p.pos_ilev[m];
+    const int end = p.pos_ilev[m + 1];
+    while (k < end) {
+      int lg;
+      if (rows_fixed > 0 || group > 0) lg = fixed_lg;
+      else lg = lanes_for(p.off_ptr[k + 1] - p.off_ptr[k]);
+      const int cap = 64 >> lg;
+      int cnt = 1;
+      while (cnt < cap && k + cnt < end) {
+        if (rows_fixed <= 0 && group <= 0) {
+          const int len = p.off_ptr[k + cnt + 1] - p.off_ptr[k + cnt];
+          if (lanes_for(len) > lg) break;
+        }
+        ++cnt;
+      }
+      t.start.push_back(k);
+      t.meta.push_back(cnt | (lg << 8));
+      t.max_lg = std::max(t.max_lg, lg);
+      k += cnt;
+    }
+  }
+  t.level_chunk[p.nlev] = static_cast<int>(t.start.size());
+}
+
+uint64_t pattern_hash(int n, const int* row_ptr, const int* col, bool upper, bool unit_diag) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](uint64_t v) {
+    for (int b = 0; b < 8; ++b) {
+      h ^= (v >> (8 * b)) & 0xff;
+      h *= 1099511628211ull;
+    }
+  };
+  mix(static_cast<uint64_t>(n));
+  mix(upper);
+  mix(unit_diag);
+  if (n == 0) return h;
+  for (int i = 0; i <= n; ++i) mix(static_cast<uint32_t>(row_ptr[i]));
+  for (int k = 0; k < row_ptr[n]; ++k) mix(static_cast<uint32_t>(col[k]));
+  return h;
+}
+
+}  // namespace sptrsv

@@ -1,0 +1,96 @@
+// Host-side setup phase of the solver (Sec. 4.4 of Li, arXiv:1710.04985):
+// pattern validation, levels (Sec. 4.1), level sets, dependency counts and
+// the level-ordered layout the kernels stream.  Pure C++, no HIP calls.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+namespace sptrsv {
+
+// Status values match sptrsv_status in include/sptrsv.h.
+enum : int {
+  kOk = 0,
+  kErrInvalidArg = -1,
+  kErrBadRowPtr = -2,
+  kErrBadColIdx = -3,
+  kErrNotTriangular = -4,
+  kErrDuplicate = -5,
+  kErrMissingDiag = -6,
+  kErrZeroPivot = -7,
+  kErrHip = -8,
+  kErrOom = -9,
+  kErrTimeout = -10,
+  kErrNotSupported = -11,
+};
+
+// Checks the problem statement of Sec. 3, eq. (1) on the pattern: row_ptr
+// monotone from 0 to nnz, columns in range and on the right side of the
+// diagonal, no repeated column in a row, a diagonal in every row unless
+// unit_diag.  diag_pos[i] receives the entry index of row i's diagonal or -1.
+int validate_pattern(int n, int64_t nnz, const int* row_ptr, const int* col, bool upper,
+                     bool unit_diag, std::vector<int>* diag_pos);
+
+// Levels of Sec. 4.1, 0-based: level[i] = 0 if row i has no stored
+// off-diagonal, else 1 + max level[j] over them.  Rows are visited in
+// dependency order (ascending for lower, descending for upper).  Returns nlev.
+int compute_levels(int n, const int* row_ptr, const int* col, bool upper, int* level);
+
+// ilev[0..nlev] level pointers and jlev rows ordered by (level, row).
+void level_sets(int n, const int* level, int nlev, int* ilev, int* jlev);
+
+// Stored off-diagonal entries per row (the dependency counts of Sec. 4.2).
+void dependency_counts(int n, const int* row_ptr, const int* col, int* depcnt);
+
+// Pattern of T^T in CSR (the CSC of T, Sec. 3) with, for every entry of T^T,
+// the index of the entry of T it came from.
+void transpose_pattern(int n, const int* row_ptr, const int* col, std::vector<int>& rowT,
+                       std::vector<int>& colT, std::vector<int>& srcT);
+
+// Level-ordered layout of one triangle, as the solve kernels read it.
+//   pos_row[k]  row (x index) solved at position k; positions run level by
+//               level (pos_ilev), inside a level grouped by the bit length of
+//               the row's off-diagonal count, ascending row inside a group.
+//   off_ptr     CSR pointers of the off-diagonal entries in position order;
+//   off_col     their column (x index); off_src their index in the caller's
+//               value array (for the value gather);
+//   diag_src[k] index of the diagonal value of position k, -1 for unit.
+struct HostPlan {
+  int n = 0;
+  int nlev = 0;
+  int64_t nnz = 0;                // stored entries incl. diagonal
+  int64_t noff = 0;               // stored off-diagonal entries
+  bool upper = false;
+  bool unit_diag = false;
+  std::vector<int> level, ilev, jlev, depcnt;   // canonical analysis (exported)
+  std::vector<int> pos_row, pos_ilev;
+  std::vector<int> off_ptr, off_col, off_src, diag_src;
+  int max_row_len = 0;            // max off-diagonal count of a row
+};
+
+// Builds the plan of the triangle (row_ptr, col); src maps an entry to its
+// value index (nullptr = identity).  The pattern must have been validated.
+void build_plan(int n, const int* row_ptr, const int* col, const int* src, bool upper,
+                bool unit_diag, HostPlan& plan);
+
+// Work chunks: runs of consecutive positions inside ONE level, processed by
+// one 64-lane wavefront.  A chunk holds `count` rows of G = 2^lg lanes each
+// (count * G <= 64).  Encoded as {start, count | lg << 8}.
+struct ChunkTable {
+  std::vector<int> start;         // first position of each chunk
+  std::vector<int> meta;          // count | (lg << 8)
+  std::vector<int> level_chunk;   // chunks of level m: [level_chunk[m], level_chunk[m+1])
+  int max_lg = 0;
+};
+
+// group > 0: every row gets G = group lanes (a power of two <= 64).
+// group == 0: G = smallest power of two with ceil(len / G) <= entries_per_lane.
+// rows_fixed > 0 overrides both: count <= rows_fixed and G = 64 / rows_fixed
+// (multi-RHS kernels, where lanes split right-hand sides, not entries).
+void build_chunks(const HostPlan& plan, int group, int entries_per_lane, int rows_fixed,
+                  ChunkTable& out);
+
+// 64-bit FNV-1a hash of a pattern (autotuner cache key).
+uint64_t pattern_hash(int n, const int* row_ptr, const int* col, bool upper, bool unit_diag);
+
+}  // namespace sptrsv

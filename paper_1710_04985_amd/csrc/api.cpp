@@ -1,0 +1,909 @@
+// C ABI of libsptrsv (include/sptrsv.h): handle lifetime, analysis upload,
+// schedule selection and launch sequencing.  Section references are to Li,
+// arXiv:1710.04985.
+#include "sptrsv.h"
+
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <utility>
+#include <vector>
+
+#include "analysis.hpp"
+#include "kernels.hpp"
+
+using namespace sptrsv;
+
+namespace {
+
+struct ChunkEntry {
+  DevChunks d;
+  std::vector<int> level_chunk;   // host copy: chunk range of every level
+  int max_lg = 0;
+};
+
+struct PlanState {
+  bool built = false;
+  HostPlan h;
+  DevPlan d;
+  void* vals_buf = nullptr;       // [noff + n] values: off-diagonals then diagonal
+  std::map<std::tuple<int, int, int>, ChunkEntry> chunks;   // (group, epl, rows_fixed)
+};
+
+struct Config {
+  int algo;
+  int group;
+  int epl;
+  int sync;
+};
+
+std::mutex g_tune_mu;
+std::map<uint64_t, Config> g_tune_cache;
+
+}  // namespace
+
+struct sptrsv_handle_s {
+  int n = 0;
+  int64_t nnz = 0;
+  sptrsv_dtype dtype = SPTRSV_F64;
+  bool upper = false;
+  bool unit = false;
+  size_t vb = 8;
+  int device = 0;
+  int num_cu = 256;
+  std::vector<int> rp_h, col_h;   // caller's pattern (host copy)
+  PlanState fwd, trn;
+  DevScratch scratch;
+  void* tmp = nullptr;            // copy of b for in-place value-sync solves
+  size_t tmp_bytes = 0;
+  // batched handles keep the concatenated pattern and values on the device
+  bool batched = false;
+  std::vector<int> sys_n, sys_nnz;
+  int* rp_cat = nullptr;
+  int* col_cat = nullptr;
+  void* vals_cat = nullptr;
+  // options
+  int algo = SPTRSV_ALGO_AUTO;
+  int group = 0;
+  int epl = 4;
+  int sync = SPTRSV_SYNC_VALUE;
+  int spin_limit = 1 << 22;
+  int grid = 0;
+  int timing = 0;
+  int wg = 256;
+  // autotuner result
+  bool tuned = false;
+  Config tuned_cfg{SPTRSV_ALGO_SELF, 0, 4, SPTRSV_SYNC_VALUE};
+  uint64_t hash = 0;
+  // timing
+  std::map<std::pair<int, int>, int> occupancy;   // (kernel kind, wg) -> blocks per CU
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
+  size_t ev_used = 0;
+  double acc_ms = 0.0;
+  int64_t acc_count = 0;
+  hipStream_t last_stream = nullptr;
+};
+
+struct sptrsv_graph_s {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+#define HIPCHK(expr)                          \
+  do {                                        \
+    if ((expr) != hipSuccess) return kErrHip; \
+  } while (0)
+
+namespace {
+
+template <typename T> T* dalloc(size_t count, int* err) {
+  if (count == 0) count = 1;
+  void* p = nullptr;
+  if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) {
+    *err = kErrOom;
+    return nullptr;
+  }
+  return static_cast<T*>(p);
+}
+
+void dfree(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+void free_chunks(PlanState& ps) {
+  for (auto& kv : ps.chunks) {
+    dfree(kv.second.d.start);
+    dfree(kv.second.d.meta);
+  }
+  ps.chunks.clear();
+}
+
+void free_plan(PlanState& ps) {
+  free_chunks(ps);
+  dfree(ps.d.off_ptr);
+  dfree(ps.d.off_col);
+  dfree(ps.d.off_src);
+  dfree(ps.d.diag_src);
+  dfree(ps.d.pos_row);
+  dfree(ps.vals_buf);
+  ps.d = DevPlan();
+  ps.vals_buf = nullptr;
+  ps.built = false;
+}
+
+int upload_ints(int** dst, const std::vector<int>& v, hipStream_t s) {
+  int err = kOk;
+  *dst = dalloc<int>(v.size(), &err);
+  if (!*dst) return err;
+  if (!v.empty())
+    HIPCHK(hipMemcpyAsync(*dst, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  return kOk;
+}
+
+// Uploads the host plan; values are gathered separately.
+int upload_plan(PlanState& ps, size_t vb, hipStream_t s) {
+  const HostPlan& h = ps.h;
+  DevPlan& d = ps.d;
+  d.n = h.n;
+  d.nlev = h.nlev;
+  d.noff = h.noff;
+  int st;
+  if ((st = upload_ints(&d.off_ptr, h.off_ptr, s))) return st;
+  if ((st = upload_ints(&d.off_col, h.off_col, s))) return st;
+  if ((st = upload_ints(&d.off_src, h.off_src, s))) return st;
+  if ((st = upload_ints(&d.diag_src, h.diag_src, s))) return st;
+  if ((st = upload_ints(&d.pos_row, h.pos_row, s))) return st;
+  int err = kOk;
+  ps.vals_buf = dalloc<char>((static_cast<size_t>(h.noff) + h.n) * vb, &err);
+  if (!ps.vals_buf) return err;
+  d.off_val = ps.vals_buf;
+  d.diag = static_cast<char*>(ps.vals_buf) + static_cast<size_t>(h.noff) * vb;
+  ps.built = true;
+  return kOk;
+}
+
+int gather(sptrsv_handle_t h, PlanState& ps, const void* vals, hipStream_t s) {
+  hipError_t e;
+  if (h->dtype == SPTRSV_F64)
+    e = launch_gather<double>(ps.d, static_cast<const double*>(vals), h->scratch.status, s);
+  else
+    e = launch_gather<float>(ps.d, static_cast<const float*>(vals), h->scratch.status, s);
+  return e == hipSuccess ? kOk : kErrHip;
+}
+
+int read_status(sptrsv_handle_t h, hipStream_t s, bool clear) {
+  int st = 0;
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipMemcpy(&st, h->scratch.status, sizeof(int), hipMemcpyDeviceToHost));
+  if (clear && st) {
+    const int zero = 0;
+    HIPCHK(hipMemcpy(h->scratch.status, &zero, sizeof(int), hipMemcpyHostToDevice));
+  }
+  if (st & kStatusTimeout) return kErrTimeout;
+  if (st & kStatusZeroPivot) return kErrZeroPivot;
+  return kOk;
+}
+
+// Builds the analysis of T^T: rows of T^T are the columns of T; each value is
+// taken from the forward plan's value buffer (so the caller's vals need not
+// outlive the analysis).
+int build_transpose(sptrsv_handle_t h, hipStream_t s) {
+  if (h->trn.built) return kOk;
+  const int n = h->n;
+  const HostPlan& f = h->fwd.h;
+  // location of every caller entry in the forward value buffer
+  std::vector<int> loc(h->nnz, -1);
+  for (int k = 0; k < n; ++k) {
+    for (int o = f.off_ptr[k]; o < f.off_ptr[k + 1]; ++o) loc[f.off_src[o]] = o;
+    if (f.diag_src[k] >= 0) loc[f.diag_src[k]] = static_cast<int>(f.noff) + k;
+  }
+  std::vector<int> rT, cT, sT;
+  transpose_pattern(n, h->rp_h.data(), h->col_h.data(), rT, cT, sT);
+  for (auto& v : sT) v = loc[v];
+  build_plan(n, rT.data(), cT.data(), sT.data(), !h->upper, h->unit, h->trn.h);
+  int st = upload_plan(h->trn, h->vb, s);
+  if (st) return st;
+  st = gather(h, h->trn, h->fwd.vals_buf, s);
+  if (st) return st;
+  HIPCHK(hipStreamSynchronize(s));
+  return kOk;
+}
+
+ChunkEntry* get_chunks(sptrsv_handle_t h, PlanState& ps, int group, int epl, int rows_fixed,
+                       int* err) {
+  auto key = std::make_tuple(group, epl, rows_fixed);
+  auto it = ps.chunks.find(key);
+  if (it != ps.chunks.end()) return &it->second;
+  ChunkTable t;
+  build_chunks(ps.h, group, epl, rows_fixed, t);
+  ChunkEntry e;
+  e.level_chunk = t.level_chunk;
+  e.max_lg = t.max_lg;
+  e.d.count = static_cast<int>(t.start.size());
+  int st;
+  // synchronous copies: the table may be built the first time a solve is
+  // issued, and the host vectors die with this call
+  e.d.start = dalloc<int>(t.start.size(), &st);
+  e.d.meta = dalloc<int>(t.meta.size(), &st);
+  if (!e.d.start || !e.d.meta) {
+    dfree(e.d.start);
+    dfree(e.d.meta);
+    *err = kErrOom;
+    return nullptr;
+  }
+  if (!t.start.empty() &&
+      (hipMemcpy(e.d.start, t.start.data(), t.start.size() * sizeof(int), hipMemcpyHostToDevice) !=
+           hipSuccess ||
+       hipMemcpy(e.d.meta, t.meta.data(), t.meta.size() * sizeof(int), hipMemcpyHostToDevice) !=
+           hipSuccess)) {
+    dfree(e.d.start);
+    dfree(e.d.meta);
+    *err = kErrHip;
+    return nullptr;
+  }
+  return &(ps.chunks[key] = e);
+}
+
+// Schedule of the next solve: the autotuner's choice if one is current,
+// else the options (ALGO_AUTO without tuning = self-scheduled, the paper's
+// proposal).
+Config resolve(sptrsv_handle_t h) {
+  if (h->tuned) return h->tuned_cfg;
+  Config c{h->algo, h->group, h->epl, h->sync};
+  if (c.algo == SPTRSV_ALGO_AUTO) c.algo = SPTRSV_ALGO_SELF;
+  return c;
+}
+
+uint64_t tune_key(sptrsv_handle_t h) {
+  return h->hash ^ (h->dtype == SPTRSV_F32 ? 0x9e3779b97f4a7c15ull : 0) ^
+         (static_cast<uint64_t>(h->algo) << 56);
+}
+
+int ensure_tmp(sptrsv_handle_t h, size_t bytes) {
+  if (h->tmp_bytes >= bytes) return kOk;
+  dfree(h->tmp);
+  h->tmp = nullptr;
+  h->tmp_bytes = 0;
+  if (hipMalloc(&h->tmp, bytes) != hipSuccess) return kErrOom;
+  h->tmp_bytes = bytes;
+  return kOk;
+}
+
+// Resident workgroups per CU of persistent kernel `kind` (0 value sync, 1 flag
+// sync, 2 multi-RHS); queried once per (kind, wg) and cached, so that solves
+// under graph capture make no occupancy query.
+int blocks_per_cu(sptrsv_handle_t h, int kind) {
+  const auto key = std::make_pair(kind, h->wg);
+  auto it = h->occupancy.find(key);
+  if (it != h->occupancy.end()) return it->second;
+  int per_cu;
+  const bool dbl = h->dtype == SPTRSV_F64;
+  if (kind == 0) per_cu = dbl ? self_value_blocks_per_cu<double>(h->wg) : self_value_blocks_per_cu<float>(h->wg);
+  else if (kind == 1) per_cu = dbl ? self_flag_blocks_per_cu<double>(h->wg) : self_flag_blocks_per_cu<float>(h->wg);
+  else per_cu = dbl ? self_multi_blocks_per_cu<double>(h->wg) : self_multi_blocks_per_cu<float>(h->wg);
+  h->occupancy[key] = per_cu;
+  return per_cu;
+}
+
+int persistent_grid(sptrsv_handle_t h, int kind, int nchunks) {
+  if (h->grid > 0) return h->grid;
+  const int per_cu = blocks_per_cu(h, kind);
+  const int waves_per_block = h->wg / 64;
+  const int need = (nchunks + waves_per_block - 1) / waves_per_block;
+  return std::max(1, std::min(per_cu * h->num_cu, need));
+}
+
+void timing_begin(sptrsv_handle_t h, hipStream_t s, hipEvent_t* stop) {
+  *stop = nullptr;
+  if (!h->timing) return;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+  if (h->ev_used == h->ev_pool.size()) {
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return;
+    if (hipEventCreate(&b) != hipSuccess) {
+      (void)hipEventDestroy(a);
+      return;
+    }
+    h->ev_pool.emplace_back(a, b);
+  }
+  auto& pr = h->ev_pool[h->ev_used++];
+  (void)hipEventRecord(pr.first, s);
+  *stop = pr.second;
+}
+
+void timing_end(hipStream_t s, hipEvent_t stop) {
+  if (stop) (void)hipEventRecord(stop, s);
+}
+
+template <typename T>
+int solve_impl(sptrsv_handle_t h, PlanState& ps, const Config& c, const void* b, void* x,
+               int nrhs, int ld, hipStream_t s) {
+  const int n = h->n;
+  h->last_stream = s;
+  if (n == 0 || nrhs == 0) return kOk;
+  const bool multi = nrhs > 1;
+  int kl = 1;
+  while (kl < nrhs && kl < 64) kl <<= 1;
+  int err = kOk;
+  ChunkEntry* ch = multi ? get_chunks(h, ps, 0, 0, 64 / kl, &err)
+                         : get_chunks(h, ps, c.group, c.epl, 0, &err);
+  if (!ch) return err;
+  SolveArgs a;
+  a.plan = &ps.d;
+  a.chunks = &ch->d;
+  a.scratch = h->scratch;
+  a.b = b;
+  a.x = x;
+  a.nrhs = nrhs;
+  a.ld = ld;
+  a.spin_limit = h->spin_limit;
+  a.wg = h->wg;
+  hipEvent_t stop;
+  if (c.algo == SPTRSV_ALGO_LEVEL) {
+    timing_begin(h, s, &stop);
+    for (int m = 0; m < ps.h.nlev; ++m) {
+      const int cb = ch->level_chunk[m], ce = ch->level_chunk[m + 1];
+      const hipError_t e = multi ? launch_level_multi<T>(a, cb, ce, s) : launch_level<T>(a, cb, ce, s);
+      if (e != hipSuccess) return kErrHip;
+    }
+    timing_end(s, stop);
+    return kOk;
+  }
+  if (c.algo != SPTRSV_ALGO_SELF) return kErrNotSupported;
+  if (c.sync == SPTRSV_SYNC_FLAG && !multi) {
+    a.grid = persistent_grid(h, 1, ch->d.count);
+    timing_begin(h, s, &stop);
+    if (launch_self_flag<T>(a, s) != hipSuccess) return kErrHip;
+    timing_end(s, stop);
+    return kOk;
+  }
+  // value sync: x starts as the sentinel; in place, b is saved first
+  T* save = nullptr;
+  if (b == x) {
+    const size_t bytes = static_cast<size_t>(ld) * nrhs * sizeof(T);
+    if ((err = ensure_tmp(h, bytes))) return err;
+    save = static_cast<T*>(h->tmp);
+    a.b = save;
+  }
+  if (launch_fill_sentinel<T>(static_cast<T*>(x), save, n, nrhs, ld, s) != hipSuccess)
+    return kErrHip;
+  a.grid = persistent_grid(h, multi ? 2 : 0, ch->d.count);
+  timing_begin(h, s, &stop);
+  const hipError_t e = multi ? launch_self_multi_value<T>(a, s) : launch_self_value<T>(a, s);
+  if (e != hipSuccess) return kErrHip;
+  timing_end(s, stop);
+  return kOk;
+}
+
+int solve_dispatch(sptrsv_handle_t h, bool transpose, const void* b, void* x, int nrhs, int ld,
+                   hipStream_t s) {
+  if (!h) return kErrInvalidArg;
+  if (h->n > 0 && (!b || !x)) return kErrInvalidArg;
+  if (transpose) {
+    const int st = build_transpose(h, s);
+    if (st) return st;
+  }
+  PlanState& ps = transpose ? h->trn : h->fwd;
+  const Config c = resolve(h);
+  if (h->dtype == SPTRSV_F64) return solve_impl<double>(h, ps, c, b, x, nrhs, ld, s);
+  return solve_impl<float>(h, ps, c, b, x, nrhs, ld, s);
+}
+
+int init_handle_common(sptrsv_handle_t h, hipStream_t s) {
+  (void)hipGetDevice(&h->device);
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device) == hipSuccess &&
+      ncu > 0)
+    h->num_cu = ncu;
+  int err = kOk;
+  h->scratch.ticket = dalloc<int>(1, &err);
+  h->scratch.status = dalloc<int>(1, &err);
+  h->scratch.epoch = dalloc<unsigned>(1, &err);
+  h->scratch.flags = dalloc<unsigned>(h->n, &err);
+  if (err) return err;
+  HIPCHK(launch_init_scratch(h->scratch, h->n, s));
+  return kOk;
+}
+
+// Validation, analysis and upload of the forward plan from a host pattern.
+int analyze_from_host(sptrsv_handle_t h, const void* vals, hipStream_t s) {
+  int st = validate_pattern(h->n, h->nnz, h->rp_h.data(), h->col_h.data(), h->upper, h->unit,
+                            nullptr);
+  if (st) return st;
+  build_plan(h->n, h->rp_h.data(), h->col_h.data(), nullptr, h->upper, h->unit, h->fwd.h);
+  if ((st = init_handle_common(h, s))) return st;
+  if ((st = upload_plan(h->fwd, h->vb, s))) return st;
+  if ((st = gather(h, h->fwd, vals, s))) return st;
+  h->hash = pattern_hash(h->n, h->rp_h.data(), h->col_h.data(), h->upper, h->unit);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(tune_key(h));
+    if (it != g_tune_cache.end()) {
+      h->tuned = true;
+      h->tuned_cfg = it->second;
+    }
+  }
+  return read_status(h, s, true);
+}
+
+void destroy_handle(sptrsv_handle_t h) {
+  if (!h) return;
+  free_plan(h->fwd);
+  free_plan(h->trn);
+  dfree(h->scratch.ticket);
+  dfree(h->scratch.status);
+  dfree(h->scratch.epoch);
+  dfree(h->scratch.flags);
+  dfree(h->tmp);
+  dfree(h->rp_cat);
+  dfree(h->col_cat);
+  dfree(h->vals_cat);
+  for (auto& pr : h->ev_pool) {
+    (void)hipEventDestroy(pr.first);
+    (void)hipEventDestroy(pr.second);
+  }
+  delete h;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sptrsv_analyze(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                   const void* vals, sptrsv_dtype dtype, sptrsv_uplo uplo, int unit_diag,
+                   hipStream_t stream, sptrsv_handle_t* out) {
+  if (!out) return kErrInvalidArg;
+  *out = nullptr;
+  if (n < 0 || nnz < 0 || (dtype != SPTRSV_F64 && dtype != SPTRSV_F32) ||
+      (uplo != SPTRSV_LOWER && uplo != SPTRSV_UPPER))
+    return kErrInvalidArg;
+  if (!row_ptr || (nnz > 0 && (!col_idx || !vals))) return kErrInvalidArg;
+  sptrsv_handle_t h = new (std::nothrow) sptrsv_handle_s;
+  if (!h) return kErrOom;
+  h->n = n;
+  h->nnz = nnz;
+  h->dtype = dtype;
+  h->vb = dtype == SPTRSV_F64 ? 8 : 4;
+  h->upper = uplo == SPTRSV_UPPER;
+  h->unit = unit_diag != 0;
+  h->rp_h.resize(static_cast<size_t>(n) + 1);
+  h->col_h.resize(nnz);
+  if (hipMemcpyAsync(h->rp_h.data(), row_ptr, (static_cast<size_t>(n) + 1) * sizeof(int),
+                     hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      (nnz > 0 && hipMemcpyAsync(h->col_h.data(), col_idx, static_cast<size_t>(nnz) * sizeof(int),
+                                 hipMemcpyDeviceToHost, stream) != hipSuccess) ||
+      hipStreamSynchronize(stream) != hipSuccess) {
+    destroy_handle(h);
+    return kErrHip;
+  }
+  const int st = analyze_from_host(h, vals, stream);
+  if (st) {
+    destroy_handle(h);
+    return st;
+  }
+  *out = h;
+  return kOk;
+}
+
+int sptrsv_analyze_batched(int32_t count, const int32_t* n, const int32_t* nnz,
+                           const int32_t* const* row_ptr, const int32_t* const* col_idx,
+                           const void* const* vals, sptrsv_dtype dtype, sptrsv_uplo uplo,
+                           int unit_diag, hipStream_t stream, sptrsv_handle_t* out) {
+  if (!out) return kErrInvalidArg;
+  *out = nullptr;
+  if (count < 1 || !n || !nnz || !row_ptr || !col_idx || !vals ||
+      (dtype != SPTRSV_F64 && dtype != SPTRSV_F32) || (uplo != SPTRSV_LOWER && uplo != SPTRSV_UPPER))
+    return kErrInvalidArg;
+  int64_t ntot = 0, nnztot = 0;
+  for (int s = 0; s < count; ++s) {
+    if (n[s] < 0 || nnz[s] < 0 || !row_ptr[s] || (nnz[s] > 0 && (!col_idx[s] || !vals[s])))
+      return kErrInvalidArg;
+    ntot += n[s];
+    nnztot += nnz[s];
+  }
+  if (ntot > INT32_MAX || nnztot > INT32_MAX) return kErrInvalidArg;
+  sptrsv_handle_t h = new (std::nothrow) sptrsv_handle_s;
+  if (!h) return kErrOom;
+  h->n = static_cast<int>(ntot);
+  h->nnz = nnztot;
+  h->dtype = dtype;
+  h->vb = dtype == SPTRSV_F64 ? 8 : 4;
+  h->upper = uplo == SPTRSV_UPPER;
+  h->unit = unit_diag != 0;
+  h->batched = true;
+  h->sys_n.assign(n, n + count);
+  h->sys_nnz.assign(nnz, nnz + count);
+  h->rp_h.assign(static_cast<size_t>(ntot) + 1, 0);
+  h->col_h.resize(nnztot);
+  int err = kOk;
+  h->vals_cat = dalloc<char>(static_cast<size_t>(nnztot) * h->vb, &err);
+  if (err) {
+    destroy_handle(h);
+    return err;
+  }
+  int64_t roff = 0, eoff = 0;
+  std::vector<int> rp_tmp;
+  for (int s = 0; s < count; ++s) {
+    rp_tmp.resize(static_cast<size_t>(n[s]) + 1);
+    if (hipMemcpyAsync(rp_tmp.data(), row_ptr[s], rp_tmp.size() * sizeof(int),
+                       hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        (nnz[s] > 0 &&
+         (hipMemcpyAsync(h->col_h.data() + eoff, col_idx[s], static_cast<size_t>(nnz[s]) * sizeof(int),
+                         hipMemcpyDeviceToHost, stream) != hipSuccess ||
+          hipMemcpyAsync(static_cast<char*>(h->vals_cat) + eoff * h->vb, vals[s],
+                         static_cast<size_t>(nnz[s]) * h->vb, hipMemcpyDeviceToDevice,
+                         stream) != hipSuccess)) ||
+        hipStreamSynchronize(stream) != hipSuccess) {
+      destroy_handle(h);
+      return kErrHip;
+    }
+    // each system is validated on its own (its errors are its own)
+    const int st = validate_pattern(n[s], nnz[s], rp_tmp.data(), h->col_h.data() + eoff,
+                                    h->upper, h->unit, nullptr);
+    if (st) {
+      destroy_handle(h);
+      return st;
+    }
+    for (int i = 0; i < n[s]; ++i) h->rp_h[roff + i + 1] = static_cast<int>(rp_tmp[i + 1] + eoff);
+    for (int64_t k = eoff; k < eoff + nnz[s]; ++k) h->col_h[k] += static_cast<int>(roff);
+    roff += n[s];
+    eoff += nnz[s];
+  }
+  int st = analyze_from_host(h, h->vals_cat, stream);
+  if (!st) st = upload_ints(&h->rp_cat, h->rp_h, stream);
+  if (!st) st = upload_ints(&h->col_cat, h->col_h, stream);
+  if (!st && hipStreamSynchronize(stream) != hipSuccess) st = kErrHip;
+  if (st) {
+    destroy_handle(h);
+    return st;
+  }
+  *out = h;
+  return kOk;
+}
+
+int sptrsv_update_values(sptrsv_handle_t h, const void* vals, hipStream_t stream) {
+  if (!h || (h->nnz > 0 && !vals)) return kErrInvalidArg;
+  if (h->batched) return kErrInvalidArg;
+  int st = gather(h, h->fwd, vals, stream);
+  if (!st && h->trn.built) st = gather(h, h->trn, h->fwd.vals_buf, stream);
+  h->last_stream = stream;
+  return st;
+}
+
+int sptrsv_update_values_batched(sptrsv_handle_t h, const void* const* vals, hipStream_t stream) {
+  if (!h || !vals || !h->batched) return kErrInvalidArg;
+  int64_t eoff = 0;
+  for (size_t s = 0; s < h->sys_n.size(); ++s) {
+    if (h->sys_nnz[s] > 0) {
+      if (!vals[s]) return kErrInvalidArg;
+      HIPCHK(hipMemcpyAsync(static_cast<char*>(h->vals_cat) + eoff * h->vb, vals[s],
+                            static_cast<size_t>(h->sys_nnz[s]) * h->vb, hipMemcpyDeviceToDevice,
+                            stream));
+    }
+    eoff += h->sys_nnz[s];
+  }
+  int st = gather(h, h->fwd, h->vals_cat, stream);
+  if (!st && h->trn.built) st = gather(h, h->trn, h->fwd.vals_buf, stream);
+  h->last_stream = stream;
+  return st;
+}
+
+int sptrsv_solve(sptrsv_handle_t h, const void* b, void* x, hipStream_t stream) {
+  return solve_dispatch(h, false, b, x, 1, h ? h->n : 0, stream);
+}
+
+int sptrsv_solve_transpose(sptrsv_handle_t h, const void* b, void* x, hipStream_t stream) {
+  return solve_dispatch(h, true, b, x, 1, h ? h->n : 0, stream);
+}
+
+int sptrsv_prepare_transpose(sptrsv_handle_t h, hipStream_t stream) {
+  if (!h) return kErrInvalidArg;
+  return build_transpose(h, stream);
+}
+
+int sptrsv_solve_multi(sptrsv_handle_t h, int32_t nrhs, int32_t ld, const void* B, void* X,
+                       int transpose, hipStream_t stream) {
+  if (!h || nrhs < 1 || ld < h->n || ld < 1) return kErrInvalidArg;
+  return solve_dispatch(h, transpose != 0, B, X, nrhs, ld, stream);
+}
+
+int sptrsv_grad_vals(sptrsv_handle_t h, const int32_t* row_ptr, const int32_t* col_idx,
+                     const void* grad_b, const void* x, void* grad_vals, hipStream_t stream) {
+  if (!h) return kErrInvalidArg;
+  if (h->n == 0) return kOk;
+  if (h->batched) {
+    row_ptr = h->rp_cat;
+    col_idx = h->col_cat;
+  }
+  if (!row_ptr || (h->nnz > 0 && (!col_idx || !grad_b || !x || !grad_vals))) return kErrInvalidArg;
+  hipError_t e;
+  if (h->dtype == SPTRSV_F64)
+    e = launch_grad_vals<double>(h->n, row_ptr, col_idx, h->unit, static_cast<const double*>(grad_b),
+                                 static_cast<const double*>(x), static_cast<double*>(grad_vals),
+                                 stream);
+  else
+    e = launch_grad_vals<float>(h->n, row_ptr, col_idx, h->unit, static_cast<const float*>(grad_b),
+                                static_cast<const float*>(x), static_cast<float*>(grad_vals), stream);
+  h->last_stream = stream;
+  return e == hipSuccess ? kOk : kErrHip;
+}
+
+int sptrsv_set_option(sptrsv_handle_t h, sptrsv_option key, int64_t v) {
+  if (!h) return kErrInvalidArg;
+  if (key == SPTRSV_OPT_ALGO || key == SPTRSV_OPT_GROUP || key == SPTRSV_OPT_ENTRIES_PER_LANE ||
+      key == SPTRSV_OPT_SYNC)
+    h->tuned = false;   // an explicit schedule option overrides the tuner's choice
+  switch (key) {
+    case SPTRSV_OPT_ALGO:
+      if (v != SPTRSV_ALGO_AUTO && v != SPTRSV_ALGO_LEVEL && v != SPTRSV_ALGO_SELF)
+        return v == SPTRSV_ALGO_BLOCK ? kErrNotSupported : kErrInvalidArg;
+      h->algo = static_cast<int>(v);
+      return kOk;
+    case SPTRSV_OPT_GROUP:
+      if (v < 0 || v > 64 || (v & (v - 1))) return kErrInvalidArg;
+      h->group = static_cast<int>(v);
+      return kOk;
+    case SPTRSV_OPT_ENTRIES_PER_LANE:
+      if (v < 1 || v > 4096) return kErrInvalidArg;
+      h->epl = static_cast<int>(v);
+      return kOk;
+    case SPTRSV_OPT_SYNC:
+      if (v != SPTRSV_SYNC_VALUE && v != SPTRSV_SYNC_FLAG) return kErrInvalidArg;
+      h->sync = static_cast<int>(v);
+      return kOk;
+    case SPTRSV_OPT_SPIN_LIMIT:
+      if (v < 1 || v > INT32_MAX) return kErrInvalidArg;
+      h->spin_limit = static_cast<int>(v);
+      return kOk;
+    case SPTRSV_OPT_GRID:
+      if (v < 0 || v > (1 << 20)) return kErrInvalidArg;
+      h->grid = static_cast<int>(v);
+      return kOk;
+    case SPTRSV_OPT_TIMING:
+      h->timing = v != 0;
+      return kOk;
+    case SPTRSV_OPT_WG:
+      if (v < 64 || v > 1024 || (v % 64)) return kErrInvalidArg;
+      h->wg = static_cast<int>(v);
+      return kOk;
+  }
+  return kErrInvalidArg;
+}
+
+int sptrsv_get_option(sptrsv_handle_t h, sptrsv_option key, int64_t* v) {
+  if (!h || !v) return kErrInvalidArg;
+  switch (key) {
+    case SPTRSV_OPT_ALGO: *v = h->algo; return kOk;
+    case SPTRSV_OPT_GROUP: *v = h->group; return kOk;
+    case SPTRSV_OPT_ENTRIES_PER_LANE: *v = h->epl; return kOk;
+    case SPTRSV_OPT_SYNC: *v = h->sync; return kOk;
+    case SPTRSV_OPT_SPIN_LIMIT: *v = h->spin_limit; return kOk;
+    case SPTRSV_OPT_GRID: *v = h->grid; return kOk;
+    case SPTRSV_OPT_TIMING: *v = h->timing; return kOk;
+    case SPTRSV_OPT_WG: *v = h->wg; return kOk;
+  }
+  return kErrInvalidArg;
+}
+
+int sptrsv_tune(sptrsv_handle_t h, const void* b, void* x, hipStream_t stream) {
+  if (!h) return kErrInvalidArg;
+  if (h->n == 0) return kOk;
+  if (!b || !x || b == x) return kErrInvalidArg;
+  // candidate schedules: lane rules (entries per lane) of the self-scheduled
+  // solve under both syncs and of the level-scheduled solve, restricted to
+  // the algorithm the options fix (all of them under ALGO_AUTO)
+  std::vector<Config> cand;
+  for (int epl : {1, 2, 4, 8}) {
+    if (h->algo != SPTRSV_ALGO_LEVEL) {
+      cand.push_back({SPTRSV_ALGO_SELF, 0, epl, SPTRSV_SYNC_VALUE});
+      cand.push_back({SPTRSV_ALGO_SELF, 0, epl, SPTRSV_SYNC_FLAG});
+    }
+    if (h->algo != SPTRSV_ALGO_SELF) cand.push_back({SPTRSV_ALGO_LEVEL, 0, epl, SPTRSV_SYNC_VALUE});
+  }
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  const int saved_timing = h->timing;
+  h->timing = 0;
+  float best = 1e30f;
+  Config best_c = cand[0];
+  int st = kOk;
+  for (const Config& c : cand) {
+    auto run = [&]() {
+      return h->dtype == SPTRSV_F64 ? solve_impl<double>(h, h->fwd, c, b, x, 1, h->n, stream)
+                                    : solve_impl<float>(h, h->fwd, c, b, x, 1, h->n, stream);
+    };
+    if ((st = run())) break;   // warm-up (also builds the chunk table)
+    if (hipEventRecord(e0, stream) != hipSuccess) { st = kErrHip; break; }
+    const int reps = 3;
+    for (int r = 0; r < reps && !st; ++r) st = run();
+    if (st) break;
+    if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+      st = kErrHip;
+      break;
+    }
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (ms < best) {
+      best = ms;
+      best_c = c;
+    }
+  }
+  h->timing = saved_timing;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st) return st;
+  st = read_status(h, stream, true);
+  if (st) return st;
+  h->tuned = true;
+  h->tuned_cfg = best_c;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_cache[tune_key(h)] = best_c;
+  return kOk;
+}
+
+int sptrsv_get_info(sptrsv_handle_t h, int32_t* n, int64_t* nnz, int32_t* nlev, int32_t* algo,
+                    int32_t* group) {
+  if (!h) return kErrInvalidArg;
+  const Config c = resolve(h);
+  if (n) *n = h->n;
+  if (nnz) *nnz = h->nnz;
+  if (nlev) *nlev = h->fwd.h.nlev;
+  if (algo) *algo = c.algo;
+  if (group) *group = c.group;
+  return kOk;
+}
+
+int sptrsv_get_schedule(sptrsv_handle_t h, int32_t* algo, int32_t* group,
+                        int32_t* entries_per_lane, int32_t* sync) {
+  if (!h) return kErrInvalidArg;
+  const Config c = resolve(h);
+  if (algo) *algo = c.algo;
+  if (group) *group = c.group;
+  if (entries_per_lane) *entries_per_lane = c.epl;
+  if (sync) *sync = c.sync;
+  return kOk;
+}
+
+int sptrsv_export_analysis(sptrsv_handle_t h, int transpose, int32_t* level, int32_t* ilev,
+                           int32_t* jlev, int32_t* depcnt) {
+  if (!h) return kErrInvalidArg;
+  if (transpose) {
+    const int st = build_transpose(h, h->last_stream);
+    if (st) return st;
+  }
+  const HostPlan& p = transpose ? h->trn.h : h->fwd.h;
+  if (level) std::copy(p.level.begin(), p.level.end(), level);
+  if (ilev) std::copy(p.ilev.begin(), p.ilev.end(), ilev);
+  if (jlev) std::copy(p.jlev.begin(), p.jlev.end(), jlev);
+  if (depcnt) std::copy(p.depcnt.begin(), p.depcnt.end(), depcnt);
+  return kOk;
+}
+
+int sptrsv_get_status(sptrsv_handle_t h) {
+  if (!h) return kErrInvalidArg;
+  return read_status(h, h->last_stream, true);
+}
+
+int sptrsv_kernel_time(sptrsv_handle_t h, double* ms, int64_t* count, int reset) {
+  if (!h) return kErrInvalidArg;
+  for (size_t i = 0; i < h->ev_used; ++i) {
+    HIPCHK(hipEventSynchronize(h->ev_pool[i].second));
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, h->ev_pool[i].first, h->ev_pool[i].second));
+    h->acc_ms += t;
+    h->acc_count++;
+  }
+  h->ev_used = 0;
+  if (ms) *ms = h->acc_ms;
+  if (count) *count = h->acc_count;
+  if (reset) {
+    h->acc_ms = 0.0;
+    h->acc_count = 0;
+  }
+  return kOk;
+}
+
+const char* sptrsv_status_string(int status) {
+  switch (status) {
+    case SPTRSV_OK: return "ok";
+    case SPTRSV_ERR_INVALID_ARG: return "invalid argument";
+    case SPTRSV_ERR_BAD_ROWPTR: return "row_ptr not monotone from 0 to nnz";
+    case SPTRSV_ERR_BAD_COLIDX: return "column index out of range";
+    case SPTRSV_ERR_NOT_TRIANGULAR: return "entry on the wrong side of the diagonal";
+    case SPTRSV_ERR_DUPLICATE: return "duplicate column in a row";
+    case SPTRSV_ERR_MISSING_DIAG: return "missing diagonal entry";
+    case SPTRSV_ERR_ZERO_PIVOT: return "zero diagonal entry";
+    case SPTRSV_ERR_HIP: return "HIP runtime error";
+    case SPTRSV_ERR_OOM: return "out of memory";
+    case SPTRSV_ERR_TIMEOUT: return "self-scheduled wait timed out";
+    case SPTRSV_ERR_NOT_SUPPORTED: return "not supported";
+  }
+  return "unknown status";
+}
+
+int sptrsv_destroy(sptrsv_handle_t h) {
+  if (!h) return kErrInvalidArg;
+  (void)hipDeviceSynchronize();
+  destroy_handle(h);
+  return kOk;
+}
+
+int sptrsv_graph_capture(sptrsv_handle_t h, const void* b, void* x, int transpose,
+                         hipStream_t stream, sptrsv_graph_t* out) {
+  if (!h || !out || !stream) return kErrInvalidArg;
+  *out = nullptr;
+  if (transpose) {
+    const int st = build_transpose(h, stream);
+    if (st) return st;
+  }
+  // make sure the chunk table exists before capture (its upload is synchronous)
+  {
+    const Config c = resolve(h);
+    int err = kOk;
+    if (h->n > 0 && !get_chunks(h, transpose ? h->trn : h->fwd, c.group, c.epl, 0, &err))
+      return err;
+    for (int kind = 0; kind < 3; ++kind) (void)blocks_per_cu(h, kind);
+  }
+  auto* g = new (std::nothrow) sptrsv_graph_s;
+  if (!g) return kErrOom;
+  if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    delete g;
+    return kErrHip;
+  }
+  const int st = solve_dispatch(h, transpose != 0, b, x, 1, h->n, stream);
+  const hipError_t e = hipStreamEndCapture(stream, &g->graph);
+  if (st || e != hipSuccess) {
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+    return st ? st : kErrHip;
+  }
+  if (hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(g->graph);
+    delete g;
+    return kErrHip;
+  }
+  *out = g;
+  return kOk;
+}
+
+int sptrsv_graph_launch(sptrsv_graph_t g, hipStream_t stream) {
+  if (!g) return kErrInvalidArg;
+  return hipGraphLaunch(g->exec, stream) == hipSuccess ? kOk : kErrHip;
+}
+
+int sptrsv_graph_destroy(sptrsv_graph_t g) {
+  if (!g) return kErrInvalidArg;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+  return kOk;
+}
+
+int sptrsv_analyze_host(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                        sptrsv_uplo uplo, int unit_diag, int32_t* level, int32_t* ilev,
+                        int32_t* jlev, int32_t* depcnt, int32_t* nlev) {
+  if (n < 0 || nnz < 0 || !row_ptr || (nnz > 0 && !col_idx) ||
+      (uplo != SPTRSV_LOWER && uplo != SPTRSV_UPPER))
+    return kErrInvalidArg;
+  const bool upper = uplo == SPTRSV_UPPER;
+  int st = validate_pattern(n, nnz, row_ptr, col_idx, upper, unit_diag != 0, nullptr);
+  if (st) return st;
+  HostPlan p;
+  build_plan(n, row_ptr, col_idx, nullptr, upper, unit_diag != 0, p);
+  if (level) std::copy(p.level.begin(), p.level.end(), level);
+  if (ilev) std::copy(p.ilev.begin(), p.ilev.end(), ilev);
+  if (jlev) std::copy(p.jlev.begin(), p.jlev.end(), jlev);
+  if (depcnt) std::copy(p.depcnt.begin(), p.depcnt.end(), depcnt);
+  if (nlev) *nlev = p.nlev;
+  return kOk;
+}
+
+}  // extern "C"

@@ -1,0 +1,78 @@
+// Launchers of the solve kernels (kernels.hip).  Host-callable; every
+// launcher enqueues on `stream` and returns the hipError_t of the launch.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <cstdint>
+
+namespace sptrsv {
+
+// Level-ordered device copy of one triangle (see HostPlan).
+struct DevPlan {
+  int n = 0;
+  int nlev = 0;
+  int64_t noff = 0;
+  int* off_ptr = nullptr;   // [n+1]
+  int* off_col = nullptr;   // [noff]
+  int* off_src = nullptr;   // [noff]
+  int* diag_src = nullptr;  // [n]
+  int* pos_row = nullptr;   // [n]
+  void* off_val = nullptr;  // [noff] T
+  void* diag = nullptr;     // [n] T
+};
+
+// One chunk table on the device.
+struct DevChunks {
+  int count = 0;
+  int* start = nullptr;
+  int* meta = nullptr;
+};
+
+// Per-handle scratch shared by the kernels.
+struct DevScratch {
+  int* ticket = nullptr;     // work counter of the persistent kernels
+  int* status = nullptr;     // bit 0: timeout, bit 1: zero pivot
+  unsigned* epoch = nullptr; // current flag epoch (flag sync)
+  unsigned* flags = nullptr; // [n] per-row ready flags (flag sync)
+};
+
+enum : int { kStatusTimeout = 1, kStatusZeroPivot = 2 };
+
+struct SolveArgs {
+  const DevPlan* plan;
+  const DevChunks* chunks;
+  DevScratch scratch;
+  const void* b;     // right-hand side (already copied aside when b == x)
+  void* x;
+  int nrhs = 1;
+  int ld = 0;
+  int spin_limit = 1 << 22;
+  int grid = 0;      // persistent workgroups
+  int wg = 256;      // threads per workgroup
+};
+
+template <typename T> hipError_t launch_gather(const DevPlan& p, const T* vals, int* status,
+                                               hipStream_t s);
+// x := sentinel (value sync); save != nullptr keeps a copy of x (in place)
+template <typename T> hipError_t launch_fill_sentinel(T* x, T* save, int n, int nrhs, int ld,
+                                                      hipStream_t s);
+// one launch per level for [chunk_begin, chunk_end) of one level
+template <typename T> hipError_t launch_level(const SolveArgs& a, int chunk_begin, int chunk_end,
+                                              hipStream_t s);
+template <typename T> hipError_t launch_self_value(const SolveArgs& a, hipStream_t s);
+template <typename T> hipError_t launch_self_flag(const SolveArgs& a, hipStream_t s);
+template <typename T> hipError_t launch_level_multi(const SolveArgs& a, int chunk_begin,
+                                                    int chunk_end, hipStream_t s);
+template <typename T> hipError_t launch_self_multi_value(const SolveArgs& a, hipStream_t s);
+template <typename T> hipError_t launch_grad_vals(int n, const int* row_ptr, const int* col,
+                                                  int unit_diag, const T* grad_b, const T* x,
+                                                  T* grad_vals, hipStream_t s);
+// flags reset (epoch wrap) and scratch initialisation
+hipError_t launch_init_scratch(DevScratch sc, int n, hipStream_t s);
+
+// occupancy of the persistent kernels: workgroups per CU at `wg` threads
+template <typename T> int self_value_blocks_per_cu(int wg);
+template <typename T> int self_flag_blocks_per_cu(int wg);
+template <typename T> int self_multi_blocks_per_cu(int wg);
+
+}  // namespace sptrsv

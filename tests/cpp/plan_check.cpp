@@ -1,0 +1,59 @@
+// CPU check of the library's level-ordered layout and work chunks (the
+// indexing every solve kernel relies on).  Built with g++ together with the
+// library's host analysis source; called from tests/test_plan_cpu.py.
+#include <cstdint>
+#include <vector>
+
+#include "analysis.hpp"
+
+using namespace sptrsv;
+
+extern "C" int check_plan(int n, const int* rp, const int* col, int upper, int unit, int group,
+                          int epl, int rows_fixed) {
+  HostPlan p;
+  build_plan(n, rp, col, nullptr, upper != 0, unit != 0, p);
+  // 1: pos_row is a permutation and every level holds the canonical rows
+  std::vector<int> seen(n, 0);
+  for (int k = 0; k < n; ++k) {
+    if (p.pos_row[k] < 0 || p.pos_row[k] >= n || seen[p.pos_row[k]]++) return 1;
+  }
+  if (p.pos_ilev != p.ilev) return 2;
+  for (int m = 0; m < p.nlev; ++m)
+    for (int k = p.pos_ilev[m]; k < p.pos_ilev[m + 1]; ++k)
+      if (p.level[p.pos_row[k]] != m) return 3;
+  // 2: off-diagonal copy maps back to the caller's entries of the same row
+  if (p.off_ptr[0] != 0 || p.off_ptr[n] != p.noff) return 4;
+  std::vector<int> used(rp[n], 0);
+  for (int k = 0; k < n; ++k) {
+    const int i = p.pos_row[k];
+    if (p.off_ptr[k + 1] - p.off_ptr[k] != p.depcnt[i]) return 5;
+    for (int o = p.off_ptr[k]; o < p.off_ptr[k + 1]; ++o) {
+      const int s = p.off_src[o];
+      if (s < rp[i] || s >= rp[i + 1] || col[s] != p.off_col[o] || col[s] == i || used[s]++) return 6;
+      if (upper ? p.off_col[o] <= i : p.off_col[o] >= i) return 7;
+    }
+    const int d = p.diag_src[k];
+    if (unit) {
+      if (d != -1) return 8;
+    } else if (d < rp[i] || d >= rp[i + 1] || col[d] != i || used[d]++) {
+      return 9;
+    }
+  }
+  // 3: chunks tile the positions in order, one level each, <= 64 lanes
+  ChunkTable t;
+  build_chunks(p, group, epl, rows_fixed, t);
+  if ((int)t.level_chunk.size() != p.nlev + 1) return 10;
+  int next = 0;
+  for (int m = 0; m < p.nlev; ++m) {
+    for (int c = t.level_chunk[m]; c < t.level_chunk[m + 1]; ++c) {
+      const int cnt = t.meta[c] & 0xff, lg = t.meta[c] >> 8;
+      if (t.start[c] != next || cnt < 1 || lg < 0 || lg > 6 || (cnt << lg) > 64) return 11;
+      if (t.start[c] < p.pos_ilev[m] || t.start[c] + cnt > p.pos_ilev[m + 1]) return 12;
+      if (group > 0 && (1 << lg) != group) return 13;
+      if (rows_fixed > 0 && (64 >> lg) != rows_fixed) return 14;
+      next += cnt;
+    }
+  }
+  if (next != n || t.level_chunk[p.nlev] != (int)t.start.size()) return 15;
+  return 0;
+}

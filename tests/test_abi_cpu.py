@@ -1,0 +1,99 @@
+"""C ABI on the CPU: the library loads, exports every declared entry point,
+and its host analysis matches the oracle bit for bit (no GPU calls)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    src = open(os.path.join(ROOT, "include", "sptrsv.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sptrsv_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1710_04985_amd._lib as L
+    names = _declared_symbols()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(L.lib, name), name
+        assert name in L.SIGNATURES, "binding lacks a signature for %s" % name
+    assert L.lib.sptrsv_status_string(-10) == b"self-scheduled wait timed out"
+
+
+def _cases():
+    out = []
+    for dims in [(5, 5), (64, 64), (7, 3), (1, 9), (6, 5, 4), (12, 12, 12), (3, 1, 8)]:
+        for upper in (False, True):
+            out.append(W.laplacian_triangle(dims, upper=upper))
+    for seed in range(6):
+        out.append(W.random_triangle(30 + seed, seed, density=0.3, upper=bool(seed % 2),
+                                     shuffle_rows=True))
+    out.append(W.powerlaw_lower(20000, 7, window=3000))
+    out.append(W.ilu0_lower((9, 8, 7)))
+    out.append(W.diagonal_matrix(np.arange(1.0, 40.0)))
+    out.append(W.bidiagonal_fast(500, 2.0, 1.0))
+    out.append(W.bidiagonal_fast(500, 2.0, 1.0, upper=True))
+    out.append(W.concat_block_diagonal([W.ilu0_lower((s, s)) for s in (4, 9, 6)]))
+    return out
+
+
+@pytest.mark.parametrize("T", _cases(), ids=lambda t: t.name)
+def test_host_analysis_matches_oracle(T):
+    from paper_1710_04985_amd import analyze_host
+    o = oracle.get()
+    st, level, ilev, jlev, dep = analyze_host(T.row_ptr, T.col_idx, T.upper, T.unit_diag)
+    assert st == 0
+    lv, nlev, il, jl, dc = o.analyze(T.row_ptr, T.col_idx, T.upper)
+    assert np.array_equal(level, lv)
+    assert np.array_equal(ilev, il) and len(ilev) == nlev + 1
+    assert np.array_equal(jlev, jl)
+    assert np.array_equal(dep, dc)
+
+
+def test_host_analysis_of_transpose_pattern():
+    """nlev(T^T) = nlev(T); levels of T^T from the reversed sweep."""
+    from paper_1710_04985_amd import analyze_host
+    o = oracle.get()
+    for T in [W.laplacian_triangle((6, 5, 4)), W.powerlaw_lower(5000, 2, window=400)]:
+        rT, cT, _ = o.transpose(T.row_ptr, T.col_idx)
+        st, lvT, ilT, jlT, _ = analyze_host(rT, cT, upper=not T.upper)
+        assert st == 0
+        want, nlevT = o.levels_row(rT, cT, not T.upper)
+        assert np.array_equal(lvT, want)
+        _, nlev = o.levels_row(T.row_ptr, T.col_idx, T.upper)
+        assert nlevT == nlev
+
+
+def test_host_validation_codes():
+    """Same classification as the oracle (codes mapped by name)."""
+    from paper_1710_04985_amd import analyze_host
+    import paper_1710_04985_amd._lib as L
+    name_of = dict(L.STATUS)
+    o = oracle.get()
+    onames = {oracle.OK: "OK", oracle.BAD_ROWPTR: "BAD_ROWPTR", oracle.BAD_COLIDX: "BAD_COLIDX",
+              oracle.NOT_TRIANGULAR: "NOT_TRIANGULAR", oracle.DUPLICATE: "DUPLICATE",
+              oracle.MISSING_DIAG: "MISSING_DIAG"}
+    T = W.laplacian_triangle((3, 3))
+    rp, ci = T.row_ptr, T.col_idx
+    cases = []
+    cases.append((rp, ci, False, False))
+    cases.append((rp, ci, True, False))
+    bad = rp.copy(); bad[3], bad[4] = bad[4], bad[3]; cases.append((bad, ci, False, False))
+    bad = ci.copy(); bad[0] = 9; cases.append((rp, bad, False, False))
+    bad = ci.copy(); bad[0] = -1; cases.append((rp, bad, False, False))
+    bad = ci.copy(); bad[2] = bad[1]; cases.append((rp, bad, False, False))
+    rp2 = rp.copy(); rp2[1:] -= 1; cases.append((rp2, ci[1:], False, False))
+    cases.append((rp2, ci[1:], False, True))
+    bad = rp.copy(); bad[-1] += 1; cases.append((bad, ci, False, False))
+    for r, c, up, unit in cases:
+        st = analyze_host(r, c, up, unit)[0]
+        ost = o.validate(r, c, None, up, unit)
+        assert name_of[st].replace("SPTRSV_ERR_", "").replace("SPTRSV_", "") == onames[ost], (st, ost)

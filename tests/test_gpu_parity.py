@@ -1,0 +1,329 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Bars: analysis (levels, level sets, dependency counts) bit-exact; FP64
+solves within 1e-12 relative (inf-norm) of the FP64 oracle, FP32 within 1e-5
+of the FP64 oracle run on the FP32 data; exactly representable cases
+bit-exact; level- and self-scheduled solves bit-identical at equal lanes per
+row (a race would show up as a difference).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from gpuhelp import DEV, bits_equal, dev, dev_tri, host, relerr
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+
+@pytest.fixture(scope="module")
+def sp():
+    import paper_1710_04985_amd as sp
+    assert torch.cuda.is_available()
+    return sp
+
+
+def _small_cases():
+    cases = [("c1_lap2d_64", W.c1_lap2d_64()[0]),
+             ("lap3d_20_L", W.laplacian_triangle((20, 20, 20))),
+             ("lap3d_20_U", W.laplacian_triangle((20, 20, 20), upper=True)),
+             ("lap3d_17x9x5_U", W.laplacian_triangle((17, 9, 5), upper=True)),
+             ("powerlaw_50k", W.powerlaw_lower(50000, 21, window=5000)),
+             ("ilu0_12", W.ilu0_lower((12, 12, 12))),
+             ("rand_upper", W.random_triangle(300, 5, density=0.05, upper=True, shuffle_rows=True)),
+             ("rand_lower", W.random_triangle(257, 6, density=0.08, shuffle_rows=True))]
+    return cases
+
+
+CASES = _small_cases()
+SCHEDULES = [("level", dict(algo=1)), ("self_value", dict(algo=2, sync=0)),
+             ("self_flag", dict(algo=2, sync=1)), ("self_value_g1", dict(algo=2, group=1)),
+             ("self_value_g8", dict(algo=2, group=8)), ("level_g64", dict(algo=1, group=64)),
+             ("self_flag_g16", dict(algo=2, sync=1, group=16)),
+             ("self_value_epl1", dict(algo=2, entries_per_lane=1))]
+
+
+@pytest.mark.parametrize("name,T", CASES, ids=[c[0] for c in CASES])
+def test_analysis_export_bit_exact(sp, name, T):
+    o = oracle.get()
+    h = sp.Handle(*dev_tri(T), uplo="U" if T.upper else "L", unit_diag=T.unit_diag)
+    level, ilev, jlev, dep = h.export_analysis()
+    lv, nlev, il, jl, dc = o.analyze(T.row_ptr, T.col_idx, T.upper)
+    assert np.array_equal(level, lv) and np.array_equal(ilev, il)
+    assert np.array_equal(jlev, jl) and np.array_equal(dep, dc)
+    assert h.info()["nlev"] == nlev
+    # analysis of T^T
+    rT, cT, _ = o.transpose(T.row_ptr, T.col_idx)
+    lvT, nlevT, ilT, jlT, dcT = o.analyze(rT, cT, not T.upper)
+    level, ilev, jlev, dep = h.export_analysis(transpose=True)
+    assert np.array_equal(level, lvT) and np.array_equal(ilev, ilT)
+    assert np.array_equal(jlev, jlT) and np.array_equal(dep, dcT)
+    assert nlevT == nlev
+
+
+@pytest.mark.parametrize("sched,opts", SCHEDULES, ids=[s[0] for s in SCHEDULES])
+@pytest.mark.parametrize("name,T", CASES, ids=[c[0] for c in CASES])
+def test_solve_fp64(sp, name, T, sched, opts):
+    o = oracle.get()
+    h = sp.Handle(*dev_tri(T), uplo="U" if T.upper else "L").configure(**opts)
+    b = W.uniform_vector(T.n, 7)
+    xo = o.solve(T.row_ptr, T.col_idx, T.vals, b, T.upper)
+    x = h.solve(dev(b))
+    h.status()
+    assert relerr(host(x), xo) <= TOL64
+    # transposed solve
+    g = W.uniform_vector(T.n, 8)
+    yo = o.solve_transpose(T.row_ptr, T.col_idx, T.vals, g, T.upper)
+    y = h.solve_t(dev(g))
+    h.status()
+    assert relerr(host(y), yo) <= TOL64
+
+
+@pytest.mark.parametrize("name,T", CASES[:5], ids=[c[0] for c in CASES[:5]])
+def test_solve_fp32(sp, name, T):
+    o = oracle.get()
+    v32 = T.vals.astype(np.float32)
+    b32 = W.uniform_vector(T.n, 9).astype(np.float32)
+    xo = o.solve(T.row_ptr, T.col_idx, v32.astype(np.float64), b32.astype(np.float64), T.upper)
+    for opts in (dict(algo=1), dict(algo=2, sync=0), dict(algo=2, sync=1)):
+        h = sp.Handle(dev(T.row_ptr), dev(T.col_idx), dev(v32),
+                      uplo="U" if T.upper else "L").configure(**opts)
+        x = h.solve(dev(b32))
+        h.status()
+        assert x.dtype == torch.float32
+        assert relerr(host(x), xo) <= TOL32, opts
+
+
+@pytest.mark.parametrize("group", [1, 4, 16, 64])
+@pytest.mark.parametrize("name,T", [CASES[1], CASES[4], CASES[6]], ids=[CASES[1][0], CASES[4][0], CASES[6][0]])
+def test_level_equals_self_bitwise(sp, name, T, group):
+    """Same per-row arithmetic under every schedule: results must be
+    bit-identical, on every one of repeated solves."""
+    b = dev(W.uniform_vector(T.n, 11))
+    hl = sp.Handle(*dev_tri(T), uplo="U" if T.upper else "L").configure(algo=1, group=group)
+    ref = hl.solve(b)
+    for sync in (0, 1):
+        hs = sp.Handle(*dev_tri(T), uplo="U" if T.upper else "L").configure(algo=2, group=group, sync=sync)
+        for _ in range(20):
+            assert bits_equal(hs.solve(b), ref)
+        hs.status()
+
+
+@pytest.mark.parametrize("opts", [dict(algo=1), dict(algo=2, sync=0), dict(algo=2, sync=1)])
+def test_in_place(sp, opts):
+    o = oracle.get()
+    T = W.laplacian_triangle((15, 14, 13))
+    b = W.uniform_vector(T.n, 3)
+    h = sp.Handle(*dev_tri(T)).configure(**opts)
+    x = dev(b)
+    h.solve(x, out=x)
+    y = dev(b)
+    h.solve_t(y, out=y)
+    h.status()
+    assert relerr(host(x), o.solve(T.row_ptr, T.col_idx, T.vals, b)) <= TOL64
+    assert relerr(host(y), o.solve_transpose(T.row_ptr, T.col_idx, T.vals, b)) <= TOL64
+
+
+@pytest.mark.parametrize("opts", [dict(algo=1), dict(algo=2, sync=0), dict(algo=2, sync=1)])
+def test_exact_cases(sp, opts):
+    """Diagonal: x = b/d; chain I - S (nlev = n): prefix sums of
+    integers; bidiagonal (2, -1) with b = e_0: x_i = 2^-(i+1).  Bit-exact."""
+    d = W.uniform_vector(5000, 1, 0.5, 3.0)
+    D = W.diagonal_matrix(d)
+    b = W.uniform_vector(5000, 2)
+    h = sp.Handle(*dev_tri(D)).configure(**opts)
+    assert np.array_equal(host(h.solve(dev(b))), b / d)
+    n = 200000 if opts["algo"] == 2 else 20000      # level-scheduled: one launch per row
+    rng = np.random.Generator(np.random.PCG64(4))
+    bi = rng.integers(-1000, 1000, n).astype(np.float64)
+    for upper in (False, True):
+        P = W.bidiagonal_fast(n, 1.0, 1.0, upper=upper)
+        h = sp.Handle(*dev_tri(P), uplo="U" if upper else "L").configure(**opts)
+        want = np.cumsum(bi[::-1])[::-1] if upper else np.cumsum(bi)
+        assert np.array_equal(host(h.solve(dev(bi))), want)
+        h.status()
+    B = W.bidiagonal_fast(600, 2.0, 1.0)
+    e = np.zeros(600)
+    e[0] = 1.0
+    h = sp.Handle(*dev_tri(B)).configure(**opts)
+    x = host(h.solve(dev(e)))
+    assert np.array_equal(x, 2.0 ** -(np.arange(600) + 1.0))
+
+
+def test_unit_diag(sp):
+    o = oracle.get()
+    T = W.ilu0_lower((11, 10, 9))          # stored unit diagonal
+    b = W.uniform_vector(T.n, 5)
+    xo = o.solve(T.row_ptr, T.col_idx, T.vals, b, False, True)
+    for opts in (dict(algo=1), dict(algo=2, sync=0), dict(algo=2, sync=1)):
+        h = sp.Handle(*dev_tri(T), unit_diag=True).configure(**opts)
+        assert relerr(host(h.solve(dev(b))), xo) <= TOL64
+    # diagonal entries absent altogether
+    rows = np.repeat(np.arange(T.n), np.diff(T.row_ptr))
+    keep = T.col_idx != rows
+    rp = np.zeros(T.n + 1, np.int32)
+    rp[1:] = np.cumsum(np.bincount(rows[keep], minlength=T.n))
+    h = sp.Handle(dev(rp), dev(T.col_idx[keep]), dev(T.vals[keep]), unit_diag=True)
+    assert relerr(host(h.solve(dev(b))), xo) <= TOL64
+
+
+@pytest.mark.parametrize("nrhs", [1, 3, 16, 70])
+@pytest.mark.parametrize("opts", [dict(algo=1), dict(algo=2)])
+def test_multi_rhs(sp, nrhs, opts):
+    o = oracle.get()
+    T = W.laplacian_triangle((14, 13, 12), upper=True)
+    F = np.stack([W.uniform_vector(T.n, 100 + r) for r in range(nrhs)], 0)     # (nrhs, n)
+    h = sp.Handle(*dev_tri(T), uplo="U").configure(group=1, **opts)
+    X = host(h.solve_multi(dev(F)))
+    Xt = host(h.solve_multi(dev(F), transpose=True))
+    h.status()
+    Xo = o.solve_multi(T.row_ptr, T.col_idx, T.vals, F.T, True)
+    for r in range(nrhs):
+        assert relerr(X[r], Xo[:, r]) <= TOL64
+        assert relerr(Xt[r], o.solve_transpose(T.row_ptr, T.col_idx, T.vals, F[r], True)) <= TOL64
+    # every column equals the single right-hand-side solve, bit for bit
+    for r in (0, nrhs - 1):
+        assert bits_equal(X[r], host(h.solve(dev(F[r]))))
+    # in place
+    B = dev(F)
+    h.solve_multi(B, out=B)
+    assert bits_equal(host(B), X)
+
+
+def test_batched(sp):
+    o = oracle.get()
+    tris = [W.ilu0_lower((s, s)) for s in (7, 33, 20, 64, 5, 41)]
+    tris.append(W.laplacian_triangle((9, 8)))
+    bs = [W.uniform_vector(t.n, 40 + i) for i, t in enumerate(tris)]
+    devs = [dev_tri(t) for t in tris]
+    for opts in (dict(algo=1), dict(algo=2, sync=0), dict(algo=2, sync=1)):
+        bh = sp.BatchedHandle([d[0] for d in devs], [d[1] for d in devs], [d[2] for d in devs]).configure(**opts)
+        x = host(bh.solve(dev(np.concatenate(bs))))
+        bh.status()
+        off = 0
+        for t, b, d in zip(tris, bs, devs):
+            xs = x[off:off + t.n]
+            assert relerr(xs, o.solve(t.row_ptr, t.col_idx, t.vals, b)) <= TOL64
+            single = sp.Handle(*d).configure(**opts)
+            assert bits_equal(xs, host(single.solve(dev(b))))
+            off += t.n
+    # grad on the concatenated pattern and new values
+    new_vals = [d[2] * 0.5 for d in devs]
+    bh.update_values(new_vals)
+    x = host(bh.solve(dev(np.concatenate(bs))))
+    off = 0
+    for t, b in zip(tris, bs):
+        assert relerr(x[off:off + t.n], o.solve(t.row_ptr, t.col_idx, t.vals * 0.5, b)) <= TOL64
+        off += t.n
+
+
+def test_update_values_and_zero_pivot(sp):
+    o = oracle.get()
+    T = W.laplacian_triangle((10, 9, 8))
+    rp, ci, v = dev_tri(T)
+    h = sp.Handle(rp, ci, v)
+    h.prepare_transpose()
+    v2 = T.vals * np.linspace(0.5, 2.0, T.nnz)
+    h.update_values(dev(v2))
+    b = W.uniform_vector(T.n, 1)
+    assert relerr(host(h.solve(dev(b))), o.solve(T.row_ptr, T.col_idx, v2, b)) <= TOL64
+    assert relerr(host(h.solve_t(dev(b))), o.solve_transpose(T.row_ptr, T.col_idx, v2, b)) <= TOL64
+    vz = v2.copy()
+    vz[T.row_ptr[5 + 1] - 1] = 0.0          # diagonal of row 5 (stored last)
+    h.update_values(dev(vz))
+    with pytest.raises(sp.SpTRSVError) as e:
+        h.status()
+    assert e.value.status == -7
+    with pytest.raises(sp.SpTRSVError) as e:
+        sp.Handle(rp, ci, dev(vz))
+    assert e.value.status == -7
+
+
+def test_validation_errors(sp):
+    T = W.laplacian_triangle((4, 4))
+    rp, ci, v = T.row_ptr, T.col_idx, T.vals
+    with pytest.raises(sp.SpTRSVError) as e:
+        sp.Handle(dev(rp), dev(ci), dev(v), uplo="U")
+    assert e.value.status == -4
+    bad = ci.copy(); bad[3] = 99
+    with pytest.raises(sp.SpTRSVError) as e:
+        sp.Handle(dev(rp), dev(bad), dev(v))
+    assert e.value.status == -3
+    rp2 = rp.copy(); rp2[1:] -= 1
+    with pytest.raises(sp.SpTRSVError) as e:
+        sp.Handle(dev(rp2), dev(ci[1:]), dev(v[1:]))
+    assert e.value.status == -6
+
+
+def test_empty_and_single(sp):
+    h = sp.Handle(dev(np.zeros(1, np.int32)), dev(np.zeros(0, np.int32)), dev(np.zeros(0)))
+    x = h.solve(dev(np.zeros(0)))
+    assert x.numel() == 0
+    h.status()
+    h = sp.Handle(dev(np.array([0, 1], np.int32)), dev(np.array([0], np.int32)), dev(np.array([4.0])))
+    for algo in (1, 2):
+        h.set_option("algo", algo)
+        assert host(h.solve(dev(np.array([2.0]))))[0] == 0.5
+
+
+@pytest.mark.parametrize("sync", [0, 1])
+def test_watchdog_timeout_is_reported_and_recovers(sp, sync):
+    """A spin limit of one poll (forced from the host) makes waits give up:
+    the kernel drains, TIMEOUT is reported; with the default limit the same
+    handle solves correctly again."""
+    n = 20000
+    P = W.bidiagonal_fast(n, 1.0, 1.0)
+    b = np.ones(n)
+    h = sp.Handle(*dev_tri(P)).configure(algo=2, sync=sync, spin_limit=1)
+    h.solve(dev(b))
+    with pytest.raises(sp.SpTRSVError) as e:
+        h.status()
+    assert e.value.status == -10
+    h.set_option("spin_limit", 1 << 22)
+    x = host(h.solve(dev(b)))
+    h.status()
+    assert np.array_equal(x, np.arange(1, n + 1, dtype=np.float64))
+
+
+@pytest.mark.parametrize("opts", [dict(algo=1), dict(algo=2, sync=0), dict(algo=2, sync=1)])
+def test_graph_replay(sp, opts):
+    T = W.laplacian_triangle((24, 23, 22))
+    h = sp.Handle(*dev_tri(T)).configure(**opts)
+    s = torch.cuda.Stream()
+    b = dev(W.uniform_vector(T.n, 2))
+    x = torch.empty_like(b)
+    with torch.cuda.stream(s):
+        ref = h.solve(b)
+        g = h.capture(b, x, stream=s)
+        gt = h.capture(b, x, transpose=True, stream=s)
+        ref_t = h.solve_t(b)
+        for rep in range(5):
+            x.zero_()
+            g.launch(s)
+            s.synchronize()
+            assert bits_equal(x, ref), rep
+            junk = h.solve(b * 2.0)            # eager work between replays
+            s.synchronize()
+            gt.launch(s)
+            s.synchronize()
+            assert bits_equal(x, ref_t), rep
+    h.status()
+
+
+def test_tune_and_timing(sp):
+    o = oracle.get()
+    T = W.laplacian_triangle((30, 30, 30))
+    h = sp.Handle(*dev_tri(T))
+    b = dev(W.uniform_vector(T.n, 3))
+    info = h.tune(b)
+    assert info["algo"] in (1, 2)
+    h.set_option("timing", 1)
+    for _ in range(4):
+        x = h.solve(b)
+    ms, cnt = h.kernel_time()
+    assert cnt == 4 and ms > 0
+    assert relerr(host(x), o.solve(T.row_ptr, T.col_idx, T.vals, host(b))) <= TOL64
