@@ -89,10 +89,23 @@ typedef enum {
     SPTRSV_OPT_ENTRIES_PER_LANE = 2, /* target entries per lane when GROUP = 0 (default 4) */
     SPTRSV_OPT_SYNC = 3,          /* sptrsv_sync (self-scheduled only) */
     SPTRSV_OPT_SPIN_LIMIT = 4,    /* max polls of one dependency before TIMEOUT (>= 1) */
-    SPTRSV_OPT_GRID = 5,          /* persistent workgroups; 0 = sized from occupancy */
+    SPTRSV_OPT_GRID = 5,          /* persistent workgroups; 0 = one wavefront per CU */
     SPTRSV_OPT_TIMING = 6,        /* 1 = record HIP events around the main solve kernel */
-    SPTRSV_OPT_WG = 7             /* threads per workgroup for the row kernels (64..1024) */
+    SPTRSV_OPT_WG = 7,            /* threads per workgroup for the row kernels (64..256,
+                                     default 64) */
+    SPTRSV_OPT_ROWS_PER_LANE = 8, /* rows one lane owns when a row gets one lane (1..4,
+                                     default 1): fewer, larger work chunks */
+    SPTRSV_OPT_ASSIGN = 9         /* sptrsv_assign: how self-scheduled wavefronts get chunks */
 } sptrsv_option;
+
+typedef enum {
+    SPTRSV_ASSIGN_STATIC = 0,     /* chunk c goes to wavefront c mod W of a cooperatively
+                                     launched (all-resident) grid, pipelined four chunks
+                                     deep; value sync, one right-hand side.  Under HIP graph
+                                     capture the ticket form is used instead. */
+    SPTRSV_ASSIGN_TICKET = 1      /* wavefronts claim chunks from an atomic ticket: needs no
+                                     co-residency, costs one serialised atomic per chunk */
+} sptrsv_assign;
 
 /* ---------------------------------------------------------------------- */
 /* Analysis (setup phase, Sec. 4.4): validates the triangle, computes the
@@ -174,8 +187,11 @@ int sptrsv_set_option(sptrsv_handle_t h, sptrsv_option key, int64_t value);
 int sptrsv_get_option(sptrsv_handle_t h, sptrsv_option key, int64_t *value);
 
 /* Time short trials of the candidate schedules on (b, x) -- both device
- * vectors of n elements, x overwritten -- and keep the fastest (ALGO, GROUP,
- * SYNC).  Results are cached per pattern hash in the process. */
+ * vectors of n elements, x overwritten -- and keep the fastest (lanes per row
+ * rule, rows per lane, sync, persistent grid; and the algorithm when ALGO is
+ * AUTO, else only candidates of the fixed ALGO).  Results are cached per
+ * pattern hash in the process.  Changing a schedule option afterwards drops
+ * the tuned choice. */
 int sptrsv_tune(sptrsv_handle_t h, const void *b, void *x, hipStream_t stream);
 
 /* n, nnz, nlev of T; the algorithm and lanes per row the next solve uses
@@ -185,10 +201,12 @@ int sptrsv_get_info(sptrsv_handle_t h, int32_t *n, int64_t *nnz, int32_t *nlev,
 
 /* The schedule the next solve will use (resolved: the autotuner's choice if
  * current, else the options): sptrsv_algo, lanes per row (0 = by row
- * length), entries per lane of the length rule, sptrsv_sync.  Any pointer
- * may be NULL. */
+ * length), entries per lane of the length rule, sptrsv_sync, rows per lane,
+ * persistent workgroups (0 = default), sptrsv_assign.  Any pointer may be
+ * NULL. */
 int sptrsv_get_schedule(sptrsv_handle_t h, int32_t *algo, int32_t *group,
-                        int32_t *entries_per_lane, int32_t *sync);
+                        int32_t *entries_per_lane, int32_t *sync, int32_t *rows_per_lane,
+                        int32_t *grid, int32_t *assign);
 
 /* Copy the analysis to HOST buffers (any may be NULL): level int32[n],
  * ilev int32[nlev+1], jlev int32[n] (rows by (level, row)), depcnt int32[n]

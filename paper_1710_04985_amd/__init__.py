@@ -12,7 +12,6 @@ from __future__ import annotations
 
 import ctypes
 import os
-import weakref
 
 import numpy as np
 import torch
@@ -26,7 +25,8 @@ __all__ = ["Handle", "BatchedHandle", "SpTRSVFunction", "sptrsv", "SpTRSVError",
 ALGO_AUTO, ALGO_LEVEL, ALGO_SELF, ALGO_BLOCK = 0, 1, 2, 3
 SYNC_VALUE, SYNC_FLAG = 0, 1
 OPT = {"algo": 0, "group": 1, "entries_per_lane": 2, "sync": 3, "spin_limit": 4,
-       "grid": 5, "timing": 6, "wg": 7}
+       "grid": 5, "timing": 6, "wg": 7, "rows_per_lane": 8, "assign": 9}
+ASSIGN_STATIC, ASSIGN_TICKET = 0, 1
 
 _DT = {torch.float64: 0, torch.float32: 1}
 
@@ -110,10 +110,12 @@ class _Base:
         nnz = ctypes.c_int64()
         check(lib.sptrsv_get_info(self._h, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(nlev),
                                   ctypes.byref(algo), ctypes.byref(group)))
-        epl, sync = ctypes.c_int32(), ctypes.c_int32()
-        check(lib.sptrsv_get_schedule(self._h, None, None, ctypes.byref(epl), ctypes.byref(sync)))
+        epl, sync, rpl, grid, assign = (ctypes.c_int32() for _ in range(5))
+        check(lib.sptrsv_get_schedule(self._h, None, None, ctypes.byref(epl), ctypes.byref(sync),
+                                      ctypes.byref(rpl), ctypes.byref(grid), ctypes.byref(assign)))
         return {"n": n.value, "nnz": nnz.value, "nlev": nlev.value, "algo": algo.value,
-                "group": group.value, "entries_per_lane": epl.value, "sync": sync.value}
+                "group": group.value, "entries_per_lane": epl.value, "sync": sync.value,
+                "rows_per_lane": rpl.value, "grid": grid.value, "assign": assign.value}
 
     def export_analysis(self, transpose=False):
         """(level, ilev, jlev, depcnt) as numpy int32 arrays (host copies)."""
@@ -263,17 +265,17 @@ class BatchedHandle(_Base):
 class SpTRSVFunction(torch.autograd.Function):
     """x = T^{-1} b with T = (pattern of `handle`, values `vals`).
 
+    Forward gathers `vals` into the handle (one streaming kernel) unless
+    `values_current` says the handle already holds exactly these values --
+    tensor identity or version counters cannot tell (in-place writes through
+    .data do not bump the version).
     Backward (the adjoint): grad_b = T^{-T} grad_x by the transposed solve,
     grad_vals[k] = -grad_b[i] * x[j] for each stored entry k = (i, j)."""
 
     @staticmethod
-    def forward(ctx, vals, b, handle):
-        # re-gather unless these exact values (same tensor object, same
-        # in-place version) were the last ones gathered
-        last = getattr(handle, "_gathered", None)
-        if last is None or last[0]() is not vals or last[1] != vals._version:
-            handle.update_values(vals)
-            handle._gathered = (weakref.ref(vals), vals._version)
+    def forward(ctx, vals, b, handle, values_current=False):
+        if not values_current:
+            handle.update_values(vals.detach().contiguous())
         x = handle.solve(b.contiguous())
         ctx.handle = handle
         ctx.save_for_backward(x)
@@ -285,12 +287,12 @@ class SpTRSVFunction(torch.autograd.Function):
         h = ctx.handle
         gb = h.solve_t(gx.contiguous())
         gv = h.grad_vals(gb, x) if ctx.needs_input_grad[0] else None
-        return gv, (gb if ctx.needs_input_grad[1] else None), None
+        return gv, (gb if ctx.needs_input_grad[1] else None), None, None
 
 
-def sptrsv(vals, b, handle):
+def sptrsv(vals, b, handle, values_current=False):
     """Differentiable x = T^{-1} b (see SpTRSVFunction)."""
-    return SpTRSVFunction.apply(vals, b, handle)
+    return SpTRSVFunction.apply(vals, b, handle, values_current)
 
 
 def analyze_host(row_ptr, col_idx, upper=False, unit_diag=False):

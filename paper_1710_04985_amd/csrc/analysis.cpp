@@ -154,8 +154,10 @@ void build_plan(int n, const int* row_ptr, const int* col, const int* src, bool 
 }
 
 void build_chunks(const HostPlan& p, int group, int entries_per_lane, int rows_fixed,
-                  ChunkTable& t) {
+                  int rows_per_lane, ChunkTable& t) {
   t = ChunkTable();
+  if (rows_per_lane < 1) rows_per_lane = 1;
+  if (rows_per_lane > kMaxRowsPerLane) rows_per_lane = kMaxRowsPerLane;
   t.level_chunk.resize(p.nlev + 1);
   if (entries_per_lane < 1) entries_per_lane = 1;
   // log2 of the lanes a row of `len` off-diagonals gets under the length rule
@@ -180,7 +182,7 @@ void build_chunks(const HostPlan& p, int group, int entries_per_lane, int rows_f
       int lg;
       if (rows_fixed > 0 || group > 0) lg = fixed_lg;
       else lg = lanes_for(p.off_ptr[k + 1] - p.off_ptr[k]);
-      const int cap = 64 >> lg;
+      const int cap = (lg == 0 && rows_fixed <= 0) ? 64 * rows_per_lane : 64 >> lg;
       int cnt = 1;
       while (cnt < cap && k + cnt < end) {
         if (rows_fixed <= 0 && group <= 0) {
@@ -190,7 +192,7 @@ void build_chunks(const HostPlan& p, int group, int entries_per_lane, int rows_f
         ++cnt;
       }
       t.start.push_back(k);
-      t.meta.push_back(cnt | (lg << 8));
+      t.meta.push_back(cnt | (lg << 16));
       t.max_lg = std::max(t.max_lg, lg);
       k += cnt;
     }

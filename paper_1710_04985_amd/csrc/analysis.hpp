@@ -74,11 +74,14 @@ void build_plan(int n, const int* row_ptr, const int* col, const int* src, bool 
                 bool unit_diag, HostPlan& plan);
 
 // Work chunks: runs of consecutive positions inside ONE level, processed by
-// one 64-lane wavefront.  A chunk holds `count` rows of G = 2^lg lanes each
-// (count * G <= 64).  Encoded as {start, count | lg << 8}.
+// one 64-lane wavefront.  A chunk holds `count` rows of G = 2^lg lanes each:
+// count * G <= 64 when G > 1; with G = 1 a lane may own up to rows_per_lane
+// rows (count <= 64 * rows_per_lane).  Encoded as {start, count | lg << 16}.
+constexpr int kMaxRowsPerLane = 4;
+
 struct ChunkTable {
   std::vector<int> start;         // first position of each chunk
-  std::vector<int> meta;          // count | (lg << 8)
+  std::vector<int> meta;          // count | (lg << 16)
   std::vector<int> level_chunk;   // chunks of level m: [level_chunk[m], level_chunk[m+1])
   int max_lg = 0;
 };
@@ -87,8 +90,9 @@ struct ChunkTable {
 // group == 0: G = smallest power of two with ceil(len / G) <= entries_per_lane.
 // rows_fixed > 0 overrides both: count <= rows_fixed and G = 64 / rows_fixed
 // (multi-RHS kernels, where lanes split right-hand sides, not entries).
+// rows_per_lane (1..kMaxRowsPerLane) caps the rows a G = 1 lane owns.
 void build_chunks(const HostPlan& plan, int group, int entries_per_lane, int rows_fixed,
-                  ChunkTable& out);
+                  int rows_per_lane, ChunkTable& out);
 
 // 64-bit FNV-1a hash of a pattern (autotuner cache key).
 uint64_t pattern_hash(int n, const int* row_ptr, const int* col, bool upper, bool unit_diag);

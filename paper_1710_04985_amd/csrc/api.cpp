@@ -33,7 +33,8 @@ struct PlanState {
   HostPlan h;
   DevPlan d;
   void* vals_buf = nullptr;       // [noff + n] values: off-diagonals then diagonal
-  std::map<std::tuple<int, int, int>, ChunkEntry> chunks;   // (group, epl, rows_fixed)
+  // (group, epl, rows_fixed, rows_per_lane)
+  std::map<std::tuple<int, int, int, int>, ChunkEntry> chunks;
 };
 
 struct Config {
@@ -41,6 +42,9 @@ struct Config {
   int group;
   int epl;
   int sync;
+  int rpl;    // rows per lane
+  int grid;   // persistent workgroups, 0 = default
+  int assign; // sptrsv_assign
 };
 
 std::mutex g_tune_mu;
@@ -76,10 +80,12 @@ struct sptrsv_handle_s {
   int spin_limit = 1 << 22;
   int grid = 0;
   int timing = 0;
-  int wg = 256;
+  int wg = 64;
+  int rpl = 1;
+  int assign = SPTRSV_ASSIGN_STATIC;
   // autotuner result
   bool tuned = false;
-  Config tuned_cfg{SPTRSV_ALGO_SELF, 0, 4, SPTRSV_SYNC_VALUE};
+  Config tuned_cfg{SPTRSV_ALGO_SELF, 0, 4, SPTRSV_SYNC_VALUE, 1, 0, SPTRSV_ASSIGN_STATIC};
   uint64_t hash = 0;
   // timing
   std::map<std::pair<int, int>, int> occupancy;   // (kernel kind, wg) -> blocks per CU
@@ -216,12 +222,13 @@ int build_transpose(sptrsv_handle_t h, hipStream_t s) {
 }
 
 ChunkEntry* get_chunks(sptrsv_handle_t h, PlanState& ps, int group, int epl, int rows_fixed,
-                       int* err) {
-  auto key = std::make_tuple(group, epl, rows_fixed);
+                       int rpl, int* err) {
+  (void)h;
+  auto key = std::make_tuple(group, epl, rows_fixed, rpl);
   auto it = ps.chunks.find(key);
   if (it != ps.chunks.end()) return &it->second;
   ChunkTable t;
-  build_chunks(ps.h, group, epl, rows_fixed, t);
+  build_chunks(ps.h, group, epl, rows_fixed, rpl, t);
   ChunkEntry e;
   e.level_chunk = t.level_chunk;
   e.max_lg = t.max_lg;
@@ -255,7 +262,7 @@ ChunkEntry* get_chunks(sptrsv_handle_t h, PlanState& ps, int group, int epl, int
 // proposal).
 Config resolve(sptrsv_handle_t h) {
   if (h->tuned) return h->tuned_cfg;
-  Config c{h->algo, h->group, h->epl, h->sync};
+  Config c{h->algo, h->group, h->epl, h->sync, h->rpl, h->grid, h->assign};
   if (c.algo == SPTRSV_ALGO_AUTO) c.algo = SPTRSV_ALGO_SELF;
   return c;
 }
@@ -276,8 +283,8 @@ int ensure_tmp(sptrsv_handle_t h, size_t bytes) {
 }
 
 // Resident workgroups per CU of persistent kernel `kind` (0 value sync, 1 flag
-// sync, 2 multi-RHS); queried once per (kind, wg) and cached, so that solves
-// under graph capture make no occupancy query.
+// sync, 2 multi-RHS, 3 static value sync); queried once per (kind, wg) and
+// cached, so that solves under graph capture make no occupancy query.
 int blocks_per_cu(sptrsv_handle_t h, int kind) {
   const auto key = std::make_pair(kind, h->wg);
   auto it = h->occupancy.find(key);
@@ -286,17 +293,21 @@ int blocks_per_cu(sptrsv_handle_t h, int kind) {
   const bool dbl = h->dtype == SPTRSV_F64;
   if (kind == 0) per_cu = dbl ? self_value_blocks_per_cu<double>(h->wg) : self_value_blocks_per_cu<float>(h->wg);
   else if (kind == 1) per_cu = dbl ? self_flag_blocks_per_cu<double>(h->wg) : self_flag_blocks_per_cu<float>(h->wg);
-  else per_cu = dbl ? self_multi_blocks_per_cu<double>(h->wg) : self_multi_blocks_per_cu<float>(h->wg);
+  else if (kind == 2) per_cu = dbl ? self_multi_blocks_per_cu<double>(h->wg) : self_multi_blocks_per_cu<float>(h->wg);
+  else per_cu = dbl ? self_static_blocks_per_cu<double>(h->wg) : self_static_blocks_per_cu<float>(h->wg);
   h->occupancy[key] = per_cu;
   return per_cu;
 }
 
-int persistent_grid(sptrsv_handle_t h, int kind, int nchunks) {
-  if (h->grid > 0) return h->grid;
+// Workgroups of a persistent launch: the explicit choice, else one
+// wavefront per CU; never more than resident capacity or than chunks need.
+int persistent_grid(sptrsv_handle_t h, int kind, int grid, int nchunks) {
   const int per_cu = blocks_per_cu(h, kind);
   const int waves_per_block = h->wg / 64;
   const int need = (nchunks + waves_per_block - 1) / waves_per_block;
-  return std::max(1, std::min(per_cu * h->num_cu, need));
+  int g = grid > 0 ? grid : (h->num_cu + waves_per_block - 1) / waves_per_block;
+  g = std::min(g, per_cu * h->num_cu);
+  return std::max(1, std::min(g, need));
 }
 
 void timing_begin(sptrsv_handle_t h, hipStream_t s, hipEvent_t* stop) {
@@ -332,8 +343,13 @@ int solve_impl(sptrsv_handle_t h, PlanState& ps, const Config& c, const void* b,
   int kl = 1;
   while (kl < nrhs && kl < 64) kl <<= 1;
   int err = kOk;
-  ChunkEntry* ch = multi ? get_chunks(h, ps, 0, 0, 64 / kl, &err)
-                         : get_chunks(h, ps, c.group, c.epl, 0, &err);
+  // static assignment keeps one row per lane (its pipeline holds one row)
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cap) != hipSuccess) return kErrHip;
+  const bool use_static = !multi && c.algo == SPTRSV_ALGO_SELF && c.sync == SPTRSV_SYNC_VALUE &&
+                          c.assign == SPTRSV_ASSIGN_STATIC && cap == hipStreamCaptureStatusNone;
+  ChunkEntry* ch = multi ? get_chunks(h, ps, 0, 0, 64 / kl, 1, &err)
+                         : get_chunks(h, ps, c.group, c.epl, 0, use_static ? 1 : c.rpl, &err);
   if (!ch) return err;
   SolveArgs a;
   a.plan = &ps.d;
@@ -358,7 +374,7 @@ int solve_impl(sptrsv_handle_t h, PlanState& ps, const Config& c, const void* b,
   }
   if (c.algo != SPTRSV_ALGO_SELF) return kErrNotSupported;
   if (c.sync == SPTRSV_SYNC_FLAG && !multi) {
-    a.grid = persistent_grid(h, 1, ch->d.count);
+    a.grid = persistent_grid(h, 1, c.grid, ch->d.count);
     timing_begin(h, s, &stop);
     if (launch_self_flag<T>(a, s) != hipSuccess) return kErrHip;
     timing_end(s, stop);
@@ -374,9 +390,10 @@ int solve_impl(sptrsv_handle_t h, PlanState& ps, const Config& c, const void* b,
   }
   if (launch_fill_sentinel<T>(static_cast<T*>(x), save, n, nrhs, ld, s) != hipSuccess)
     return kErrHip;
-  a.grid = persistent_grid(h, multi ? 2 : 0, ch->d.count);
+  a.grid = persistent_grid(h, multi ? 2 : (use_static ? 3 : 0), c.grid, ch->d.count);
   timing_begin(h, s, &stop);
-  const hipError_t e = multi ? launch_self_multi_value<T>(a, s) : launch_self_value<T>(a, s);
+  const hipError_t e = multi ? launch_self_multi_value<T>(a, s)
+                             : (use_static ? launch_self_static<T>(a, s) : launch_self_value<T>(a, s));
   if (e != hipSuccess) return kErrHip;
   timing_end(s, stop);
   return kOk;
@@ -638,7 +655,8 @@ int sptrsv_grad_vals(sptrsv_handle_t h, const int32_t* row_ptr, const int32_t* c
 int sptrsv_set_option(sptrsv_handle_t h, sptrsv_option key, int64_t v) {
   if (!h) return kErrInvalidArg;
   if (key == SPTRSV_OPT_ALGO || key == SPTRSV_OPT_GROUP || key == SPTRSV_OPT_ENTRIES_PER_LANE ||
-      key == SPTRSV_OPT_SYNC)
+      key == SPTRSV_OPT_SYNC || key == SPTRSV_OPT_ROWS_PER_LANE || key == SPTRSV_OPT_GRID ||
+      key == SPTRSV_OPT_ASSIGN)
     h->tuned = false;   // an explicit schedule option overrides the tuner's choice
   switch (key) {
     case SPTRSV_OPT_ALGO:
@@ -670,8 +688,16 @@ int sptrsv_set_option(sptrsv_handle_t h, sptrsv_option key, int64_t v) {
       h->timing = v != 0;
       return kOk;
     case SPTRSV_OPT_WG:
-      if (v < 64 || v > 1024 || (v % 64)) return kErrInvalidArg;
+      if (v < 64 || v > 256 || (v % 64)) return kErrInvalidArg;
       h->wg = static_cast<int>(v);
+      return kOk;
+    case SPTRSV_OPT_ROWS_PER_LANE:
+      if (v < 1 || v > kMaxRowsPerLane) return kErrInvalidArg;
+      h->rpl = static_cast<int>(v);
+      return kOk;
+    case SPTRSV_OPT_ASSIGN:
+      if (v != SPTRSV_ASSIGN_STATIC && v != SPTRSV_ASSIGN_TICKET) return kErrInvalidArg;
+      h->assign = static_cast<int>(v);
       return kOk;
   }
   return kErrInvalidArg;
@@ -688,6 +714,8 @@ int sptrsv_get_option(sptrsv_handle_t h, sptrsv_option key, int64_t* v) {
     case SPTRSV_OPT_GRID: *v = h->grid; return kOk;
     case SPTRSV_OPT_TIMING: *v = h->timing; return kOk;
     case SPTRSV_OPT_WG: *v = h->wg; return kOk;
+    case SPTRSV_OPT_ROWS_PER_LANE: *v = h->rpl; return kOk;
+    case SPTRSV_OPT_ASSIGN: *v = h->assign; return kOk;
   }
   return kErrInvalidArg;
 }
@@ -696,16 +724,24 @@ int sptrsv_tune(sptrsv_handle_t h, const void* b, void* x, hipStream_t stream) {
   if (!h) return kErrInvalidArg;
   if (h->n == 0) return kOk;
   if (!b || !x || b == x) return kErrInvalidArg;
-  // candidate schedules: lane rules (entries per lane) of the self-scheduled
-  // solve under both syncs and of the level-scheduled solve, restricted to
-  // the algorithm the options fix (all of them under ALGO_AUTO)
+  // candidate schedules, restricted to the algorithm the options fix (all of
+  // them under ALGO_AUTO): the lane rule (entries per lane), rows per lane
+  // and, for the self-scheduled solve, the persistent grid and the sync
   std::vector<Config> cand;
+  const int ncu = h->num_cu;
+  const bool self_ok = h->algo != SPTRSV_ALGO_LEVEL, level_ok = h->algo != SPTRSV_ALGO_SELF;
   for (int epl : {1, 2, 4, 8}) {
-    if (h->algo != SPTRSV_ALGO_LEVEL) {
-      cand.push_back({SPTRSV_ALGO_SELF, 0, epl, SPTRSV_SYNC_VALUE});
-      cand.push_back({SPTRSV_ALGO_SELF, 0, epl, SPTRSV_SYNC_FLAG});
+    if (self_ok) {
+      for (int grid : {ncu / 2, ncu, 2 * ncu, 4 * ncu})
+        cand.push_back({SPTRSV_ALGO_SELF, 0, epl, SPTRSV_SYNC_VALUE, 1, grid, SPTRSV_ASSIGN_STATIC});
+      for (int rpl : {1, 4})
+        cand.push_back({SPTRSV_ALGO_SELF, 0, epl, SPTRSV_SYNC_VALUE, rpl, ncu, SPTRSV_ASSIGN_TICKET});
+      if (epl == 1 || epl == 4)
+        cand.push_back({SPTRSV_ALGO_SELF, 0, epl, SPTRSV_SYNC_FLAG, 1, ncu, SPTRSV_ASSIGN_TICKET});
     }
-    if (h->algo != SPTRSV_ALGO_SELF) cand.push_back({SPTRSV_ALGO_LEVEL, 0, epl, SPTRSV_SYNC_VALUE});
+    if (level_ok)
+      for (int rpl : {1, 4})
+        cand.push_back({SPTRSV_ALGO_LEVEL, 0, epl, SPTRSV_SYNC_VALUE, rpl, 0, SPTRSV_ASSIGN_TICKET});
   }
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
@@ -720,9 +756,18 @@ int sptrsv_tune(sptrsv_handle_t h, const void* b, void* x, hipStream_t stream) {
       return h->dtype == SPTRSV_F64 ? solve_impl<double>(h, h->fwd, c, b, x, 1, h->n, stream)
                                     : solve_impl<float>(h, h->fwd, c, b, x, 1, h->n, stream);
     };
-    if ((st = run())) break;   // warm-up (also builds the chunk table)
+    // level-scheduled trials cost a launch per level: skip them on very deep DAGs
+    if (c.algo == SPTRSV_ALGO_LEVEL && h->fwd.h.nlev > 20000 && cand.size() > 1) continue;
     if (hipEventRecord(e0, stream) != hipSuccess) { st = kErrHip; break; }
-    const int reps = 3;
+    if ((st = run())) break;   // warm-up (also builds the chunk table)
+    if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+      st = kErrHip;
+      break;
+    }
+    float warm_ms = 0.f;
+    (void)hipEventElapsedTime(&warm_ms, e0, e1);
+    if (hipEventRecord(e0, stream) != hipSuccess) { st = kErrHip; break; }
+    const int reps = warm_ms > 20.f ? 1 : 3;
     for (int r = 0; r < reps && !st; ++r) st = run();
     if (st) break;
     if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
@@ -731,6 +776,7 @@ int sptrsv_tune(sptrsv_handle_t h, const void* b, void* x, hipStream_t stream) {
     }
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, e0, e1);
+    ms /= reps;
     if (ms < best) {
       best = ms;
       best_c = c;
@@ -762,13 +808,17 @@ int sptrsv_get_info(sptrsv_handle_t h, int32_t* n, int64_t* nnz, int32_t* nlev, 
 }
 
 int sptrsv_get_schedule(sptrsv_handle_t h, int32_t* algo, int32_t* group,
-                        int32_t* entries_per_lane, int32_t* sync) {
+                        int32_t* entries_per_lane, int32_t* sync, int32_t* rows_per_lane,
+                        int32_t* grid, int32_t* assign) {
   if (!h) return kErrInvalidArg;
   const Config c = resolve(h);
   if (algo) *algo = c.algo;
   if (group) *group = c.group;
   if (entries_per_lane) *entries_per_lane = c.epl;
   if (sync) *sync = c.sync;
+  if (rows_per_lane) *rows_per_lane = c.rpl;
+  if (grid) *grid = c.grid;
+  if (assign) *assign = c.assign;
   return kOk;
 }
 
@@ -848,9 +898,9 @@ int sptrsv_graph_capture(sptrsv_handle_t h, const void* b, void* x, int transpos
   {
     const Config c = resolve(h);
     int err = kOk;
-    if (h->n > 0 && !get_chunks(h, transpose ? h->trn : h->fwd, c.group, c.epl, 0, &err))
+    if (h->n > 0 && !get_chunks(h, transpose ? h->trn : h->fwd, c.group, c.epl, 0, c.rpl, &err))
       return err;
-    for (int kind = 0; kind < 3; ++kind) (void)blocks_per_cu(h, kind);
+    for (int kind = 0; kind < 4; ++kind) (void)blocks_per_cu(h, kind);
   }
   auto* g = new (std::nothrow) sptrsv_graph_s;
   if (!g) return kErrOom;

@@ -24,6 +24,7 @@
 // counter, without its per-solve reset).
 #include <hip/hip_runtime.h>
 
+#include "analysis.hpp"
 #include "kernels.hpp"
 
 namespace sptrsv {
@@ -102,6 +103,8 @@ template <typename T> struct KArgs {
   const int* chunk_start;
   const int* chunk_meta;
   int nchunks;
+  int n;
+  int64_t noff;
   const int* off_ptr;
   const int* off_col;
   const T* off_val;
@@ -118,15 +121,14 @@ template <typename T> struct KArgs {
   int spin_limit;
 };
 
-// Sum over the lane's entries e0+gl, e0+gl+G, ... of val*x[col], in that
-// order, four entries in flight at a time.  kPoll: x is read with agent-scope
-// atomic loads and sentinel values are waited for.
+// Continues `sum` over the lane's entries e, e+G, e+2G, ... < e1 of one row,
+// four entries in flight at a time.  kPoll: x is read with agent-scope atomic
+// loads and sentinel values are waited for.
 template <typename T, bool kPoll>
 __device__ __forceinline__ T row_dot(const int* __restrict__ off_col,
-                                     const T* __restrict__ off_val, int e0, int e1, int gl,
-                                     int G, const T* x, int spin_limit, int* status) {
-  T sum = T(0);
-  for (int e = e0 + gl; e < e1; e += 4 * G) {
+                                     const T* __restrict__ off_val, int e, int e1, int G,
+                                     const T* x, int spin_limit, int* status, T sum) {
+  for (; e < e1; e += 4 * G) {
     int j[4];
     T v[4], xv[4];
 #pragma unroll
@@ -157,7 +159,92 @@ template <typename T> __device__ __forceinline__ T group_sum(T v, int lg) {
   return v;
 }
 
+template <typename T, bool kPoll> __device__ __forceinline__ void store_x(T* p, T v) {
+  if constexpr (kPoll) store_agent(p, v);
+  else *p = v;
+}
+
 __device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Solves the rows of one chunk (see the chunk encoding in analysis.hpp).
+//  G = 1: lane l owns rows start+l, start+l+64, ... (up to kMaxRowsPerLane);
+//         the bounds, first four entries, x gathers, b and diagonal of all its
+//         rows are issued before any wait, then each row is finished.
+//  G > 1: rows of G lanes; lanes stride the row, the group sums by butterfly.
+// Per row the accumulation order is the same in every kernel using this, so
+// level- and self-scheduled solves agree bit for bit at equal chunking.
+template <typename T, bool kPoll>
+__device__ __forceinline__ void solve_chunk(const KArgs<T>& a, int start, int meta, int lane) {
+  const int cnt = meta & 0xffff, lg = meta >> 16;
+  if (lg == 0) {
+    constexpr int R = kMaxRowsPerLane;
+    constexpr int E = 4;
+    int k[R], e0[R], e1[R], i[R];
+    T bi[R], di[R];
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int rr = lane + 64 * u;
+      k[u] = rr < cnt ? start + rr : -1;
+      e0[u] = 0;
+      e1[u] = 0;
+      i[u] = 0;
+      bi[u] = T(0);
+      di[u] = T(1);
+      if (k[u] >= 0) {
+        e0[u] = a.off_ptr[k[u]];
+        e1[u] = a.off_ptr[k[u] + 1];
+        i[u] = a.pos_row[k[u]];
+        di[u] = a.diag[k[u]];
+      }
+    }
+    int j[R][E];
+    T v[R][E], xv[R][E];
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      if (k[u] >= 0) bi[u] = a.b[i[u]];
+#pragma unroll
+      for (int q = 0; q < E; ++q) {
+        const int ee = e0[u] + q;
+        j[u][q] = ee < e1[u] ? a.off_col[ee] : -1;
+        v[u][q] = ee < e1[u] ? a.off_val[ee] : T(0);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < R; ++u)
+#pragma unroll
+      for (int q = 0; q < E; ++q)
+        xv[u][q] = j[u][q] >= 0 ? (kPoll ? load_agent(a.x + j[u][q]) : a.x[j[u][q]]) : T(0);
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      if (k[u] < 0) continue;
+      T sum = T(0);
+#pragma unroll
+      for (int q = 0; q < E; ++q) {
+        if (j[u][q] < 0) continue;
+        T xx = xv[u][q];
+        if (kPoll && is_sentinel(xx)) xx = wait_value(a.x + j[u][q], a.spin_limit, a.status);
+        sum = __builtin_fma(v[u][q], xx, sum);
+      }
+      if (e1[u] > e0[u] + E)
+        sum = row_dot<T, kPoll>(a.off_col, a.off_val, e0[u] + E, e1[u], 1, a.x, a.spin_limit,
+                                a.status, sum);
+      store_x<T, kPoll>(a.x + i[u], canonical((bi[u] - sum) / di[u]));
+    }
+    return;
+  }
+  const int r = lane >> lg, gl = lane & ((1 << lg) - 1);
+  const bool active = r < cnt;
+  const int k = start + r;
+  T sum = T(0);
+  if (active)
+    sum = row_dot<T, kPoll>(a.off_col, a.off_val, a.off_ptr[k] + gl, a.off_ptr[k + 1], 1 << lg,
+                            a.x, a.spin_limit, a.status, T(0));
+  sum = group_sum(sum, lg);
+  if (active && gl == 0) {
+    const int i = a.pos_row[k];
+    store_x<T, kPoll>(a.x + i, canonical((a.b[i] - sum) / a.diag[k]));
+  }
+}
 
 // Claims the next chunk for the calling wavefront (lane 0 does the atomic).
 // Returns -1 when all chunks are taken; the very last claim of the grid
@@ -176,55 +263,158 @@ __device__ __forceinline__ int claim_chunk(int* ticket, int nchunks, int lane) {
 
 // ---------------------------------------------------------------- level
 template <typename T>
-__global__ void __launch_bounds__(1024) k_level(KArgs<T> a, int chunk_begin, int chunk_end) {
+__global__ void __launch_bounds__(256) k_level(KArgs<T> a, int chunk_begin, int chunk_end) {
   const int lane = threadIdx.x & 63;
   const int c = wave_uniform(chunk_begin + static_cast<int>((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
   if (c >= chunk_end) return;
-  const int start = a.chunk_start[c];
-  const int meta = a.chunk_meta[c];
-  const int cnt = meta & 0xff, lg = meta >> 8;
-  const int r = lane >> lg, gl = lane & ((1 << lg) - 1);
-  const bool active = r < cnt;
-  const int k = start + r;
-  T sum = T(0);
-  if (active)
-    sum = row_dot<T, false>(a.off_col, a.off_val, a.off_ptr[k], a.off_ptr[k + 1], gl, 1 << lg,
-                            a.x, 0, a.status);
-  sum = group_sum(sum, lg);
-  if (active && gl == 0) {
-    const int i = a.pos_row[k];
-    a.x[i] = canonical((a.b[i] - sum) / a.diag[k]);
-  }
+  solve_chunk<T, false>(a, a.chunk_start[c], a.chunk_meta[c], lane);
 }
 
 // ----------------------------------------------------- self, value sync
 template <typename T>
-__global__ void __launch_bounds__(1024) k_self_value(KArgs<T> a) {
+__global__ void __launch_bounds__(256) k_self_value(KArgs<T> a) {
   const int lane = threadIdx.x & 63;
   for (;;) {
     const int c = claim_chunk(a.ticket, a.nchunks, lane);
     if (c < 0) return;
-    const int start = a.chunk_start[c];
-    const int meta = a.chunk_meta[c];
-    const int cnt = meta & 0xff, lg = meta >> 8;
-    const int r = lane >> lg, gl = lane & ((1 << lg) - 1);
-    const bool active = r < cnt;
-    const int k = start + r;
-    T sum = T(0);
-    if (active)
-      sum = row_dot<T, true>(a.off_col, a.off_val, a.off_ptr[k], a.off_ptr[k + 1], gl, 1 << lg,
-                             a.x, a.spin_limit, a.status);
-    sum = group_sum(sum, lg);
-    if (active && gl == 0) {
-      const int i = a.pos_row[k];
-      store_agent(a.x + i, canonical((a.b[i] - sum) / a.diag[k]));
+    solve_chunk<T, true>(a, a.chunk_start[c], a.chunk_meta[c], lane);
+  }
+}
+
+// ------------------------------------- self, value sync, static pipeline
+// Wavefront w of W takes chunks w, w+W, w+2W, ... in that order (the grid is
+// launched cooperatively, so all W wavefronts are resident: the wavefront
+// holding the lowest unfinished chunk has finished its earlier chunks and is
+// working on it, and that chunk's dependencies are done).  No claim atomics.
+// Each chunk moves through four stages, one chunk apart, so the dependent
+// index loads of later chunks are in flight while this one waits on x:
+//   A descriptor -> B row bounds, row, diagonal -> C first entries, b
+//   -> D gather x (poll), accumulate, store.
+// Per row the arithmetic is that of solve_chunk with one row per lane.
+// Each stage only stores raw loaded values; any arithmetic on them happens
+// one iteration later, so no wait for a load is needed before the next
+// stage's loads (and the x gathers) have been issued.
+template <typename T> struct StageB {   // descriptor, raw
+  int c, start, meta;
+};
+template <typename T> struct StageC {   // row bounds, raw
+  int c, meta, k, p0, p1, i;
+  T d;
+};
+template <typename T> struct StageD {   // first entries of the lane, raw
+  int c, lg, k, e, e1, i;
+  T d, bi;
+  int j[4];
+  T v[4];
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_self_static(KArgs<T> a, const int* __restrict__ cstart, const int* __restrict__ cmeta) {
+  const int lane = threadIdx.x & 63;
+  const int W = static_cast<int>(gridDim.x * (blockDim.x >> 6));
+  const int w = wave_uniform(static_cast<int>((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+  const int nch = a.nchunks;
+  const int nlast = a.n - 1;          // clamp for loads whose result is discarded
+  const int64_t olast = a.noff > 0 ? a.noff - 1 : 0;
+  StageB<T> sb{-1, 0, 0};
+  StageC<T> sc{-1, 0, -1, 0, 0, 0, T(1)};
+  StageD<T> sd;
+  sd.c = -1;
+  sd.lg = 0;
+  sd.k = -1;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) sd.j[q] = -1;
+  int next = w;                       // next chunk to enter stage A
+  for (;;) {
+    // ---- A: descriptor of a new chunk (uniform index, read-only table)
+    StageB<T> nb{-1, 0, 0};
+    {
+      const int cn = wave_uniform(next < nch ? next : nch - 1);
+      nb.start = cstart[cn];
+      nb.meta = cmeta[cn];
+      if (next < nch) {
+        nb.c = next;
+        next += W;
+      }
     }
+    // ---- D (issue): gather x for the chunk whose entries arrived last time
+    T xv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) xv[q] = load_agent(a.x + (sd.j[q] >= 0 ? sd.j[q] : 0));
+    // ---- B: row bounds, row and diagonal of the chunk described last time
+    StageC<T> nc{sb.c, sb.meta, -1, 0, 0, 0, T(1)};
+    {
+      const int lg = sb.meta >> 16, cnt = sb.meta & 0xffff;
+      const int r = lane >> lg;
+      const bool live = sb.c >= 0 && r < cnt;
+      const int kk = live ? sb.start + r : nlast;
+      nc.k = live ? kk : -1;
+      nc.p0 = a.off_ptr[kk];
+      nc.p1 = a.off_ptr[kk + 1];
+      nc.i = a.pos_row[kk];
+      nc.d = a.diag[kk];
+    }
+    // ---- C: the lane's first four entries and b of the chunk bounded last time
+    StageD<T> nd;
+    nd.c = sc.c;
+    nd.lg = sc.meta >> 16;
+    nd.k = sc.k;
+    nd.i = sc.i;
+    nd.d = sc.d;
+    {
+      const int G = 1 << nd.lg;
+      const int gl = lane & (G - 1);
+      nd.e = sc.p0 + gl;
+      nd.e1 = sc.p1;
+      const bool live = sc.c >= 0 && sc.k >= 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int ee = nd.e + q * G;
+        const bool ok = live && ee < nd.e1;
+        const int64_t ec = ok ? ee : olast;
+        const int jj = a.off_col[ec];
+        const T vv = a.off_val[ec];
+        nd.j[q] = ok ? jj : -1;
+        nd.v[q] = ok ? vv : T(0);
+      }
+      const T bb = a.b[sc.i];
+      nd.bi = (live && gl == 0) ? bb : T(0);
+    }
+    // ---- D (finish): wait, accumulate, rest of the row, group sum, store
+    if (sd.c >= 0) {
+      const int G = 1 << sd.lg;
+      T sum = T(0);
+      if (sd.k >= 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (sd.j[q] < 0) continue;
+          T xx = xv[q];
+          if (is_sentinel(xx)) xx = wait_value(a.x + sd.j[q], a.spin_limit, a.status);
+          sum = __builtin_fma(sd.v[q], xx, sum);
+        }
+        if (sd.e + 4 * G < sd.e1)
+          sum = row_dot<T, true>(a.off_col, a.off_val, sd.e + 4 * G, sd.e1, G, a.x, a.spin_limit,
+                                 a.status, sum);
+      }
+      sum = group_sum(sum, sd.lg);
+      if (sd.k >= 0 && (lane & (G - 1)) == 0)
+        store_agent(a.x + sd.i, canonical((sd.bi - sum) / sd.d));
+    } else if (sc.c < 0 && sb.c < 0 && nb.c < 0) {
+      return;                         // pipeline drained
+    }
+    sd = nd;
+    sc = nc;
+    sb = nb;
   }
 }
 
 // ------------------------------------------------------ self, flag sync
+// Rows of a chunk: wait for the flags of all their dependencies, acquire,
+// solve with plain loads (same per-row order as solve_chunk), release, stamp
+// the rows' flags with this solve's epoch.
 template <typename T>
-__global__ void __launch_bounds__(1024) k_self_flag(KArgs<T> a) {
+__global__ void __launch_bounds__(256) k_self_flag(KArgs<T> a) {
   const int lane = threadIdx.x & 63;
   const unsigned epoch = *a.epoch;
   for (;;) {
@@ -243,16 +433,13 @@ __global__ void __launch_bounds__(1024) k_self_flag(KArgs<T> a) {
     }
     const int start = a.chunk_start[c];
     const int meta = a.chunk_meta[c];
-    const int cnt = meta & 0xff, lg = meta >> 8;
+    const int cnt = meta & 0xffff, lg = meta >> 16;
     const int G = 1 << lg;
-    const int r = lane >> lg, gl = lane & (G - 1);
-    const bool active = r < cnt;
-    const int k = start + r;
-    int e0 = 0, e1 = 0;
-    if (active) {
-      e0 = a.off_ptr[k];
-      e1 = a.off_ptr[k + 1];
-      for (int e = e0 + gl; e < e1; e += G) {
+    const int rstep = 64 >> lg;
+    const int r0 = lane >> lg, gl = lane & (G - 1);
+    for (int rr = r0; rr < cnt; rr += rstep) {
+      const int k = start + rr;
+      for (int e = a.off_ptr[k] + gl; e < a.off_ptr[k + 1]; e += G) {
         const unsigned* f = a.flags + a.off_col[e];
         if (__hip_atomic_load(const_cast<unsigned*>(f), __ATOMIC_RELAXED,
                               __HIP_MEMORY_SCOPE_AGENT) != epoch)
@@ -260,17 +447,25 @@ __global__ void __launch_bounds__(1024) k_self_flag(KArgs<T> a) {
       }
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    T sum = T(0);
-    if (active) sum = row_dot<T, false>(a.off_col, a.off_val, e0, e1, gl, G, a.x, 0, a.status);
-    sum = group_sum(sum, lg);
-    int i = -1;
-    if (active && gl == 0) {
-      i = a.pos_row[k];
-      a.x[i] = canonical((a.b[i] - sum) / a.diag[k]);
+    for (int rb = 0; rb < cnt; rb += rstep) {     // wave-uniform trip count
+      const int rr = rb + r0;
+      const bool active = rr < cnt;
+      const int k = start + rr;
+      T sum = T(0);
+      if (active)
+        sum = row_dot<T, false>(a.off_col, a.off_val, a.off_ptr[k] + gl, a.off_ptr[k + 1], G, a.x,
+                                0, a.status, T(0));
+      sum = group_sum(sum, lg);
+      if (active && gl == 0) {
+        const int i = a.pos_row[k];
+        a.x[i] = canonical((a.b[i] - sum) / a.diag[k]);
+      }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    if (i >= 0)
-      __hip_atomic_store(a.flags + i, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (gl == 0)
+      for (int rr = r0; rr < cnt; rr += rstep)
+        __hip_atomic_store(a.flags + a.pos_row[start + rr], epoch, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -282,7 +477,7 @@ template <typename T, bool kPoll>
 __device__ __forceinline__ void multi_rows(const KArgs<T>& a, int c, int lane) {
   const int start = a.chunk_start[c];
   const int meta = a.chunk_meta[c];
-  const int cnt = meta & 0xff, lg = meta >> 8;
+  const int cnt = meta & 0xffff, lg = meta >> 16;
   const int r = lane >> lg, q0 = lane & ((1 << lg) - 1);
   if (r >= cnt) return;
   const int k = start + r;
@@ -291,8 +486,8 @@ __device__ __forceinline__ void multi_rows(const KArgs<T>& a, int c, int lane) {
   const T d = a.diag[k];
   for (int q = q0; q < a.nrhs; q += (1 << lg)) {
     const size_t off = static_cast<size_t>(q) * a.ld;
-    const T sum = row_dot<T, kPoll>(a.off_col, a.off_val, e0, e1, 0, 1, a.x + off, a.spin_limit,
-                                    a.status);
+    const T sum = row_dot<T, kPoll>(a.off_col, a.off_val, e0, e1, 1, a.x + off, a.spin_limit,
+                                    a.status, T(0));
     const T xi = canonical((a.b[off + i] - sum) / d);
     if (kPoll) store_agent(a.x + off + i, xi);
     else a.x[off + i] = xi;
@@ -300,7 +495,7 @@ __device__ __forceinline__ void multi_rows(const KArgs<T>& a, int c, int lane) {
 }
 
 template <typename T>
-__global__ void __launch_bounds__(1024) k_level_multi(KArgs<T> a, int chunk_begin, int chunk_end) {
+__global__ void __launch_bounds__(256) k_level_multi(KArgs<T> a, int chunk_begin, int chunk_end) {
   const int lane = threadIdx.x & 63;
   const int c = wave_uniform(chunk_begin + static_cast<int>((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
   if (c >= chunk_end) return;
@@ -308,7 +503,7 @@ __global__ void __launch_bounds__(1024) k_level_multi(KArgs<T> a, int chunk_begi
 }
 
 template <typename T>
-__global__ void __launch_bounds__(1024) k_self_multi_value(KArgs<T> a) {
+__global__ void __launch_bounds__(256) k_self_multi_value(KArgs<T> a) {
   const int lane = threadIdx.x & 63;
   for (;;) {
     const int c = claim_chunk(a.ticket, a.nchunks, lane);
@@ -383,6 +578,8 @@ template <typename T> KArgs<T> make_args(const SolveArgs& s) {
   a.chunk_start = s.chunks->start;
   a.chunk_meta = s.chunks->meta;
   a.nchunks = s.chunks->count;
+  a.n = s.plan->n;
+  a.noff = s.plan->noff;
   a.off_ptr = s.plan->off_ptr;
   a.off_col = s.plan->off_col;
   a.off_val = static_cast<const T*>(s.plan->off_val);
@@ -448,6 +645,16 @@ template <typename T> hipError_t launch_self_value(const SolveArgs& sa, hipStrea
   return hipGetLastError();
 }
 
+template <typename T> hipError_t launch_self_static(const SolveArgs& sa, hipStream_t s) {
+  if (sa.chunks->count == 0) return hipSuccess;
+  KArgs<T> ka = make_args<T>(sa);
+  const int* cs = sa.chunks->start;
+  const int* cm = sa.chunks->meta;
+  void* args[] = {&ka, &cs, &cm};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_self_static<T>), dim3(sa.grid),
+                                    dim3(sa.wg), args, 0, s);
+}
+
 template <typename T> hipError_t launch_self_flag(const SolveArgs& sa, hipStream_t s) {
   if (sa.chunks->count == 0) return hipSuccess;
   k_self_flag<T><<<sa.grid, sa.wg, 0, s>>>(make_args<T>(sa));
@@ -487,6 +694,12 @@ template <typename T> int self_flag_blocks_per_cu(int wg) {
     return 1;
   return nb > 0 ? nb : 1;
 }
+template <typename T> int self_static_blocks_per_cu(int wg) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_self_static<T>, wg, 0) != hipSuccess)
+    return 1;
+  return nb > 0 ? nb : 1;
+}
 template <typename T> int self_multi_blocks_per_cu(int wg) {
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_self_multi_value<T>, wg, 0) != hipSuccess)
@@ -501,6 +714,8 @@ template <typename T> int self_multi_blocks_per_cu(int wg) {
   template hipError_t launch_level_multi<T>(const SolveArgs&, int, int, hipStream_t);           \
   template hipError_t launch_self_value<T>(const SolveArgs&, hipStream_t);                      \
   template hipError_t launch_self_flag<T>(const SolveArgs&, hipStream_t);                       \
+  template hipError_t launch_self_static<T>(const SolveArgs&, hipStream_t);                     \
+  template int self_static_blocks_per_cu<T>(int);                                               \
   template hipError_t launch_self_multi_value<T>(const SolveArgs&, hipStream_t);                \
   template hipError_t launch_grad_vals<T>(int, const int*, const int*, int, const T*, const T*, \
                                           T*, hipStream_t);                                     \

@@ -61,6 +61,8 @@ template <typename T> hipError_t launch_level(const SolveArgs& a, int chunk_begi
                                               hipStream_t s);
 template <typename T> hipError_t launch_self_value(const SolveArgs& a, hipStream_t s);
 template <typename T> hipError_t launch_self_flag(const SolveArgs& a, hipStream_t s);
+// value sync, static round-robin chunks, cooperative launch (all resident)
+template <typename T> hipError_t launch_self_static(const SolveArgs& a, hipStream_t s);
 template <typename T> hipError_t launch_level_multi(const SolveArgs& a, int chunk_begin,
                                                     int chunk_end, hipStream_t s);
 template <typename T> hipError_t launch_self_multi_value(const SolveArgs& a, hipStream_t s);
@@ -74,5 +76,6 @@ hipError_t launch_init_scratch(DevScratch sc, int n, hipStream_t s);
 template <typename T> int self_value_blocks_per_cu(int wg);
 template <typename T> int self_flag_blocks_per_cu(int wg);
 template <typename T> int self_multi_blocks_per_cu(int wg);
+template <typename T> int self_static_blocks_per_cu(int wg);
 
 }  // namespace sptrsv

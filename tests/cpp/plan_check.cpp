@@ -9,7 +9,7 @@
 using namespace sptrsv;
 
 extern "C" int check_plan(int n, const int* rp, const int* col, int upper, int unit, int group,
-                          int epl, int rows_fixed) {
+                          int epl, int rows_fixed, int rows_per_lane) {
   HostPlan p;
   build_plan(n, rp, col, nullptr, upper != 0, unit != 0, p);
   // 1: pos_row is a permutation and every level holds the canonical rows
@@ -41,13 +41,15 @@ extern "C" int check_plan(int n, const int* rp, const int* col, int upper, int u
   }
   // 3: chunks tile the positions in order, one level each, <= 64 lanes
   ChunkTable t;
-  build_chunks(p, group, epl, rows_fixed, t);
+  build_chunks(p, group, epl, rows_fixed, rows_per_lane, t);
   if ((int)t.level_chunk.size() != p.nlev + 1) return 10;
   int next = 0;
   for (int m = 0; m < p.nlev; ++m) {
     for (int c = t.level_chunk[m]; c < t.level_chunk[m + 1]; ++c) {
-      const int cnt = t.meta[c] & 0xff, lg = t.meta[c] >> 8;
-      if (t.start[c] != next || cnt < 1 || lg < 0 || lg > 6 || (cnt << lg) > 64) return 11;
+      const int cnt = t.meta[c] & 0xffff, lg = t.meta[c] >> 16;
+      const int cap = (lg == 0 && rows_fixed <= 0) ? 64 * rows_per_lane : 64;
+      if (t.start[c] != next || cnt < 1 || lg < 0 || lg > 6 || (cnt << lg) > cap) return 11;
+      if (rows_per_lane > kMaxRowsPerLane) return 16;
       if (t.start[c] < p.pos_ilev[m] || t.start[c] + cnt > p.pos_ilev[m + 1]) return 12;
       if (group > 0 && (1 << lg) != group) return 13;
       if (rows_fixed > 0 && (64 >> lg) != rows_fixed) return 14;

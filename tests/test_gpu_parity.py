@@ -41,10 +41,17 @@ def _small_cases():
 
 CASES = _small_cases()
 SCHEDULES = [("level", dict(algo=1)), ("self_value", dict(algo=2, sync=0)),
+             ("self_ticket", dict(algo=2, sync=0, assign=1)),
+             ("self_static_g4_grid3", dict(algo=2, sync=0, assign=0, group=4, grid=3)),
+             ("self_static_wg256", dict(algo=2, sync=0, assign=0, wg=256, grid=2)),
              ("self_flag", dict(algo=2, sync=1)), ("self_value_g1", dict(algo=2, group=1)),
              ("self_value_g8", dict(algo=2, group=8)), ("level_g64", dict(algo=1, group=64)),
              ("self_flag_g16", dict(algo=2, sync=1, group=16)),
-             ("self_value_epl1", dict(algo=2, entries_per_lane=1))]
+             ("self_value_epl1", dict(algo=2, entries_per_lane=1)),
+             ("self_value_rpl1_grid8", dict(algo=2, rows_per_lane=1, grid=8)),
+             ("level_rpl2", dict(algo=1, rows_per_lane=2, group=1)),
+             ("self_flag_rpl3_wg256", dict(algo=2, sync=1, rows_per_lane=3, wg=256, grid=4)),
+             ("self_value_wg256_grid1", dict(algo=2, wg=256, grid=1))]
 
 
 @pytest.mark.parametrize("name,T", CASES, ids=[c[0] for c in CASES])
@@ -98,16 +105,20 @@ def test_solve_fp32(sp, name, T):
         assert relerr(host(x), xo) <= TOL32, opts
 
 
-@pytest.mark.parametrize("group", [1, 4, 16, 64])
+@pytest.mark.parametrize("group,rpl", [(1, 1), (1, 4), (0, 4), (4, 1), (16, 1), (64, 1)])
 @pytest.mark.parametrize("name,T", [CASES[1], CASES[4], CASES[6]], ids=[CASES[1][0], CASES[4][0], CASES[6][0]])
-def test_level_equals_self_bitwise(sp, name, T, group):
+def test_level_equals_self_bitwise(sp, name, T, group, rpl):
     """Same per-row arithmetic under every schedule: results must be
     bit-identical, on every one of repeated solves."""
     b = dev(W.uniform_vector(T.n, 11))
-    hl = sp.Handle(*dev_tri(T), uplo="U" if T.upper else "L").configure(algo=1, group=group)
+    hl = sp.Handle(*dev_tri(T), uplo="U" if T.upper else "L").configure(algo=1, group=group,
+                                                                        rows_per_lane=rpl)
     ref = hl.solve(b)
-    for sync in (0, 1):
-        hs = sp.Handle(*dev_tri(T), uplo="U" if T.upper else "L").configure(algo=2, group=group, sync=sync)
+    for sync, assign in ((0, 0), (0, 1), (1, 1)):
+        if assign == 0 and rpl != 1:
+            continue                  # static assignment keeps one row per lane
+        hs = sp.Handle(*dev_tri(T), uplo="U" if T.upper else "L").configure(
+            algo=2, group=group, sync=sync, rows_per_lane=rpl, assign=assign)
         for _ in range(20):
             assert bits_equal(hs.solve(b), ref)
         hs.status()
@@ -128,7 +139,8 @@ def test_in_place(sp, opts):
     assert relerr(host(y), o.solve_transpose(T.row_ptr, T.col_idx, T.vals, b)) <= TOL64
 
 
-@pytest.mark.parametrize("opts", [dict(algo=1), dict(algo=2, sync=0), dict(algo=2, sync=1)])
+@pytest.mark.parametrize("opts", [dict(algo=1), dict(algo=2, sync=0), dict(algo=2, sync=1),
+                                  dict(algo=2, sync=0, assign=1)])
 def test_exact_cases(sp, opts):
     """Diagonal: x = b/d; chain I - S (nlev = n): prefix sums of
     integers; bidiagonal (2, -1) with b = e_0: x_i = 2^-(i+1).  Bit-exact."""
@@ -270,15 +282,15 @@ def test_empty_and_single(sp):
         assert host(h.solve(dev(np.array([2.0]))))[0] == 0.5
 
 
-@pytest.mark.parametrize("sync", [0, 1])
-def test_watchdog_timeout_is_reported_and_recovers(sp, sync):
+@pytest.mark.parametrize("sync,assign", [(0, 0), (0, 1), (1, 1)])
+def test_watchdog_timeout_is_reported_and_recovers(sp, sync, assign):
     """A spin limit of one poll (forced from the host) makes waits give up:
     the kernel drains, TIMEOUT is reported; with the default limit the same
     handle solves correctly again."""
     n = 20000
     P = W.bidiagonal_fast(n, 1.0, 1.0)
     b = np.ones(n)
-    h = sp.Handle(*dev_tri(P)).configure(algo=2, sync=sync, spin_limit=1)
+    h = sp.Handle(*dev_tri(P)).configure(algo=2, sync=sync, assign=assign, spin_limit=1)
     h.solve(dev(b))
     with pytest.raises(sp.SpTRSVError) as e:
         h.status()

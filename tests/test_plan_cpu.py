@@ -22,7 +22,7 @@ def checker(tmp_path_factory):
     lib = ctypes.CDLL(str(out))
     P = ctypes.POINTER(ctypes.c_int32)
     lib.check_plan.argtypes = [ctypes.c_int, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                               ctypes.c_int, ctypes.c_int]
+                               ctypes.c_int, ctypes.c_int, ctypes.c_int]
     return lib
 
 
@@ -35,8 +35,9 @@ def _tris():
 
 
 @pytest.mark.parametrize("T", _tris(), ids=lambda t: t.name)
-@pytest.mark.parametrize("policy", [(0, 1, 0), (0, 4, 0), (0, 8, 0), (1, 4, 0), (4, 4, 0),
-                                    (64, 4, 0), (0, 4, 4), (0, 4, 1), (0, 4, 64)])
+@pytest.mark.parametrize("policy", [(0, 1, 0, 1), (0, 4, 0, 4), (0, 8, 0, 2), (1, 4, 0, 1),
+                                    (1, 4, 0, 4), (1, 1, 0, 3), (4, 4, 0, 4), (64, 4, 0, 4),
+                                    (0, 4, 4, 4), (0, 4, 1, 1), (0, 4, 64, 2)])
 def test_plan_and_chunks(checker, T, policy):
     rp = np.ascontiguousarray(T.row_ptr, np.int32)
     ci = np.ascontiguousarray(T.col_idx, np.int32)
