@@ -46,8 +46,34 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--epl", type=int, default=None, help="fixed entries per lane (with --no-tune)")
+    ap.add_argument("--grid", type=int, default=None, help="fixed persistent grid (with --no-tune)")
+    ap.add_argument("--assign", type=int, default=None, help="fixed chunk assignment (with --no-tune)")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="also run a plain device copy of this size (counter calibration)")
     ap.add_argument("--suite", action="store_true")
     return ap.parse_args()
+
+
+def committed_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None if it covers another kernel or kernels.hip changed since."""
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(root, "profiles", "k_self_static_lap3d128_hbm_counters.md")
+    try:
+        rec = None
+        with open(path) as f:
+            for line in f:
+                if line.startswith("traffic_json:"):
+                    rec = json.loads(line.split(":", 1)[1])
+        src = os.path.join(root, "paper_1710_04985_amd", "csrc", "kernels.hip")
+        h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("kernels_hip_sha256_16") != h or rec.get("kernel") != kernel:
+        return None
+    return rec["bytes_per_launch"]
 
 
 def cpu_info():
@@ -122,8 +148,15 @@ def main():
                 h.set_option("algo", sp.ALGO_SELF)
             tuned[name] = h.tune(b)
     else:
-        hL.set_option("algo", sp.ALGO_SELF)
-        hU.set_option("algo", sp.ALGO_SELF)
+        for h in (hL, hU):
+            h.set_option("algo", sp.ALGO_SELF)
+            if args.epl is not None:
+                h.set_option("entries_per_lane", args.epl)
+            if args.grid is not None:
+                h.set_option("grid", args.grid)
+            if args.assign is not None:
+                h.set_option("assign", args.assign)
+        tuned = {"L": hL.info(), "U": hU.info()}
 
     def step(hl, hu, out1, out2):
         hl.solve(b, out=out1)
@@ -177,6 +210,13 @@ def main():
         h.set_option("timing", 0)
     kernel_ms = (kmsL + kmsU) / max(1, kcL + kcU)
 
+    infoL = hL.info()
+    if infoL["sync"] == sp.SYNC_FLAG:
+        kernel_name = "k_self_flag<double>"
+    elif infoL["assign"] == sp.ASSIGN_STATIC:
+        kernel_name = "k_self_static<double,false>"
+    else:
+        kernel_name = "k_self_value<double>"
     lbL = lb_bytes(TL.n, TL.nnz)
     lbU = lb_bytes(TU.n, TU.nnz)
     step_bytes = lbL + lbU
@@ -208,9 +248,9 @@ def main():
         "analysis_ms": round(analysis_ms, 2),
         "bytes_per_step": step_bytes,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
-                     "kernel": "k_self_flag<double>" if hL.info()["sync"] == sp.SYNC_FLAG
-                     else "k_self_value<double>",
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+                     "traffic": committed_traffic(kernel_name),
+                     "kernel": kernel_name,
                      "kernel_ms": round(kernel_ms, 5), "bytes_per_launch": lbL},
     }
     if not args.no_cpu_baseline:
@@ -220,6 +260,18 @@ def main():
                                "cores": 1, "kind": "oracle",
                                "sample": "%d full L+U steps of the same workload (%.1f ms each) on %s, "
                                          "%d host CPUs visible" % (reps, t_cpu * 1e3, model, ncpu)}
+    if args.copy_probe_mb:
+        nbytes = args.copy_probe_mb << 20
+        src = torch.empty(nbytes // 8, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = nbytes
+    if args.suite:
+        import bench_suite
+        bench_suite.run(sp, torch, out_path=os.path.join("gpurun_out", "bench_suite.jsonl"))
     print(json.dumps(out), flush=True)
 
 

@@ -1,0 +1,234 @@
+"""Per-configuration measurements (bench.py --suite).
+
+For each workload: parity of the level- and self-scheduled solves against
+the oracle at full size, then the mean time of repeated solves of each
+(warm, inputs resident in HBM), effective GB/s over the bytes lower bound,
+and the self-over-level speedup.  One JSON line per workload goes to the
+output file; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import json
+import sys
+import time
+
+import numpy as np
+
+import oracle
+import workloads as W
+
+DEV = "cuda:0"
+
+
+def lb_bytes(n, nnz, vb=8, k=1):
+    return nnz * (vb + 4) + (n + 1) * 4 + 3 * n * vb * k
+
+
+def _log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _relerr(x, ref):
+    return float(np.abs(np.asarray(x, np.float64) - ref).max() / max(np.abs(ref).max(), 1e-300))
+
+
+def _time(torch, fn, reps, warm=3):
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def _tri(torch, T, dtype=None):
+    dtype = dtype or torch.float64
+    return (torch.from_numpy(T.row_ptr).to(DEV), torch.from_numpy(T.col_idx).to(DEV),
+            torch.from_numpy(T.vals).to(DEV).to(dtype))
+
+
+def _single(sp, torch, name, T, b, reps, dtype=None, tol=1e-12):
+    """Level vs self on one triangle with one right-hand side."""
+    dtype = dtype or torch.float64
+    o = oracle.get()
+    vals64 = T.vals if dtype == torch.float64 else T.vals.astype(np.float32).astype(np.float64)
+    b64 = b if dtype == torch.float64 else b.astype(np.float32).astype(np.float64)
+    xo = o.solve(T.row_ptr, T.col_idx, vals64, b64, T.upper)
+    d = _tri(torch, T, dtype)
+    bd = torch.from_numpy(b).to(DEV).to(dtype)
+    x = torch.empty_like(bd)
+    uplo = "U" if T.upper else "L"
+    res = {"config": name, "n": T.n, "nnz": T.nnz, "dtype": "f64" if dtype == torch.float64 else "f32"}
+    t0 = time.perf_counter()
+    hs = sp.Handle(*d, uplo=uplo)
+    res["analysis_ms"] = round((time.perf_counter() - t0) * 1e3, 2)
+    res["nlev"] = hs.info()["nlev"]
+    hl = sp.Handle(*d, uplo=uplo).configure(algo=sp.ALGO_LEVEL)
+    hs.set_option("algo", sp.ALGO_SELF)
+    res["tuned_self"] = hs.tune(bd, x)
+    res["tuned_level"] = hl.tune(bd, x)
+    hb = sp.Handle(*d, uplo=uplo).configure(algo=sp.ALGO_BLOCK)
+    for tag, h in (("self", hs), ("level", hl), ("block", hb)):
+        h.solve(bd, out=x)
+        h.status()
+        err = _relerr(x.cpu().numpy(), xo)
+        res["rel_err_" + tag] = float("%.3e" % err)
+        if err > tol:
+            res["parity"] = "FAIL"
+        res[tag + "_ms"] = round(_time(torch, lambda: h.solve(bd, out=x), reps), 5)
+    vb = 8 if dtype == torch.float64 else 4
+    lb = lb_bytes(T.n, T.nnz, vb)
+    res["lb_bytes"] = lb
+    res["gbs_self"] = round(lb / (res["self_ms"] * 1e-3) / 1e9, 3)
+    res["gbs_level"] = round(lb / (res["level_ms"] * 1e-3) / 1e9, 3)
+    res["gbs_block"] = round(lb / (res["block_ms"] * 1e-3) / 1e9, 3)
+    res["solves_per_s_self"] = round(1e3 / res["self_ms"], 2)
+    res["speedup_self_vs_level"] = round(res["level_ms"] / res["self_ms"], 3)
+    res.setdefault("parity", "ok")
+    return res
+
+
+def _batched(sp, torch, reps):
+    o = oracle.get()
+    tris, xs, bs = W.c4a_batch()
+    devs = [_tri(torch, t) for t in tris]
+    bcat = np.concatenate(bs)
+    bd = torch.from_numpy(bcat).to(DEV)
+    x = torch.empty_like(bd)
+    n = sum(t.n for t in tris)
+    nnz = sum(t.nnz for t in tris)
+    res = {"config": "c4a_batched_256_ilu0_2d", "n": n, "nnz": nnz, "systems": len(tris),
+           "dtype": "f64"}
+    t0 = time.perf_counter()
+    hs = sp.BatchedHandle([d[0] for d in devs], [d[1] for d in devs], [d[2] for d in devs])
+    res["analysis_ms"] = round((time.perf_counter() - t0) * 1e3, 2)
+    res["nlev"] = hs.info()["nlev"]
+    hl = sp.BatchedHandle([d[0] for d in devs], [d[1] for d in devs], [d[2] for d in devs])
+    hl.set_option("algo", sp.ALGO_LEVEL)
+    hs.set_option("algo", sp.ALGO_SELF)
+    hb = sp.BatchedHandle([d[0] for d in devs], [d[1] for d in devs], [d[2] for d in devs])
+    hb.set_option("algo", sp.ALGO_BLOCK)
+    res["tuned_self"] = hs.tune(bd, x)
+    res["tuned_level"] = hl.tune(bd, x)
+    xo = np.concatenate([o.solve(t.row_ptr, t.col_idx, t.vals, b) for t, b in zip(tris, bs)])
+    for tag, h in (("self", hs), ("level", hl), ("block", hb)):
+        h.solve(bd, out=x)
+        h.status()
+        res["rel_err_" + tag] = float("%.3e" % _relerr(x.cpu().numpy(), xo))
+        res[tag + "_ms"] = round(_time(torch, lambda: h.solve(bd, out=x), reps), 5)
+    # one HIP graph per solve, replayed
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        for tag, h in (("self", hs), ("level", hl), ("block", hb)):
+            g = h.capture(bd, x, stream=s)
+            g.launch(s)
+            s.synchronize()
+            res["rel_err_graph_" + tag] = float("%.3e" % _relerr(x.cpu().numpy(), xo))
+            res["graph_" + tag + "_ms"] = round(_time(torch, lambda: g.launch(s), reps), 5)
+            g.close()
+    lb = lb_bytes(n, nnz)
+    res["lb_bytes"] = lb
+    res["gbs_self"] = round(lb / (res["self_ms"] * 1e-3) / 1e9, 3)
+    res["gbs_level"] = round(lb / (res["level_ms"] * 1e-3) / 1e9, 3)
+    res["speedup_self_vs_level"] = round(res["level_ms"] / res["self_ms"], 3)
+    res["gbs_block"] = round(lb / (res["block_ms"] * 1e-3) / 1e9, 3)
+    res["parity"] = "ok" if max(v for k, v in res.items() if k.startswith("rel_err")) <= 1e-12 else "FAIL"
+    return res
+
+
+def _multi(sp, torch, reps, nrhs=16):
+    o = oracle.get()
+    T, X, B = W.c4b_multi(nrhs=nrhs)
+    d = _tri(torch, T)
+    Bd = torch.from_numpy(np.ascontiguousarray(B.T)).to(DEV)        # (nrhs, n): column-major n x nrhs
+    Xd = torch.empty_like(Bd)
+    res = {"config": "c4b_lap3d_128_lower_%drhs" % nrhs, "n": T.n, "nnz": T.nnz, "nrhs": nrhs,
+           "dtype": "f64"}
+    hs = sp.Handle(*d).configure(algo=sp.ALGO_SELF)
+    hl = sp.Handle(*d).configure(algo=sp.ALGO_LEVEL)
+    res["nlev"] = hs.info()["nlev"]
+    Xo = o.solve_multi(T.row_ptr, T.col_idx, T.vals, B)
+    for tag, h in (("self", hs), ("level", hl)):
+        h.solve_multi(Bd, out=Xd)
+        h.status()
+        res["rel_err_" + tag] = float("%.3e" % _relerr(Xd.cpu().numpy().T, Xo))
+        res[tag + "_ms"] = round(_time(torch, lambda: h.solve_multi(Bd, out=Xd), reps), 5)
+    lb = lb_bytes(T.n, T.nnz, 8, nrhs)
+    res["lb_bytes"] = lb
+    res["gbs_self"] = round(lb / (res["self_ms"] * 1e-3) / 1e9, 3)
+    res["gbs_level"] = round(lb / (res["level_ms"] * 1e-3) / 1e9, 3)
+    res["rhs_solves_per_s_self"] = round(nrhs * 1e3 / res["self_ms"], 2)
+    res["speedup_self_vs_level"] = round(res["level_ms"] / res["self_ms"], 3)
+    res["parity"] = "ok" if max(res["rel_err_self"], res["rel_err_level"]) <= 1e-12 else "FAIL"
+    return res
+
+
+def _adjoint(sp, torch, reps, side=96):
+    o = oracle.get()
+    T, b, w = W.c5_ilu3d(side=side)
+    d = _tri(torch, T)
+    res = {"config": "c5_ilu0_3d_%d_fwd_adjoint" % side, "n": T.n, "nnz": T.nnz, "dtype": "f64"}
+    xo, gbo, gvo = o.adjoint(T.row_ptr, T.col_idx, T.vals, b, w)
+    wd = torch.from_numpy(w).to(DEV)
+    bd0 = torch.from_numpy(b).to(DEV)
+    for tag, algo in (("self", sp.ALGO_SELF), ("level", sp.ALGO_LEVEL)):
+        h = sp.Handle(*d).configure(algo=algo)
+        h.prepare_transpose()
+        res["nlev"] = h.info()["nlev"]
+        vals = d[2].clone().requires_grad_(True)
+        bd = bd0.clone().requires_grad_(True)
+
+        def step():
+            vals.grad = None
+            bd.grad = None
+            x = sp.sptrsv(vals, bd, h)
+            x.backward(wd)
+            return x
+
+        x = step()
+        h.status()
+        err = max(_relerr(x.detach().cpu().numpy(), xo), _relerr(bd.grad.cpu().numpy(), gbo),
+                  _relerr(vals.grad.cpu().numpy(), gvo))
+        res["rel_err_" + tag] = float("%.3e" % err)
+        res[tag + "_ms"] = round(_time(torch, step, reps), 5)
+    # forward + adjoint traffic: value gather (read vals, write copy), forward
+    # solve, transposed solve, gradient on the pattern (row_ptr, col, x gather,
+    # grad_b, grad_vals)
+    lb_solve = lb_bytes(T.n, T.nnz)
+    gather = T.nnz * 8 * 2 + T.nnz * 4
+    grad = (T.n + 1) * 4 + T.nnz * 4 + T.n * 8 * 2 + T.nnz * 8
+    lb = 2 * lb_solve + gather + grad
+    res["lb_bytes"] = lb
+    res["gbs_self"] = round(lb / (res["self_ms"] * 1e-3) / 1e9, 3)
+    res["gbs_level"] = round(lb / (res["level_ms"] * 1e-3) / 1e9, 3)
+    res["speedup_self_vs_level"] = round(res["level_ms"] / res["self_ms"], 3)
+    res["parity"] = "ok" if max(res["rel_err_self"], res["rel_err_level"]) <= 1e-12 else "FAIL"
+    return res
+
+
+def run(sp, torch, out_path, reps=20):
+    lines = []
+
+    def emit(r):
+        lines.append(r)
+        _log(json.dumps(r))
+        with open(out_path, "a") as f:
+            f.write(json.dumps(r) + "\n")
+
+    T, xs, b = W.c1_lap2d_64()
+    emit(_single(sp, torch, "c1_lap2d_64_lower", T, b, reps))
+    for upper in (False, True):
+        T, xs, b = W.c2_lap3d(upper=upper)
+        emit(_single(sp, torch, "c2_lap3d_128_" + ("upper" if upper else "lower"), T, b, reps))
+    T, xs, b = W.c3_powerlaw()
+    emit(_single(sp, torch, "c3_powerlaw_1M_f64", T, b, reps))
+    emit(_single(sp, torch, "c3_powerlaw_1M_f32", T, b, reps, dtype=torch.float32, tol=1e-5))
+    emit(_batched(sp, torch, reps))
+    emit(_multi(sp, torch, reps))
+    emit(_adjoint(sp, torch, reps))
+    return lines

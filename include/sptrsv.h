@@ -70,8 +70,11 @@ typedef enum {
     SPTRSV_ALGO_LEVEL = 1,  /* level-scheduled: one launch per level (Sec. 4.1) */
     SPTRSV_ALGO_SELF = 2,   /* self-scheduled: one persistent launch (Sec. 4.2) */
     SPTRSV_ALGO_BLOCK = 3   /* level-scheduled inside one workgroup per independent
-                               system (block-diagonal batches, small n): the level
-                               barrier is a workgroup barrier, not a launch */
+                               system (each system of a batched handle; the whole
+                               triangle otherwise): the level barrier is a workgroup
+                               barrier, not a launch; x of a system is kept in LDS when
+                               the largest system fits.  One right-hand side (several:
+                               the level-scheduled solve is used). */
 } sptrsv_algo;
 
 typedef enum {
@@ -101,7 +104,7 @@ typedef enum {
 typedef enum {
     SPTRSV_ASSIGN_STATIC = 0,     /* chunk c goes to wavefront c mod W of a cooperatively
                                      launched (all-resident) grid, pipelined four chunks
-                                     deep; value sync, one right-hand side.  Under HIP graph
+                                     deep; value sync, one or several right-hand sides.  Under HIP graph
                                      capture the ticket form is used instead. */
     SPTRSV_ASSIGN_TICKET = 1      /* wavefronts claim chunks from an atomic ticket: needs no
                                      co-residency, costs one serialised atomic per chunk */

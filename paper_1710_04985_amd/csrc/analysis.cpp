@@ -200,6 +200,81 @@ void build_chunks(const HostPlan& p, int group, int entries_per_lane, int rows_f
   t.level_chunk[p.nlev] = static_cast<int>(t.start.size());
 }
 
+void reorder_plan(const HostPlan& f, const std::vector<int>& order, HostPlan& o) {
+  o = HostPlan();
+  o.n = f.n;
+  o.nlev = f.nlev;
+  o.nnz = f.nnz;
+  o.noff = f.noff;
+  o.upper = f.upper;
+  o.unit_diag = f.unit_diag;
+  o.level = f.level;
+  o.ilev = f.ilev;
+  o.jlev = f.jlev;
+  o.depcnt = f.depcnt;
+  o.max_row_len = f.max_row_len;
+  o.pos_ilev = f.pos_ilev;   // only meaningful when order keeps levels in place
+  const int n = f.n;
+  o.pos_row.resize(n);
+  o.off_ptr.assign(n + 1, 0);
+  o.diag_src.assign(n, -1);
+  for (int t = 0; t < n; ++t) {
+    const int k = order[t];
+    o.pos_row[t] = f.pos_row[k];
+    o.off_ptr[t + 1] = o.off_ptr[t] + (f.off_ptr[k + 1] - f.off_ptr[k]);
+    if (f.diag_src[k] >= 0) o.diag_src[t] = static_cast<int>(f.noff) + k;
+  }
+  o.off_col.resize(o.noff);
+  o.off_src.resize(o.noff);
+  for (int t = 0; t < n; ++t) {
+    const int k = order[t];
+    int d = o.off_ptr[t];
+    for (int e = f.off_ptr[k]; e < f.off_ptr[k + 1]; ++e, ++d) {
+      o.off_col[d] = f.off_col[e];
+      o.off_src[d] = e;
+    }
+  }
+}
+
+void build_block_plan(const HostPlan& f, const std::vector<int>& seg_row0, HostPlan& out,
+                      BlockInfo& info) {
+  const int n = f.n;
+  const int nseg = static_cast<int>(seg_row0.size()) - 1;
+  std::vector<int> seg_of(n);
+  for (int s = 0; s < nseg; ++s)
+    for (int i = seg_row0[s]; i < seg_row0[s + 1]; ++i) seg_of[i] = s;
+  // stable counting sort of f's positions by system
+  std::vector<int> cnt(nseg + 1, 0);
+  for (int k = 0; k < n; ++k) cnt[seg_of[f.pos_row[k]] + 1]++;
+  for (int s = 0; s < nseg; ++s) cnt[s + 1] += cnt[s];
+  std::vector<int> order(n);
+  {
+    std::vector<int> fill(cnt.begin(), cnt.end() - 1);
+    for (int k = 0; k < n; ++k) order[fill[seg_of[f.pos_row[k]]]++] = k;
+  }
+  reorder_plan(f, order, out);
+  // level bounds per system (levels are consecutive runs inside a system)
+  info = BlockInfo();
+  info.seg_row0 = seg_row0;
+  info.seg_base.assign(nseg + 1, 0);
+  for (int s = 0; s < nseg; ++s) {
+    const int a = cnt[s], b = cnt[s + 1];
+    info.max_rows = std::max(info.max_rows, b - a);
+    info.seg_base[s] = static_cast<int>(info.lev_pos.size());
+    if (a == b) continue;
+    int run = a;
+    info.lev_pos.push_back(a);
+    for (int t = a + 1; t <= b; ++t) {
+      if (t == b || f.level[out.pos_row[t]] != f.level[out.pos_row[t - 1]]) {
+        info.lev_pos.push_back(t);
+        info.max_level = std::max(info.max_level, t - run);
+        run = t;
+      }
+    }
+  }
+  info.seg_base[nseg] = static_cast<int>(info.lev_pos.size());
+}
+
 uint64_t pattern_hash(int n, const int* row_ptr, const int* col, bool upper, bool unit_diag) {
   uint64_t h = 1469598103934665603ull;
   auto mix = [&](uint64_t v) {

@@ -94,6 +94,23 @@ struct ChunkTable {
 void build_chunks(const HostPlan& plan, int group, int entries_per_lane, int rows_fixed,
                   int rows_per_lane, ChunkTable& out);
 
+// Plan whose positions are those of `f` in the order given by `order` (new
+// position t holds f's position order[t]); its value sources index f's value
+// buffer (off-diagonals of f, then f's diagonal).
+void reorder_plan(const HostPlan& f, const std::vector<int>& order, HostPlan& out);
+
+// Block order for independent systems (block-diagonal triangles): rows of
+// system s are seg_row0[s] .. seg_row0[s+1]-1.  Positions are sorted by
+// (system, level, f's order inside the level); system s has its levels'
+// position bounds at lev_pos[seg_base[s] .. seg_base[s+1]-1].
+struct BlockInfo {
+  std::vector<int> seg_row0, seg_base, lev_pos;
+  int max_rows = 0;        // rows of the largest system
+  int max_level = 0;       // rows of the largest level of any system
+};
+void build_block_plan(const HostPlan& f, const std::vector<int>& seg_row0, HostPlan& out,
+                      BlockInfo& info);
+
 // 64-bit FNV-1a hash of a pattern (autotuner cache key).
 uint64_t pattern_hash(int n, const int* row_ptr, const int* col, bool upper, bool unit_diag);
 

@@ -37,6 +37,17 @@ struct PlanState {
   std::map<std::tuple<int, int, int, int>, ChunkEntry> chunks;
 };
 
+// Block-ordered plan (SPTRSV_ALGO_BLOCK) of one direction, on the device.
+struct BlockState {
+  bool built = false;
+  PlanState ps;
+  BlockInfo info;
+  int* seg_row0 = nullptr;
+  int* seg_base = nullptr;
+  int* lev_pos = nullptr;
+  ChunkEntry dummy;   // unused chunk table (the block kernel needs none)
+};
+
 struct Config {
   int algo;
   int group;
@@ -61,8 +72,10 @@ struct sptrsv_handle_s {
   size_t vb = 8;
   int device = 0;
   int num_cu = 256;
+  int lds_limit = 65536;          // bytes of LDS one workgroup may use
   std::vector<int> rp_h, col_h;   // caller's pattern (host copy)
   PlanState fwd, trn;
+  BlockState blk[2];               // block-ordered plans of T and T^T
   DevScratch scratch;
   void* tmp = nullptr;            // copy of b for in-place value-sync solves
   size_t tmp_bytes = 0;
@@ -221,6 +234,30 @@ int build_transpose(sptrsv_handle_t h, hipStream_t s) {
   return kOk;
 }
 
+// Builds the block-ordered plan of direction `dir` (0: T, 1: T^T): one
+// segment per system of a batched handle, else one; values are gathered from
+// the direction's level-ordered plan.  Blocking (uploads synchronously).
+int build_block(sptrsv_handle_t h, int dir, hipStream_t s) {
+  BlockState& b = h->blk[dir];
+  if (b.built) return kOk;
+  PlanState& base = dir ? h->trn : h->fwd;
+  std::vector<int> seg_row0(1, 0);
+  if (h->batched)
+    for (int ni : h->sys_n) seg_row0.push_back(seg_row0.back() + ni);
+  else
+    seg_row0.push_back(h->n);
+  build_block_plan(base.h, seg_row0, b.ps.h, b.info);
+  int st = upload_plan(b.ps, h->vb, s);
+  if (st) return st;
+  if ((st = upload_ints(&b.seg_row0, b.info.seg_row0, s))) return st;
+  if ((st = upload_ints(&b.seg_base, b.info.seg_base, s))) return st;
+  if ((st = upload_ints(&b.lev_pos, b.info.lev_pos, s))) return st;
+  if ((st = gather(h, b.ps, base.vals_buf, s))) return st;
+  HIPCHK(hipStreamSynchronize(s));
+  b.built = true;
+  return kOk;
+}
+
 ChunkEntry* get_chunks(sptrsv_handle_t h, PlanState& ps, int group, int epl, int rows_fixed,
                        int rpl, int* err) {
   (void)h;
@@ -346,7 +383,8 @@ int solve_impl(sptrsv_handle_t h, PlanState& ps, const Config& c, const void* b,
   // static assignment keeps one row per lane (its pipeline holds one row)
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &cap) != hipSuccess) return kErrHip;
-  const bool use_static = !multi && c.algo == SPTRSV_ALGO_SELF && c.sync == SPTRSV_SYNC_VALUE &&
+  const bool use_static = c.algo == SPTRSV_ALGO_SELF &&
+                          (multi || c.sync == SPTRSV_SYNC_VALUE) &&
                           c.assign == SPTRSV_ASSIGN_STATIC && cap == hipStreamCaptureStatusNone;
   ChunkEntry* ch = multi ? get_chunks(h, ps, 0, 0, 64 / kl, 1, &err)
                          : get_chunks(h, ps, c.group, c.epl, 0, use_static ? 1 : c.rpl, &err);
@@ -362,7 +400,24 @@ int solve_impl(sptrsv_handle_t h, PlanState& ps, const Config& c, const void* b,
   a.spin_limit = h->spin_limit;
   a.wg = h->wg;
   hipEvent_t stop;
-  if (c.algo == SPTRSV_ALGO_LEVEL) {
+  if (c.algo == SPTRSV_ALGO_BLOCK && !multi) {
+    const int dir = (&ps == &h->trn) ? 1 : 0;
+    BlockState& bs = h->blk[dir];
+    if (!bs.built) return kErrInvalidArg;   // built by solve_dispatch / capture
+    a.plan = &bs.ps.d;
+    int threads = 64;
+    while (threads < bs.info.max_level && threads < 1024) threads <<= 1;
+    const size_t lds_bytes = static_cast<size_t>(bs.info.max_rows) * sizeof(T);
+    const int lds_rows = lds_bytes <= static_cast<size_t>(h->lds_limit) ? bs.info.max_rows : 0;
+    const int nseg = static_cast<int>(bs.info.seg_row0.size()) - 1;
+    timing_begin(h, s, &stop);
+    if (launch_block<T>(a, bs.seg_row0, bs.seg_base, bs.lev_pos, nseg, threads, lds_rows, s) !=
+        hipSuccess)
+      return kErrHip;
+    timing_end(s, stop);
+    return kOk;
+  }
+  if (c.algo == SPTRSV_ALGO_LEVEL || c.algo == SPTRSV_ALGO_BLOCK) {
     timing_begin(h, s, &stop);
     for (int m = 0; m < ps.h.nlev; ++m) {
       const int cb = ch->level_chunk[m], ce = ch->level_chunk[m + 1];
@@ -390,10 +445,10 @@ int solve_impl(sptrsv_handle_t h, PlanState& ps, const Config& c, const void* b,
   }
   if (launch_fill_sentinel<T>(static_cast<T*>(x), save, n, nrhs, ld, s) != hipSuccess)
     return kErrHip;
-  a.grid = persistent_grid(h, multi ? 2 : (use_static ? 3 : 0), c.grid, ch->d.count);
+  a.grid = persistent_grid(h, use_static ? 3 : (multi ? 2 : 0), c.grid, ch->d.count);
   timing_begin(h, s, &stop);
-  const hipError_t e = multi ? launch_self_multi_value<T>(a, s)
-                             : (use_static ? launch_self_static<T>(a, s) : launch_self_value<T>(a, s));
+  const hipError_t e = use_static ? launch_self_static<T>(a, s)
+                                  : (multi ? launch_self_multi_value<T>(a, s) : launch_self_value<T>(a, s));
   if (e != hipSuccess) return kErrHip;
   timing_end(s, stop);
   return kOk;
@@ -409,6 +464,10 @@ int solve_dispatch(sptrsv_handle_t h, bool transpose, const void* b, void* x, in
   }
   PlanState& ps = transpose ? h->trn : h->fwd;
   const Config c = resolve(h);
+  if (c.algo == SPTRSV_ALGO_BLOCK && nrhs == 1) {
+    const int st = build_block(h, transpose ? 1 : 0, s);
+    if (st) return st;
+  }
   if (h->dtype == SPTRSV_F64) return solve_impl<double>(h, ps, c, b, x, nrhs, ld, s);
   return solve_impl<float>(h, ps, c, b, x, nrhs, ld, s);
 }
@@ -419,6 +478,11 @@ int init_handle_common(sptrsv_handle_t h, hipStream_t s) {
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device) == hipSuccess &&
       ncu > 0)
     h->num_cu = ncu;
+  int lds = 0;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device) ==
+          hipSuccess &&
+      lds > 0)
+    h->lds_limit = lds;
   int err = kOk;
   h->scratch.ticket = dalloc<int>(1, &err);
   h->scratch.status = dalloc<int>(1, &err);
@@ -450,10 +514,20 @@ int analyze_from_host(sptrsv_handle_t h, const void* vals, hipStream_t s) {
   return read_status(h, s, true);
 }
 
+void free_block(BlockState& b) {
+  free_plan(b.ps);
+  dfree(b.seg_row0);
+  dfree(b.seg_base);
+  dfree(b.lev_pos);
+  b = BlockState();
+}
+
 void destroy_handle(sptrsv_handle_t h) {
   if (!h) return;
   free_plan(h->fwd);
   free_plan(h->trn);
+  free_block(h->blk[0]);
+  free_block(h->blk[1]);
   dfree(h->scratch.ticket);
   dfree(h->scratch.status);
   dfree(h->scratch.epoch);
@@ -590,6 +664,8 @@ int sptrsv_update_values(sptrsv_handle_t h, const void* vals, hipStream_t stream
   if (h->batched) return kErrInvalidArg;
   int st = gather(h, h->fwd, vals, stream);
   if (!st && h->trn.built) st = gather(h, h->trn, h->fwd.vals_buf, stream);
+  if (!st && h->blk[0].built) st = gather(h, h->blk[0].ps, h->fwd.vals_buf, stream);
+  if (!st && h->blk[1].built) st = gather(h, h->blk[1].ps, h->trn.vals_buf, stream);
   h->last_stream = stream;
   return st;
 }
@@ -608,6 +684,8 @@ int sptrsv_update_values_batched(sptrsv_handle_t h, const void* const* vals, hip
   }
   int st = gather(h, h->fwd, h->vals_cat, stream);
   if (!st && h->trn.built) st = gather(h, h->trn, h->fwd.vals_buf, stream);
+  if (!st && h->blk[0].built) st = gather(h, h->blk[0].ps, h->fwd.vals_buf, stream);
+  if (!st && h->blk[1].built) st = gather(h, h->blk[1].ps, h->trn.vals_buf, stream);
   h->last_stream = stream;
   return st;
 }
@@ -660,8 +738,9 @@ int sptrsv_set_option(sptrsv_handle_t h, sptrsv_option key, int64_t v) {
     h->tuned = false;   // an explicit schedule option overrides the tuner's choice
   switch (key) {
     case SPTRSV_OPT_ALGO:
-      if (v != SPTRSV_ALGO_AUTO && v != SPTRSV_ALGO_LEVEL && v != SPTRSV_ALGO_SELF)
-        return v == SPTRSV_ALGO_BLOCK ? kErrNotSupported : kErrInvalidArg;
+      if (v != SPTRSV_ALGO_AUTO && v != SPTRSV_ALGO_LEVEL && v != SPTRSV_ALGO_SELF &&
+          v != SPTRSV_ALGO_BLOCK)
+        return kErrInvalidArg;
       h->algo = static_cast<int>(v);
       return kOk;
     case SPTRSV_OPT_GROUP:
@@ -729,7 +808,8 @@ int sptrsv_tune(sptrsv_handle_t h, const void* b, void* x, hipStream_t stream) {
   // and, for the self-scheduled solve, the persistent grid and the sync
   std::vector<Config> cand;
   const int ncu = h->num_cu;
-  const bool self_ok = h->algo != SPTRSV_ALGO_LEVEL, level_ok = h->algo != SPTRSV_ALGO_SELF;
+  const bool self_ok = h->algo == SPTRSV_ALGO_AUTO || h->algo == SPTRSV_ALGO_SELF;
+  const bool level_ok = h->algo == SPTRSV_ALGO_AUTO || h->algo == SPTRSV_ALGO_LEVEL;
   for (int epl : {1, 2, 4, 8}) {
     if (self_ok) {
       for (int grid : {ncu / 2, ncu, 2 * ncu, 4 * ncu})
@@ -742,6 +822,11 @@ int sptrsv_tune(sptrsv_handle_t h, const void* b, void* x, hipStream_t stream) {
     if (level_ok)
       for (int rpl : {1, 4})
         cand.push_back({SPTRSV_ALGO_LEVEL, 0, epl, SPTRSV_SYNC_VALUE, rpl, 0, SPTRSV_ASSIGN_TICKET});
+  }
+  if (h->algo == SPTRSV_ALGO_AUTO || h->algo == SPTRSV_ALGO_BLOCK) {
+    const int st0 = build_block(h, 0, stream);
+    if (st0) return st0;
+    cand.push_back({SPTRSV_ALGO_BLOCK, 0, 4, SPTRSV_SYNC_VALUE, 1, 0, SPTRSV_ASSIGN_TICKET});
   }
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
@@ -899,6 +984,8 @@ int sptrsv_graph_capture(sptrsv_handle_t h, const void* b, void* x, int transpos
     const Config c = resolve(h);
     int err = kOk;
     if (h->n > 0 && !get_chunks(h, transpose ? h->trn : h->fwd, c.group, c.epl, 0, c.rpl, &err))
+      return err;
+    if (h->n > 0 && c.algo == SPTRSV_ALGO_BLOCK && (err = build_block(h, transpose ? 1 : 0, stream)))
       return err;
     for (int kind = 0; kind < 4; ++kind) (void)blocks_per_cu(h, kind);
   }

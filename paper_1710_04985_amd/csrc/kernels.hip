@@ -308,7 +308,12 @@ template <typename T> struct StageD {   // first entries of the lane, raw
   T v[4];
 };
 
-template <typename T>
+// kMulti: several right-hand sides (column stride ld).  The lanes of a row
+// take columns q0 = lane % KL (KL = 2^lg lanes per row) instead of entries;
+// every lane walks all entries of its row in order, so each column is solved
+// exactly as the single right-hand side with one lane per row.  Columns
+// beyond the first KL are finished by the same lanes, unpipelined.
+template <typename T, bool kMulti>
 __global__ void __launch_bounds__(256)
 k_self_static(KArgs<T> a, const int* __restrict__ cstart, const int* __restrict__ cmeta) {
   const int lane = threadIdx.x & 63;
@@ -339,15 +344,18 @@ k_self_static(KArgs<T> a, const int* __restrict__ cstart, const int* __restrict_
       }
     }
     // ---- D (issue): gather x for the chunk whose entries arrived last time
+    const int64_t xoff_d = kMulti ? static_cast<int64_t>(lane & ((1 << sd.lg) - 1)) * a.ld : 0;
     T xv[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) xv[q] = load_agent(a.x + (sd.j[q] >= 0 ? sd.j[q] : 0));
+    for (int q = 0; q < 4; ++q)
+      xv[q] = load_agent(a.x + (sd.j[q] >= 0 ? xoff_d + sd.j[q] : 0));
     // ---- B: row bounds, row and diagonal of the chunk described last time
     StageC<T> nc{sb.c, sb.meta, -1, 0, 0, 0, T(1)};
     {
       const int lg = sb.meta >> 16, cnt = sb.meta & 0xffff;
       const int r = lane >> lg;
-      const bool live = sb.c >= 0 && r < cnt;
+      bool live = sb.c >= 0 && r < cnt;
+      if (kMulti) live = live && (lane & ((1 << lg) - 1)) < a.nrhs;
       const int kk = live ? sb.start + r : nlast;
       nc.k = live ? kk : -1;
       nc.p0 = a.off_ptr[kk];
@@ -363,9 +371,9 @@ k_self_static(KArgs<T> a, const int* __restrict__ cstart, const int* __restrict_
     nd.i = sc.i;
     nd.d = sc.d;
     {
-      const int G = 1 << nd.lg;
-      const int gl = lane & (G - 1);
-      nd.e = sc.p0 + gl;
+      const int G = kMulti ? 1 : 1 << nd.lg;          // entry stride of the lane
+      const int gl = lane & ((1 << nd.lg) - 1);
+      nd.e = sc.p0 + (kMulti ? 0 : gl);
       nd.e1 = sc.p1;
       const bool live = sc.c >= 0 && sc.k >= 0;
 #pragma unroll
@@ -378,34 +386,157 @@ k_self_static(KArgs<T> a, const int* __restrict__ cstart, const int* __restrict_
         nd.j[q] = ok ? jj : -1;
         nd.v[q] = ok ? vv : T(0);
       }
-      const T bb = a.b[sc.i];
-      nd.bi = (live && gl == 0) ? bb : T(0);
+      const int64_t boff = kMulti && live ? static_cast<int64_t>(gl) * a.ld : 0;
+      const T bb = a.b[boff + sc.i];
+      nd.bi = (live && (kMulti || gl == 0)) ? bb : T(0);
     }
     // ---- D (finish): wait, accumulate, rest of the row, group sum, store
     if (sd.c >= 0) {
-      const int G = 1 << sd.lg;
+      const int G = kMulti ? 1 : 1 << sd.lg;
+      T* xq = a.x + xoff_d;
       T sum = T(0);
       if (sd.k >= 0) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           if (sd.j[q] < 0) continue;
           T xx = xv[q];
-          if (is_sentinel(xx)) xx = wait_value(a.x + sd.j[q], a.spin_limit, a.status);
+          if (is_sentinel(xx)) xx = wait_value(xq + sd.j[q], a.spin_limit, a.status);
           sum = __builtin_fma(sd.v[q], xx, sum);
         }
         if (sd.e + 4 * G < sd.e1)
-          sum = row_dot<T, true>(a.off_col, a.off_val, sd.e + 4 * G, sd.e1, G, a.x, a.spin_limit,
+          sum = row_dot<T, true>(a.off_col, a.off_val, sd.e + 4 * G, sd.e1, G, xq, a.spin_limit,
                                  a.status, sum);
       }
-      sum = group_sum(sum, sd.lg);
-      if (sd.k >= 0 && (lane & (G - 1)) == 0)
-        store_agent(a.x + sd.i, canonical((sd.bi - sum) / sd.d));
+      if constexpr (kMulti) {
+        if (sd.k >= 0) {
+          store_agent(xq + sd.i, canonical((sd.bi - sum) / sd.d));
+          // columns beyond the first 2^lg, same lane, unpipelined
+          const int KL = 1 << sd.lg;
+          for (int q = (lane & (KL - 1)) + KL; q < a.nrhs; q += KL) {
+            const int64_t off = static_cast<int64_t>(q) * a.ld;
+            const T s2 = row_dot<T, true>(a.off_col, a.off_val, sd.e, sd.e1, 1, a.x + off,
+                                          a.spin_limit, a.status, T(0));
+            store_agent(a.x + off + sd.i, canonical((a.b[off + sd.i] - s2) / sd.d));
+          }
+        }
+      } else {
+        sum = group_sum(sum, sd.lg);
+        if (sd.k >= 0 && (lane & (G - 1)) == 0)
+          store_agent(a.x + sd.i, canonical((sd.bi - sum) / sd.d));
+      }
     } else if (sc.c < 0 && sb.c < 0 && nb.c < 0) {
       return;                         // pipeline drained
     }
     sd = nd;
     sc = nc;
     sb = nb;
+  }
+}
+
+// ------------------------------------------- block: a workgroup per system
+// Level-scheduled inside one workgroup per independent system (block-diagonal
+// batches, or one small system): thread t solves row t of each level (and
+// t + blockDim, ... for larger levels); the level barrier is a workgroup
+// barrier.  kLds: x of the system lives in LDS (the barrier then waits for
+// LDS traffic only, so the global loads below stay in flight across it);
+// otherwise x is read from global memory after a full workgroup barrier.
+// Row data of the next two levels are loaded ahead in two raw stages (row
+// bounds, then entries and b), as in the static self-scheduled kernel.
+// One row per thread, entries in stored order: the arithmetic of the other
+// kernels with one lane per row.
+template <typename T> struct BlkRow {   // raw row bounds
+  int k, p0, p1, i;
+  T d;
+};
+template <typename T> struct BlkEnt {   // raw first entries and b
+  int k, e, e1, i;
+  T d, bi;
+  int j[4];
+  T v[4];
+};
+
+template <typename T, bool kLds>
+__device__ __forceinline__ T blk_x(const T* xs, const T* x, int j, int r0) {
+  if constexpr (kLds) return xs[j - r0];
+  else return x[j];
+}
+
+template <typename T, bool kLds>
+__global__ void __launch_bounds__(1024)
+k_block(KArgs<T> a, const int* __restrict__ seg_row0, const int* __restrict__ seg_base,
+        const int* __restrict__ lev_pos) {
+  extern __shared__ __align__(16) unsigned char blk_smem[];
+  T* xs = reinterpret_cast<T*>(blk_smem);
+  const int s = blockIdx.x;
+  const int r0 = seg_row0[s];
+  const int lb = seg_base[s];
+  const int nl = seg_base[s + 1] - lb - 1;       // levels of this system (-1 if empty)
+  const int tid = threadIdx.x, NT = blockDim.x;
+  const int nlast = a.n - 1;
+  const int64_t olast = a.noff > 0 ? a.noff - 1 : 0;
+  auto bounds = [&](int m) {
+    BlkRow<T> r{-1, 0, 0, 0, T(1)};
+    const int p = (m < nl ? lev_pos[lb + m] : 0) + tid;
+    const bool live = m < nl && p < lev_pos[lb + m + 1];
+    const int kk = live ? p : nlast;
+    r.k = live ? kk : -1;
+    r.p0 = a.off_ptr[kk];
+    r.p1 = a.off_ptr[kk + 1];
+    r.i = a.pos_row[kk];
+    r.d = a.diag[kk];
+    return r;
+  };
+  auto entries = [&](const BlkRow<T>& r) {
+    BlkEnt<T> en;
+    en.k = r.k;
+    en.e = r.p0;
+    en.e1 = r.p1;
+    en.i = r.i;
+    en.d = r.d;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const bool ok = r.k >= 0 && r.p0 + q < r.p1;
+      const int64_t ec = ok ? r.p0 + q : olast;
+      const int jj = a.off_col[ec];
+      const T vv = a.off_val[ec];
+      en.j[q] = ok ? jj : -1;
+      en.v[q] = ok ? vv : T(0);
+    }
+    en.bi = a.b[r.i];
+    return en;
+  };
+  auto finish = [&](int e, int e1, int i, T d, T bi, T sum) {
+    for (; e < e1; ++e) sum = __builtin_fma(a.off_val[e], blk_x<T, kLds>(xs, a.x, a.off_col[e], r0), sum);
+    const T xi = canonical((bi - sum) / d);
+    if constexpr (kLds) xs[i - r0] = xi;
+    a.x[i] = xi;
+  };
+  BlkRow<T> r1 = bounds(1);
+  BlkEnt<T> e0 = entries(bounds(0));
+  for (int m = 0; m < nl; ++m) {
+    const BlkRow<T> r2 = bounds(m + 2);
+    const BlkEnt<T> e1 = entries(r1);
+    if (e0.k >= 0) {
+      T sum = T(0);
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (e0.j[q] >= 0) sum = __builtin_fma(e0.v[q], blk_x<T, kLds>(xs, a.x, e0.j[q], r0), sum);
+      finish(e0.e + 4, e0.e1, e0.i, e0.d, e0.bi, sum);
+    }
+    // rows of this level beyond the first blockDim, not loaded ahead
+    for (int p = lev_pos[lb + m] + tid + NT; p < lev_pos[lb + m + 1]; p += NT) {
+      const int i = a.pos_row[p];
+      finish(a.off_ptr[p], a.off_ptr[p + 1], i, a.diag[p], a.b[i], T(0));
+    }
+    if constexpr (kLds) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+      __builtin_amdgcn_s_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+    } else {
+      __syncthreads();
+    }
+    e0 = e1;
+    r1 = r2;
   }
 }
 
@@ -651,8 +782,27 @@ template <typename T> hipError_t launch_self_static(const SolveArgs& sa, hipStre
   const int* cs = sa.chunks->start;
   const int* cm = sa.chunks->meta;
   void* args[] = {&ka, &cs, &cm};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_self_static<T>), dim3(sa.grid),
-                                    dim3(sa.wg), args, 0, s);
+  const void* fn = sa.nrhs > 1 ? reinterpret_cast<const void*>(k_self_static<T, true>)
+                               : reinterpret_cast<const void*>(k_self_static<T, false>);
+  return hipLaunchCooperativeKernel(fn, dim3(sa.grid), dim3(sa.wg), args, 0, s);
+}
+
+template <typename T>
+hipError_t launch_block(const SolveArgs& sa, const int* seg_row0, const int* seg_base,
+                        const int* lev_pos, int nseg, int threads, int lds_rows, hipStream_t s) {
+  if (nseg == 0) return hipSuccess;
+  const KArgs<T> ka = make_args<T>(sa);
+  if (lds_rows > 0) {
+    const size_t bytes = static_cast<size_t>(lds_rows) * sizeof(T);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_block<T, true>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       static_cast<int>(bytes));
+    if (e != hipSuccess) return e;
+    k_block<T, true><<<nseg, threads, bytes, s>>>(ka, seg_row0, seg_base, lev_pos);
+  } else {
+    k_block<T, false><<<nseg, threads, 0, s>>>(ka, seg_row0, seg_base, lev_pos);
+  }
+  return hipGetLastError();
 }
 
 template <typename T> hipError_t launch_self_flag(const SolveArgs& sa, hipStream_t s) {
@@ -696,8 +846,12 @@ template <typename T> int self_flag_blocks_per_cu(int wg) {
 }
 template <typename T> int self_static_blocks_per_cu(int wg) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_self_static<T>, wg, 0) != hipSuccess)
+  // the multi-RHS form uses at least as many registers: size for the larger
+  int nb1 = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_self_static<T, false>, wg, 0) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb1, k_self_static<T, true>, wg, 0) != hipSuccess)
     return 1;
+  nb = nb < nb1 ? nb : nb1;
   return nb > 0 ? nb : 1;
 }
 template <typename T> int self_multi_blocks_per_cu(int wg) {
@@ -715,6 +869,8 @@ template <typename T> int self_multi_blocks_per_cu(int wg) {
   template hipError_t launch_self_value<T>(const SolveArgs&, hipStream_t);                      \
   template hipError_t launch_self_flag<T>(const SolveArgs&, hipStream_t);                       \
   template hipError_t launch_self_static<T>(const SolveArgs&, hipStream_t);                     \
+  template hipError_t launch_block<T>(const SolveArgs&, const int*, const int*, const int*, int,   \
+                                      int, int, hipStream_t);                                     \
   template int self_static_blocks_per_cu<T>(int);                                               \
   template hipError_t launch_self_multi_value<T>(const SolveArgs&, hipStream_t);                \
   template hipError_t launch_grad_vals<T>(int, const int*, const int*, int, const T*, const T*, \

@@ -61,6 +61,11 @@ template <typename T> hipError_t launch_level(const SolveArgs& a, int chunk_begi
                                               hipStream_t s);
 template <typename T> hipError_t launch_self_value(const SolveArgs& a, hipStream_t s);
 template <typename T> hipError_t launch_self_flag(const SolveArgs& a, hipStream_t s);
+// one workgroup of `threads` per independent system; lds_rows > 0: x of each
+// system in LDS (lds_rows >= the largest system), else in global memory
+template <typename T> hipError_t launch_block(const SolveArgs& a, const int* seg_row0,
+                                              const int* seg_base, const int* lev_pos, int nseg,
+                                              int threads, int lds_rows, hipStream_t s);
 // value sync, static round-robin chunks, cooperative launch (all resident)
 template <typename T> hipError_t launch_self_static(const SolveArgs& a, hipStream_t s);
 template <typename T> hipError_t launch_level_multi(const SolveArgs& a, int chunk_begin,

@@ -41,6 +41,7 @@ def _small_cases():
 
 CASES = _small_cases()
 SCHEDULES = [("level", dict(algo=1)), ("self_value", dict(algo=2, sync=0)),
+             ("block", dict(algo=3)), ("block_wg_ignored", dict(algo=3, group=4)),
              ("self_ticket", dict(algo=2, sync=0, assign=1)),
              ("self_static_g4_grid3", dict(algo=2, sync=0, assign=0, group=4, grid=3)),
              ("self_static_wg256", dict(algo=2, sync=0, assign=0, wg=256, grid=2)),
@@ -114,6 +115,10 @@ def test_level_equals_self_bitwise(sp, name, T, group, rpl):
     hl = sp.Handle(*dev_tri(T), uplo="U" if T.upper else "L").configure(algo=1, group=group,
                                                                         rows_per_lane=rpl)
     ref = hl.solve(b)
+    if group == 1:
+        hb = sp.Handle(*dev_tri(T), uplo="U" if T.upper else "L").configure(algo=3)
+        for _ in range(5):
+            assert bits_equal(hb.solve(b), ref)
     for sync, assign in ((0, 0), (0, 1), (1, 1)):
         if assign == 0 and rpl != 1:
             continue                  # static assignment keeps one row per lane
@@ -140,7 +145,7 @@ def test_in_place(sp, opts):
 
 
 @pytest.mark.parametrize("opts", [dict(algo=1), dict(algo=2, sync=0), dict(algo=2, sync=1),
-                                  dict(algo=2, sync=0, assign=1)])
+                                  dict(algo=2, sync=0, assign=1), dict(algo=3)])
 def test_exact_cases(sp, opts):
     """Diagonal: x = b/d; chain I - S (nlev = n): prefix sums of
     integers; bidiagonal (2, -1) with b = e_0: x_i = 2^-(i+1).  Bit-exact."""
@@ -184,7 +189,8 @@ def test_unit_diag(sp):
 
 
 @pytest.mark.parametrize("nrhs", [1, 3, 16, 70])
-@pytest.mark.parametrize("opts", [dict(algo=1), dict(algo=2)])
+@pytest.mark.parametrize("opts", [dict(algo=1), dict(algo=2), dict(algo=2, assign=1),
+                                  dict(algo=2, grid=3)])
 def test_multi_rhs(sp, nrhs, opts):
     o = oracle.get()
     T = W.laplacian_triangle((14, 13, 12), upper=True)
@@ -212,7 +218,7 @@ def test_batched(sp):
     tris.append(W.laplacian_triangle((9, 8)))
     bs = [W.uniform_vector(t.n, 40 + i) for i, t in enumerate(tris)]
     devs = [dev_tri(t) for t in tris]
-    for opts in (dict(algo=1), dict(algo=2, sync=0), dict(algo=2, sync=1)):
+    for opts in (dict(algo=1), dict(algo=2, sync=0), dict(algo=2, sync=1), dict(algo=3)):
         bh = sp.BatchedHandle([d[0] for d in devs], [d[1] for d in devs], [d[2] for d in devs]).configure(**opts)
         x = host(bh.solve(dev(np.concatenate(bs))))
         bh.status()
@@ -233,17 +239,44 @@ def test_batched(sp):
         off += t.n
 
 
+def test_block_global_x_path(sp):
+    """A batch whose largest system does not fit in LDS (x in global memory),
+    against the oracle and bitwise against the one-lane-per-row level solve."""
+    o = oracle.get()
+    tris = [W.ilu0_lower((150, 150)), W.ilu0_lower((40, 37)), W.laplacian_triangle((9, 8, 7))]
+    bs = [W.uniform_vector(t.n, 60 + i) for i, t in enumerate(tris)]
+    devs = [dev_tri(t) for t in tris]
+    bb = dev(np.concatenate(bs))
+    hb = sp.BatchedHandle([d[0] for d in devs], [d[1] for d in devs], [d[2] for d in devs]).configure(algo=3)
+    hl = sp.BatchedHandle([d[0] for d in devs], [d[1] for d in devs], [d[2] for d in devs]).configure(algo=1, group=1)
+    x = hb.solve(bb)
+    assert bits_equal(x, hl.solve(bb))
+    xt = host(hb.solve_t(bb))
+    x = host(x)
+    off = 0
+    for t, b in zip(tris, bs):
+        assert relerr(x[off:off + t.n], o.solve(t.row_ptr, t.col_idx, t.vals, b)) <= TOL64
+        assert relerr(xt[off:off + t.n], o.solve_transpose(t.row_ptr, t.col_idx, t.vals, b)) <= TOL64
+        off += t.n
+    hb.status()
+
+
 def test_update_values_and_zero_pivot(sp):
     o = oracle.get()
     T = W.laplacian_triangle((10, 9, 8))
     rp, ci, v = dev_tri(T)
     h = sp.Handle(rp, ci, v)
     h.prepare_transpose()
+    hb = sp.Handle(rp, ci, v).configure(algo=3)
+    hb.solve_t(dev(np.ones(T.n)))         # builds both block plans before the update
+    hb.solve(dev(np.ones(T.n)))
     v2 = T.vals * np.linspace(0.5, 2.0, T.nnz)
     h.update_values(dev(v2))
+    hb.update_values(dev(v2))
     b = W.uniform_vector(T.n, 1)
-    assert relerr(host(h.solve(dev(b))), o.solve(T.row_ptr, T.col_idx, v2, b)) <= TOL64
-    assert relerr(host(h.solve_t(dev(b))), o.solve_transpose(T.row_ptr, T.col_idx, v2, b)) <= TOL64
+    for hh in (h, hb):
+        assert relerr(host(hh.solve(dev(b))), o.solve(T.row_ptr, T.col_idx, v2, b)) <= TOL64
+        assert relerr(host(hh.solve_t(dev(b))), o.solve_transpose(T.row_ptr, T.col_idx, v2, b)) <= TOL64
     vz = v2.copy()
     vz[T.row_ptr[5 + 1] - 1] = 0.0          # diagonal of row 5 (stored last)
     h.update_values(dev(vz))
@@ -301,7 +334,8 @@ def test_watchdog_timeout_is_reported_and_recovers(sp, sync, assign):
     assert np.array_equal(x, np.arange(1, n + 1, dtype=np.float64))
 
 
-@pytest.mark.parametrize("opts", [dict(algo=1), dict(algo=2, sync=0), dict(algo=2, sync=1)])
+@pytest.mark.parametrize("opts", [dict(algo=1), dict(algo=2, sync=0), dict(algo=2, sync=1),
+                                  dict(algo=3)])
 def test_graph_replay(sp, opts):
     T = W.laplacian_triangle((24, 23, 22))
     h = sp.Handle(*dev_tri(T)).configure(**opts)
