@@ -52,6 +52,10 @@ def parse():
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     ap.add_argument("--suite", action="store_true")
+    ap.add_argument("--setup", action="store_true",
+                    help="also time the host and device setup routes (gpurun_out/bench_setup.jsonl)")
+    ap.add_argument("--table2", action="store_true",
+                    help="also run the Table 2 grid sweep (gpurun_out/bench_table2.jsonl)")
     return ap.parse_args()
 
 
@@ -272,6 +276,12 @@ def main():
     if args.suite:
         import bench_suite
         bench_suite.run(sp, torch, out_path=os.path.join("gpurun_out", "bench_suite.jsonl"))
+    if args.setup:
+        import bench_suite
+        bench_suite.setup_routes(sp, torch, out_path=os.path.join("gpurun_out", "bench_setup.jsonl"))
+    if args.table2:
+        import bench_suite
+        bench_suite.table2(sp, torch, out_path=os.path.join("gpurun_out", "bench_table2.jsonl"))
     print(json.dumps(out), flush=True)
 
 

@@ -232,3 +232,104 @@ def run(sp, torch, out_path, reps=20):
     emit(_multi(sp, torch, reps))
     emit(_adjoint(sp, torch, reps))
     return lines
+
+
+def table2(sp, torch, out_path, reps=10):
+    """The paper's Sec. 5.1 experiment on its Table 2 grids: lower then upper
+    solve (eq. (3)) of the 5/9-point (2-D, n = 2^20) and 7/27-point (3-D,
+    n = 2^21) operators, self- vs level-scheduled, against nlev."""
+    o = oracle.get()
+    rows = []
+    for dims_list, stencils in ((W.TABLE2_2D, (5, 9)), (W.TABLE2_3D, (7, 27))):
+        for dims in dims_list:
+            for pts in stencils:
+                L = W.stencil_triangle(dims, pts)
+                U = W.stencil_triangle(dims, pts, upper=True)
+                b = W.uniform_vector(L.n, 7)
+                y1 = o.solve(L.row_ptr, L.col_idx, L.vals, b, False)
+                yo = o.solve(U.row_ptr, U.col_idx, U.vals, y1, True)
+                dL, dU = _tri(torch, L), _tri(torch, U)
+                bd = torch.from_numpy(b).to(DEV)
+                t1 = torch.empty_like(bd)
+                t2 = torch.empty_like(bd)
+                res = {"config": "table2_%dpt_%s" % (pts, "x".join(map(str, dims))), "n": L.n,
+                       "nnz_lower": L.nnz, "points": pts}
+                for tag, algo in (("self", sp.ALGO_SELF), ("level", sp.ALGO_LEVEL)):
+                    hl = sp.Handle(*dL, uplo="L").configure(algo=algo)
+                    hu = sp.Handle(*dU, uplo="U").configure(algo=algo)
+                    res["nlev"] = hl.info()["nlev"]
+                    hl.tune(bd, t1)
+                    hu.tune(bd, t1)
+
+                    def step():
+                        hl.solve(bd, out=t1)
+                        hu.solve(t1, out=t2)
+
+                    step()
+                    hl.status()
+                    hu.status()
+                    res["rel_err_" + tag] = float("%.3e" % _relerr(t2.cpu().numpy(), yo))
+                    res[tag + "_ms"] = round(_time(torch, step, reps), 5)
+                lb = lb_bytes(L.n, L.nnz) + lb_bytes(U.n, U.nnz)
+                res["lb_bytes_step"] = lb
+                # the paper's GFLOPS of eq. (4): 2 nnz(A) / t, A = L + D + U
+                nnzA = L.nnz + U.nnz - L.n
+                res["gflops_self"] = round(2 * nnzA / (res["self_ms"] * 1e-3) / 1e9, 3)
+                res["gflops_level"] = round(2 * nnzA / (res["level_ms"] * 1e-3) / 1e9, 3)
+                res["gbs_self"] = round(lb / (res["self_ms"] * 1e-3) / 1e9, 3)
+                res["speedup_self_vs_level"] = round(res["level_ms"] / res["self_ms"], 3)
+                res["parity"] = "ok" if max(res["rel_err_self"], res["rel_err_level"]) <= 1e-12 else "FAIL"
+                rows.append(res)
+                _log(json.dumps(res))
+                with open(out_path, "a") as f:
+                    f.write(json.dumps(res) + "\n")
+    return rows
+
+
+def setup_routes(sp, torch, out_path, reps=3):
+    """Setup phase (Sec. 4.4, Table 1 routes): wall time of the analysis on
+    the host route and on the device route, the oracle's analysis on one
+    host core, and the tuned self-scheduled solve time, whose ratio to the
+    setup time is the number of solves that pay for one analysis."""
+    o = oracle.get()
+    rows = []
+    work = [("c2_lap3d_128_lower", W.c2_lap3d(upper=False)[0]),
+            ("c2_lap3d_128_upper", W.c2_lap3d(upper=True)[0]),
+            ("c3_powerlaw_1M", W.c3_powerlaw()[0]),
+            ("c5_ilu0_96", W.c5_ilu3d()[0])]
+    for name, T in work:
+        d = _tri(torch, T)
+        uplo = "U" if T.upper else "L"
+        res = {"config": "setup_" + name, "n": T.n, "nnz": T.nnz}
+        t0 = time.perf_counter()
+        lv, nlev, _, _, _ = o.analyze(T.row_ptr, T.col_idx, T.upper)
+        res["oracle_analysis_ms"] = round((time.perf_counter() - t0) * 1e3, 3)
+        res["nlev"] = int(nlev)
+        for route in ("host", "device"):
+            ts = []
+            for _ in range(reps + 1):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                h = sp.Handle(*d, uplo=uplo, setup=route)
+                torch.cuda.synchronize()
+                ts.append((time.perf_counter() - t0) * 1e3)
+                got_route, lib_ms = h.setup_info()
+                assert got_route == route
+                if route == "device":
+                    level = h.export_analysis()[0]
+                    res["device_levels_equal_oracle"] = bool(np.array_equal(level, lv))
+                h.close()
+            res[route + "_setup_ms"] = round(float(np.median(ts[1:])), 3)
+        h = sp.Handle(*d, uplo=uplo, setup="device")
+        bd = torch.from_numpy(W.uniform_vector(T.n, 7)).to(DEV)
+        xd = torch.empty_like(bd)
+        h.tune(bd, xd)
+        res["solve_ms"] = round(_time(torch, lambda: h.solve(bd, out=xd), 20), 5)
+        res["device_setup_speedup"] = round(res["host_setup_ms"] / res["device_setup_ms"], 3)
+        res["solves_per_device_setup"] = round(res["device_setup_ms"] / res["solve_ms"], 1)
+        h.close()
+        rows.append(res)
+        _log(json.dumps(res))
+        with open(out_path, "a") as f:
+            f.write(json.dumps(res) + "\n")
+    return rows

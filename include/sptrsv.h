@@ -106,8 +106,12 @@ typedef enum {
                                      launched (all-resident) grid, pipelined four chunks
                                      deep; value sync, one or several right-hand sides.  Under HIP graph
                                      capture the ticket form is used instead. */
-    SPTRSV_ASSIGN_TICKET = 1      /* wavefronts claim chunks from an atomic ticket: needs no
+    SPTRSV_ASSIGN_TICKET = 1,     /* wavefronts claim chunks from an atomic ticket: needs no
                                      co-residency, costs one serialised atomic per chunk */
+    SPTRSV_ASSIGN_XCD = 2         /* as STATIC, but each level's chunks are cut into 8
+                                     contiguous regions, region r going to the wavefronts of
+                                     workgroups r, r+8, ... (dispatched to one XCD), so that
+                                     most dependencies are produced under the same L2 */
 } sptrsv_assign;
 
 /* ---------------------------------------------------------------------- */
@@ -127,10 +131,41 @@ typedef enum {
  *   out        receives the new handle (NULL on failure)
  * Errors: INVALID_ARG, BAD_ROWPTR, BAD_COLIDX, NOT_TRIANGULAR, DUPLICATE,
  * MISSING_DIAG, ZERO_PIVOT, HIP, OOM.  Blocking: copies the pattern to the
- * host, computes there, uploads the result. */
+ * host, computes there, uploads the result (the host route of
+ * sptrsv_analyze_ex).  row_ptr / col_idx / vals may be freed afterwards. */
 int sptrsv_analyze(int32_t n, int32_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
                    const void *vals, sptrsv_dtype dtype, sptrsv_uplo uplo, int unit_diag,
                    hipStream_t stream, sptrsv_handle_t *out);
+
+/* Where the setup phase runs (Table 1 compares the two routes). */
+typedef enum {
+    SPTRSV_SETUP_HOST = 0,    /* pattern copied to the host, analysed there, plan uploaded */
+    SPTRSV_SETUP_DEVICE = 1   /* analysed in device memory: validity check and dependency
+                                 counts, a sync-free max-plus sweep for the levels (the
+                                 self-scheduled solve of Sec. 4.2 with max(level)+1 in
+                                 place of the dot product), stable radix sorts for jlev and
+                                 the level-ordered layout; only nlev, ilev and the row
+                                 pointers of that layout come to the host */
+} sptrsv_setup;
+
+/* sptrsv_analyze with a choice of route.  Results (levels, jlev, ilev,
+ * depcnt, the plan, every solve) are identical for both routes.  The device
+ * route handles patterns whose rows hold strictly increasing columns; any
+ * other pattern, and every invalid one, goes through the host route, which
+ * also names the validation error.  The device route keeps a device copy of
+ * the pattern and downloads it, with the plan, the first time something
+ * needs them on the host (the analysis of T^T, the block plan, export,
+ * sptrsv_tune).  Errors as for sptrsv_analyze, plus INVALID_ARG for an
+ * unknown route and TIMEOUT (level sweep; cannot happen on a valid
+ * triangle).  Blocking. */
+int sptrsv_analyze_ex(int32_t n, int32_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                      const void *vals, sptrsv_dtype dtype, sptrsv_uplo uplo, int unit_diag,
+                      int setup, hipStream_t stream, sptrsv_handle_t *out);
+
+/* Route the handle's analysis took (sptrsv_setup) and its wall time in
+ * milliseconds (host clock around the whole analysis call).  Either
+ * pointer may be NULL. */
+int sptrsv_get_setup(sptrsv_handle_t h, int32_t *route, double *ms);
 
 /* Batched analysis of `count` independent triangles of one dtype/uplo, solved
  * together as their block-diagonal concatenation (rows and columns of system

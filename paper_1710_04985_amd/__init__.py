@@ -26,7 +26,8 @@ ALGO_AUTO, ALGO_LEVEL, ALGO_SELF, ALGO_BLOCK = 0, 1, 2, 3
 SYNC_VALUE, SYNC_FLAG = 0, 1
 OPT = {"algo": 0, "group": 1, "entries_per_lane": 2, "sync": 3, "spin_limit": 4,
        "grid": 5, "timing": 6, "wg": 7, "rows_per_lane": 8, "assign": 9}
-ASSIGN_STATIC, ASSIGN_TICKET = 0, 1
+ASSIGN_STATIC, ASSIGN_TICKET, ASSIGN_XCD = 0, 1, 2
+SETUP = {"host": 0, "device": 1}
 
 _DT = {torch.float64: 0, torch.float32: 1}
 
@@ -185,12 +186,15 @@ class Handle(_Base):
     The handle keeps references to the three tensors (their device memory is
     read by analysis, update_values and grad_vals)."""
 
-    def __init__(self, row_ptr, col_idx, vals, uplo="L", unit_diag=False, stream=None):
+    def __init__(self, row_ptr, col_idx, vals, uplo="L", unit_diag=False, stream=None,
+                 setup="host"):
         _need_cuda(row_ptr, "row_ptr", torch.int32)
         _need_cuda(col_idx, "col_idx", torch.int32)
         _need_cuda(vals, "vals")
         if vals.dtype not in _DT:
             raise TypeError("vals must be float64 or float32")
+        if setup not in SETUP:
+            raise ValueError("setup must be one of %s" % sorted(SETUP))
         self.n = row_ptr.numel() - 1
         self.nnz = col_idx.numel()
         self.dtype = vals.dtype
@@ -198,10 +202,19 @@ class Handle(_Base):
         self.unit_diag = bool(unit_diag)
         self.row_ptr, self.col_idx, self.vals = row_ptr, col_idx, vals
         h = ctypes.c_void_p()
-        check(lib.sptrsv_analyze(self.n, self.nnz, _ptr(row_ptr), _ptr(col_idx), _ptr(vals),
-                                 _DT[vals.dtype], int(self.upper), int(self.unit_diag),
-                                 _stream(stream), ctypes.byref(h)))
+        check(lib.sptrsv_analyze_ex(self.n, self.nnz, _ptr(row_ptr), _ptr(col_idx), _ptr(vals),
+                                    _DT[vals.dtype], int(self.upper), int(self.unit_diag),
+                                    SETUP[setup], _stream(stream), ctypes.byref(h)))
         self._h = h
+
+    def setup_info(self):
+        """(route, milliseconds): where the analysis ran ('host' or 'device',
+        the device route hands invalid or unsorted patterns to the host one)
+        and its wall time."""
+        route = ctypes.c_int32()
+        ms = ctypes.c_double()
+        check(lib.sptrsv_get_setup(self._h, ctypes.byref(route), ctypes.byref(ms)))
+        return {v: k for k, v in SETUP.items()}[route.value], ms.value
 
     def update_values(self, vals, stream=None):
         _need_cuda(vals, "vals", self.dtype)

@@ -4,8 +4,28 @@
 
 #include <algorithm>
 #include <cstring>
+#include <thread>
 
 namespace sptrsv {
+
+// Runs fn(begin, end) over [0, n) split across up to 16 host threads; the
+// pieces must be independent.  Small ranges run on the calling thread.
+template <typename F> static void parallel_for(int64_t n, F fn) {
+  const unsigned hw = std::thread::hardware_concurrency();
+  int nt = static_cast<int>(std::min<unsigned>(hw ? hw : 1, 16));
+  if (n < (1 << 16) || nt <= 1) {
+    fn(int64_t(0), n);
+    return;
+  }
+  std::vector<std::thread> th;
+  const int64_t step = (n + nt - 1) / nt;
+  for (int t = 0; t < nt; ++t) {
+    const int64_t a = t * step, b = std::min(n, a + step);
+    if (a >= b) break;
+    th.emplace_back([=] { fn(a, b); });
+  }
+  for (auto& x : th) x.join();
+}
 
 int validate_pattern(int n, int64_t nnz, const int* row_ptr, const int* col, bool upper,
                      bool unit_diag, std::vector<int>* diag_pos) {
@@ -62,11 +82,13 @@ void level_sets(int n, const int* level, int nlev, int* ilev, int* jlev) {
 }
 
 void dependency_counts(int n, const int* row_ptr, const int* col, int* depcnt) {
-  for (int i = 0; i < n; ++i) {
-    int c = row_ptr[i + 1] - row_ptr[i];
-    for (int k = row_ptr[i]; k < row_ptr[i + 1]; ++k) c -= (col[k] == i);
-    depcnt[i] = c;
-  }
+  parallel_for(n, [&](int64_t a, int64_t b) {
+    for (int i = static_cast<int>(a); i < b; ++i) {
+      int c = row_ptr[i + 1] - row_ptr[i];
+      for (int k = row_ptr[i]; k < row_ptr[i + 1]; ++k) c -= (col[k] == i);
+      depcnt[i] = c;
+    }
+  });
 }
 
 void transpose_pattern(int n, const int* row_ptr, const int* col, std::vector<int>& rowT,
@@ -112,22 +134,24 @@ void build_plan(int n, const int* row_ptr, const int* col, const int* src, bool 
   for (int i = 0; i < n; ++i) max_len = std::max(max_len, p.depcnt[i]);
   p.max_row_len = max_len;
   const int nclass = bit_length(static_cast<unsigned>(max_len)) + 1;
-  std::vector<int> cls_count(nclass);
-  for (int m = 0; m < p.nlev; ++m) {
-    const int a = p.ilev[m], b = p.ilev[m + 1];
-    std::fill(cls_count.begin(), cls_count.end(), 0);
-    for (int t = a; t < b; ++t) cls_count[bit_length(p.depcnt[p.jlev[t]])]++;
-    int acc = a;
-    for (int c = 0; c < nclass; ++c) {
-      const int cnt = cls_count[c];
-      cls_count[c] = acc;
-      acc += cnt;
+  parallel_for(p.nlev, [&](int64_t ma, int64_t mb) {
+    std::vector<int> cls_count(nclass);
+    for (int m = static_cast<int>(ma); m < mb; ++m) {
+      const int a = p.ilev[m], b = p.ilev[m + 1];
+      std::fill(cls_count.begin(), cls_count.end(), 0);
+      for (int t = a; t < b; ++t) cls_count[bit_length(p.depcnt[p.jlev[t]])]++;
+      int acc = a;
+      for (int c = 0; c < nclass; ++c) {
+        const int cnt = cls_count[c];
+        cls_count[c] = acc;
+        acc += cnt;
+      }
+      for (int t = a; t < b; ++t) {
+        const int i = p.jlev[t];
+        p.pos_row[cls_count[bit_length(p.depcnt[i])]++] = i;
+      }
     }
-    for (int t = a; t < b; ++t) {
-      const int i = p.jlev[t];
-      p.pos_row[cls_count[bit_length(p.depcnt[i])]++] = i;
-    }
-  }
+  });
 
   // off-diagonal CSR in position order, value sources, diagonal sources
   p.off_ptr.resize(n + 1);
@@ -135,22 +159,30 @@ void build_plan(int n, const int* row_ptr, const int* col, const int* src, bool 
   for (int k = 0; k < n; ++k) p.off_ptr[k + 1] = p.off_ptr[k] + p.depcnt[p.pos_row[k]];
   p.noff = p.off_ptr[n];
   p.off_col.resize(p.noff);
+  p.off_pos.resize(p.noff);
   p.off_src.resize(p.noff);
   p.diag_src.assign(n, -1);
-  for (int k = 0; k < n; ++k) {
-    const int i = p.pos_row[k];
-    int o = p.off_ptr[k];
-    for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
-      const int s = src ? src[e] : e;
-      if (col[e] == i) {
-        if (!unit_diag) p.diag_src[k] = s;
-        continue;
+  std::vector<int> pos_of(n);
+  parallel_for(n, [&](int64_t a, int64_t b) {
+    for (int k = static_cast<int>(a); k < b; ++k) pos_of[p.pos_row[k]] = k;
+  });
+  parallel_for(n, [&](int64_t a, int64_t b) {
+    for (int k = static_cast<int>(a); k < b; ++k) {
+      const int i = p.pos_row[k];
+      int o = p.off_ptr[k];
+      for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+        const int s = src ? src[e] : e;
+        if (col[e] == i) {
+          if (!unit_diag) p.diag_src[k] = s;
+          continue;
+        }
+        p.off_col[o] = col[e];
+        p.off_pos[o] = pos_of[col[e]];
+        p.off_src[o] = s;
+        ++o;
       }
-      p.off_col[o] = col[e];
-      p.off_src[o] = s;
-      ++o;
     }
-  }
+  });
 }
 
 void build_chunks(const HostPlan& p, int group, int entries_per_lane, int rows_fixed,
@@ -225,12 +257,16 @@ void reorder_plan(const HostPlan& f, const std::vector<int>& order, HostPlan& o)
     if (f.diag_src[k] >= 0) o.diag_src[t] = static_cast<int>(f.noff) + k;
   }
   o.off_col.resize(o.noff);
+  o.off_pos.resize(o.noff);
   o.off_src.resize(o.noff);
+  std::vector<int> pos_of(n);
+  for (int t = 0; t < n; ++t) pos_of[o.pos_row[t]] = t;
   for (int t = 0; t < n; ++t) {
     const int k = order[t];
     int d = o.off_ptr[t];
     for (int e = f.off_ptr[k]; e < f.off_ptr[k + 1]; ++e, ++d) {
       o.off_col[d] = f.off_col[e];
+      o.off_pos[d] = pos_of[f.off_col[e]];
       o.off_src[d] = e;
     }
   }
@@ -275,20 +311,44 @@ void build_block_plan(const HostPlan& f, const std::vector<int>& seg_row0, HostP
   info.seg_base[nseg] = static_cast<int>(info.lev_pos.size());
 }
 
-uint64_t pattern_hash(int n, const int* row_ptr, const int* col, bool upper, bool unit_diag) {
-  uint64_t h = 1469598103934665603ull;
-  auto mix = [&](uint64_t v) {
-    for (int b = 0; b < 8; ++b) {
-      h ^= (v >> (8 * b)) & 0xff;
-      h *= 1099511628211ull;
+void build_wave_lists(const ChunkTable& t, int W, int regions, std::vector<int>& ptr,
+                      std::vector<int>& list) {
+  const int nch = static_cast<int>(t.start.size());
+  if (regions < 1 || W % regions != 0) regions = 1;
+  const int per = W / regions;                  // wavefronts per region
+  std::vector<int> owner(nch);
+  std::vector<long long> taken(regions, 0);     // chunks handed out per region so far
+  const int nlev = static_cast<int>(t.level_chunk.size()) - 1;
+  for (int m = 0; m < nlev; ++m) {
+    const int a = t.level_chunk[m], b = t.level_chunk[m + 1], L = b - a;
+    for (int c = a; c < b; ++c) {
+      const int r = static_cast<int>(static_cast<long long>(c - a) * regions / (L > 0 ? L : 1));
+      owner[c] = r + regions * static_cast<int>(taken[r]++ % per);
     }
+  }
+  ptr.assign(W + 1, 0);
+  for (int c = 0; c < nch; ++c) ptr[owner[c] + 1]++;
+  for (int w = 0; w < W; ++w) ptr[w + 1] += ptr[w];
+  list.resize(nch);
+  std::vector<int> fill(ptr.begin(), ptr.end() - 1);
+  for (int c = 0; c < nch; ++c) list[fill[owner[c]]++] = c;
+}
+
+uint64_t pattern_hash(int n, const int* row_ptr, const int* col, bool upper, bool unit_diag) {
+  // 64-bit multiply / xor-shift mixing of every index (splitmix64 finaliser)
+  auto mix = [](uint64_t h, uint64_t v) {
+    h ^= v + 0x9e3779b97f4a7c15ull + (h << 6) + (h >> 2);
+    h ^= h >> 30;
+    h *= 0xbf58476d1ce4e5b9ull;
+    h ^= h >> 27;
+    h *= 0x94d049bb133111ebull;
+    return h ^ (h >> 31);
   };
-  mix(static_cast<uint64_t>(n));
-  mix(upper);
-  mix(unit_diag);
+  uint64_t h = mix(mix(mix(0x243f6a8885a308d3ull, static_cast<uint64_t>(n)), upper), unit_diag);
   if (n == 0) return h;
-  for (int i = 0; i <= n; ++i) mix(static_cast<uint32_t>(row_ptr[i]));
-  for (int k = 0; k < row_ptr[n]; ++k) mix(static_cast<uint32_t>(col[k]));
+  const int64_t nnz = row_ptr[n];
+  for (int i = 0; i <= n; ++i) h = mix(h, static_cast<uint32_t>(row_ptr[i]));
+  for (int64_t k = 0; k < nnz; ++k) h = mix(h, static_cast<uint32_t>(col[k]));
   return h;
 }
 

@@ -52,8 +52,9 @@ void transpose_pattern(int n, const int* row_ptr, const int* col, std::vector<in
 //               level (pos_ilev), inside a level grouped by the bit length of
 //               the row's off-diagonal count, ascending row inside a group.
 //   off_ptr     CSR pointers of the off-diagonal entries in position order;
-//   off_col     their column (x index); off_src their index in the caller's
-//               value array (for the value gather);
+//   off_col     their column (x index); off_pos the position the column's
+//               row is solved at; off_src their index in the caller's value
+//               array (for the value gather);
 //   diag_src[k] index of the diagonal value of position k, -1 for unit.
 struct HostPlan {
   int n = 0;
@@ -64,7 +65,7 @@ struct HostPlan {
   bool unit_diag = false;
   std::vector<int> level, ilev, jlev, depcnt;   // canonical analysis (exported)
   std::vector<int> pos_row, pos_ilev;
-  std::vector<int> off_ptr, off_col, off_src, diag_src;
+  std::vector<int> off_ptr, off_col, off_pos, off_src, diag_src;
   int max_row_len = 0;            // max off-diagonal count of a row
 };
 
@@ -111,7 +112,17 @@ struct BlockInfo {
 void build_block_plan(const HostPlan& f, const std::vector<int>& seg_row0, HostPlan& out,
                       BlockInfo& info);
 
-// 64-bit FNV-1a hash of a pattern (autotuner cache key).
+// Chunk lists of the W wavefronts of a static schedule, as CSR: wavefront w
+// takes chunks list[ptr[w] .. ptr[w+1]) in that (increasing) order.  Each
+// level's chunks are cut into `regions` contiguous runs; run r goes to the
+// wavefronts w with w % regions == r (round-robin among them), so that a
+// chunk and the chunks of earlier levels at the same relative place in their
+// level land on the same group of wavefronts.  regions = 1 gives the plain
+// round-robin c -> c % W.
+void build_wave_lists(const ChunkTable& t, int W, int regions, std::vector<int>& ptr,
+                      std::vector<int>& list);
+
+// 64-bit hash of a pattern (autotuner cache key).
 uint64_t pattern_hash(int n, const int* row_ptr, const int* col, bool upper, bool unit_diag);
 
 }  // namespace sptrsv

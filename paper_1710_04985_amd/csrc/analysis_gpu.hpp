@@ -1,0 +1,46 @@
+// Device-side setup phase (Sec. 4.4 of Li, arXiv:1710.04985, the paper's
+// LEV_GPU / DEP_GPU route of Table 1): levels, level-ordered layout and level
+// pointers computed on the GPU from the caller's device pattern, without
+// copying it to the host.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+#include <vector>
+
+namespace sptrsv {
+
+// Device arrays of one analysed triangle (owned by the caller after success;
+// free with free_device_analysis).  Same meaning as the HostPlan fields.
+struct DeviceAnalysis {
+  int n = 0;
+  int nlev = 0;
+  int64_t noff = 0;
+  int max_row_len = 0;
+  int* level = nullptr;     // [n]
+  int* depcnt = nullptr;    // [n]
+  int* jlev = nullptr;      // [n] rows by (level, row)
+  int* pos_row = nullptr;   // [n]
+  int* off_ptr = nullptr;   // [n+1]
+  int* off_col = nullptr;   // [noff]
+  int* off_pos = nullptr;   // [noff]
+  int* off_src = nullptr;   // [noff]
+  int* diag_src = nullptr;  // [n]
+  std::vector<int> ilev;    // host: level pointers [nlev+1]
+  std::vector<int> off_ptr_h;   // host copy of off_ptr
+};
+
+// Analyses the triangle (row_ptr, col) held in device memory.  Returns kOk,
+// or kErrNotSupported when the pattern is not one the device path takes
+// (an invalid pattern, columns not strictly increasing inside a row, n or
+// nnz beyond its limits): the caller then runs the host analysis, which also
+// produces the exact validation error.  Other errors: kErrHip, kErrOom,
+// kErrTimeout (level kernel spin limit; cannot happen on a valid pattern).
+// Blocking: synchronises `stream`.
+int device_analysis(int n, int64_t nnz, const int* row_ptr, const int* col, bool upper,
+                    bool unit_diag, int num_cu, hipStream_t stream, DeviceAnalysis& out);
+
+void free_device_analysis(DeviceAnalysis& a);
+
+}  // namespace sptrsv

@@ -16,16 +16,24 @@
 #include <vector>
 
 #include "analysis.hpp"
+#include "analysis_gpu.hpp"
 #include "kernels.hpp"
 
 using namespace sptrsv;
 
 namespace {
 
+struct WaveLists {
+  int* ptr = nullptr;
+  int* list = nullptr;
+};
+
 struct ChunkEntry {
   DevChunks d;
   std::vector<int> level_chunk;   // host copy: chunk range of every level
+  std::vector<int> h_start, h_meta;
   int max_lg = 0;
+  std::map<std::pair<int, int>, WaveLists> waves;   // (wavefronts, regions)
 };
 
 struct PlanState {
@@ -75,10 +83,21 @@ struct sptrsv_handle_s {
   int lds_limit = 65536;          // bytes of LDS one workgroup may use
   std::vector<int> rp_h, col_h;   // caller's pattern (host copy)
   PlanState fwd, trn;
+  // device setup: the forward host plan holds only nlev, ilev and off_ptr
+  // until something needs the rest (transpose, block plan, export, tuner
+  // hash), which then downloads it and the handle's copy of the pattern
+  bool host_plan = true;
+  int* rp_dev = nullptr;
+  int* col_dev = nullptr;
+  int* dev_level = nullptr;
+  int* dev_depcnt = nullptr;
+  int* dev_jlev = nullptr;
+  int setup = SPTRSV_SETUP_HOST;  // route the analysis took
+  double setup_ms = 0.0;           // wall time of the analysis call
   BlockState blk[2];               // block-ordered plans of T and T^T
   DevScratch scratch;
-  void* tmp = nullptr;            // copy of b for in-place value-sync solves
-  size_t tmp_bytes = 0;
+  void* xp = nullptr;             // position-ordered solution(s) of the solve kernels
+  int64_t xp_elems = 0;
   // batched handles keep the concatenated pattern and values on the device
   bool batched = false;
   std::vector<int> sys_n, sys_nnz;
@@ -99,7 +118,8 @@ struct sptrsv_handle_s {
   // autotuner result
   bool tuned = false;
   Config tuned_cfg{SPTRSV_ALGO_SELF, 0, 4, SPTRSV_SYNC_VALUE, 1, 0, SPTRSV_ASSIGN_STATIC};
-  uint64_t hash = 0;
+  uint64_t hash = 0;               // pattern hash, computed by the first sptrsv_tune
+  bool hash_valid = false;
   // timing
   std::map<std::pair<int, int>, int> occupancy;   // (kernel kind, wg) -> blocks per CU
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
@@ -139,14 +159,46 @@ void free_chunks(PlanState& ps) {
   for (auto& kv : ps.chunks) {
     dfree(kv.second.d.start);
     dfree(kv.second.d.meta);
+    for (auto& w : kv.second.waves) {
+      dfree(w.second.ptr);
+      dfree(w.second.list);
+    }
   }
   ps.chunks.clear();
+}
+
+// Per-wavefront chunk lists of a static schedule over W wavefronts (built on
+// first use and kept; synchronous upload).
+const WaveLists* get_wave_lists(ChunkEntry& ch, int W, int regions, int* err) {
+  const auto key = std::make_pair(W, regions);
+  auto it = ch.waves.find(key);
+  if (it != ch.waves.end()) return &it->second;
+  ChunkTable t;
+  t.start = ch.h_start;
+  t.meta = ch.h_meta;
+  t.level_chunk = ch.level_chunk;
+  std::vector<int> ptr, list;
+  build_wave_lists(t, W, regions, ptr, list);
+  WaveLists wl;
+  int st = kOk;
+  wl.ptr = dalloc<int>(ptr.size(), &st);
+  wl.list = dalloc<int>(list.size(), &st);
+  if (st || hipMemcpy(wl.ptr, ptr.data(), ptr.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+      (!list.empty() &&
+       hipMemcpy(wl.list, list.data(), list.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)) {
+    dfree(wl.ptr);
+    dfree(wl.list);
+    *err = st ? st : kErrHip;
+    return nullptr;
+  }
+  return &(ch.waves[key] = wl);
 }
 
 void free_plan(PlanState& ps) {
   free_chunks(ps);
   dfree(ps.d.off_ptr);
   dfree(ps.d.off_col);
+  dfree(ps.d.off_pos);
   dfree(ps.d.off_src);
   dfree(ps.d.diag_src);
   dfree(ps.d.pos_row);
@@ -175,6 +227,7 @@ int upload_plan(PlanState& ps, size_t vb, hipStream_t s) {
   int st;
   if ((st = upload_ints(&d.off_ptr, h.off_ptr, s))) return st;
   if ((st = upload_ints(&d.off_col, h.off_col, s))) return st;
+  if ((st = upload_ints(&d.off_pos, h.off_pos, s))) return st;
   if ((st = upload_ints(&d.off_src, h.off_src, s))) return st;
   if ((st = upload_ints(&d.diag_src, h.diag_src, s))) return st;
   if ((st = upload_ints(&d.pos_row, h.pos_row, s))) return st;
@@ -184,6 +237,40 @@ int upload_plan(PlanState& ps, size_t vb, hipStream_t s) {
   d.off_val = ps.vals_buf;
   d.diag = static_cast<char*>(ps.vals_buf) + static_cast<size_t>(h.noff) * vb;
   ps.built = true;
+  return kOk;
+}
+
+// Completes the forward host plan of a handle analysed on the device: its
+// pattern and every plan array are downloaded once (blocking).
+int ensure_host_plan(sptrsv_handle_t h) {
+  if (h->host_plan) return kOk;
+  const size_t n = static_cast<size_t>(h->n);
+  HostPlan& p = h->fwd.h;
+  const DevPlan& d = h->fwd.d;
+  h->rp_h.resize(n + 1);
+  h->col_h.resize(h->nnz);
+  p.level.resize(n);
+  p.depcnt.resize(n);
+  p.jlev.resize(n);
+  p.pos_row.resize(n);
+  p.off_col.resize(p.noff);
+  p.off_pos.resize(p.noff);
+  p.off_src.resize(p.noff);
+  p.diag_src.resize(n);
+  const std::pair<int*, const int*> parts[] = {
+      {h->rp_h.data(), h->rp_dev},     {h->col_h.data(), h->col_dev},
+      {p.level.data(), h->dev_level},  {p.depcnt.data(), h->dev_depcnt},
+      {p.jlev.data(), h->dev_jlev},    {p.pos_row.data(), d.pos_row},
+      {p.off_col.data(), d.off_col},   {p.off_pos.data(), d.off_pos},
+      {p.off_src.data(), d.off_src},   {p.diag_src.data(), d.diag_src}};
+  const size_t counts[] = {n + 1, static_cast<size_t>(h->nnz), n, n, n, n,
+                           static_cast<size_t>(p.noff), static_cast<size_t>(p.noff),
+                           static_cast<size_t>(p.noff), n};
+  for (size_t q = 0; q < sizeof(counts) / sizeof(counts[0]); ++q)
+    if (counts[q] > 0)
+      HIPCHK(hipMemcpy(parts[q].first, parts[q].second, counts[q] * sizeof(int),
+                       hipMemcpyDeviceToHost));
+  h->host_plan = true;
   return kOk;
 }
 
@@ -214,6 +301,7 @@ int read_status(sptrsv_handle_t h, hipStream_t s, bool clear) {
 // outlive the analysis).
 int build_transpose(sptrsv_handle_t h, hipStream_t s) {
   if (h->trn.built) return kOk;
+  if (const int st = ensure_host_plan(h)) return st;
   const int n = h->n;
   const HostPlan& f = h->fwd.h;
   // location of every caller entry in the forward value buffer
@@ -240,6 +328,7 @@ int build_transpose(sptrsv_handle_t h, hipStream_t s) {
 int build_block(sptrsv_handle_t h, int dir, hipStream_t s) {
   BlockState& b = h->blk[dir];
   if (b.built) return kOk;
+  if (const int st = ensure_host_plan(h)) return st;
   PlanState& base = dir ? h->trn : h->fwd;
   std::vector<int> seg_row0(1, 0);
   if (h->batched)
@@ -268,6 +357,8 @@ ChunkEntry* get_chunks(sptrsv_handle_t h, PlanState& ps, int group, int epl, int
   build_chunks(ps.h, group, epl, rows_fixed, rpl, t);
   ChunkEntry e;
   e.level_chunk = t.level_chunk;
+  e.h_start = t.start;
+  e.h_meta = t.meta;
   e.max_lg = t.max_lg;
   e.d.count = static_cast<int>(t.start.size());
   int st;
@@ -309,18 +400,24 @@ uint64_t tune_key(sptrsv_handle_t h) {
          (static_cast<uint64_t>(h->algo) << 56);
 }
 
-int ensure_tmp(sptrsv_handle_t h, size_t bytes) {
-  if (h->tmp_bytes >= bytes) return kOk;
-  dfree(h->tmp);
-  h->tmp = nullptr;
-  h->tmp_bytes = 0;
-  if (hipMalloc(&h->tmp, bytes) != hipSuccess) return kErrOom;
-  h->tmp_bytes = bytes;
+// Grows the position-ordered solution buffer to `elems` values (blocking:
+// frees the previous buffer once the device is idle).
+int ensure_xp(sptrsv_handle_t h, int64_t elems) {
+  if (h->xp_elems >= elems) return kOk;
+  if (h->xp) {
+    HIPCHK(hipDeviceSynchronize());
+    dfree(h->xp);
+  }
+  h->xp = nullptr;
+  h->xp_elems = 0;
+  if (hipMalloc(&h->xp, static_cast<size_t>(elems > 0 ? elems : 1) * h->vb) != hipSuccess)
+    return kErrOom;
+  h->xp_elems = elems;
   return kOk;
 }
 
 // Resident workgroups per CU of persistent kernel `kind` (0 value sync, 1 flag
-// sync, 2 multi-RHS, 3 static value sync); queried once per (kind, wg) and
+// sync, 3 static value sync); queried once per (kind, wg) and
 // cached, so that solves under graph capture make no occupancy query.
 int blocks_per_cu(sptrsv_handle_t h, int kind) {
   const auto key = std::make_pair(kind, h->wg);
@@ -330,7 +427,6 @@ int blocks_per_cu(sptrsv_handle_t h, int kind) {
   const bool dbl = h->dtype == SPTRSV_F64;
   if (kind == 0) per_cu = dbl ? self_value_blocks_per_cu<double>(h->wg) : self_value_blocks_per_cu<float>(h->wg);
   else if (kind == 1) per_cu = dbl ? self_flag_blocks_per_cu<double>(h->wg) : self_flag_blocks_per_cu<float>(h->wg);
-  else if (kind == 2) per_cu = dbl ? self_multi_blocks_per_cu<double>(h->wg) : self_multi_blocks_per_cu<float>(h->wg);
   else per_cu = dbl ? self_static_blocks_per_cu<double>(h->wg) : self_static_blocks_per_cu<float>(h->wg);
   h->occupancy[key] = per_cu;
   return per_cu;
@@ -385,16 +481,19 @@ int solve_impl(sptrsv_handle_t h, PlanState& ps, const Config& c, const void* b,
   if (hipStreamIsCapturing(s, &cap) != hipSuccess) return kErrHip;
   const bool use_static = c.algo == SPTRSV_ALGO_SELF &&
                           (multi || c.sync == SPTRSV_SYNC_VALUE) &&
-                          c.assign == SPTRSV_ASSIGN_STATIC && cap == hipStreamCaptureStatusNone;
+                          (c.assign == SPTRSV_ASSIGN_STATIC || c.assign == SPTRSV_ASSIGN_XCD) &&
+                          cap == hipStreamCaptureStatusNone;
   ChunkEntry* ch = multi ? get_chunks(h, ps, 0, 0, 64 / kl, 1, &err)
                          : get_chunks(h, ps, c.group, c.epl, 0, use_static ? 1 : c.rpl, &err);
   if (!ch) return err;
+  if ((err = ensure_xp(h, static_cast<int64_t>(n) * nrhs))) return err;
   SolveArgs a;
   a.plan = &ps.d;
   a.chunks = &ch->d;
   a.scratch = h->scratch;
   a.b = b;
   a.x = x;
+  a.xp = h->xp;
   a.nrhs = nrhs;
   a.ld = ld;
   a.spin_limit = h->spin_limit;
@@ -421,7 +520,7 @@ int solve_impl(sptrsv_handle_t h, PlanState& ps, const Config& c, const void* b,
     timing_begin(h, s, &stop);
     for (int m = 0; m < ps.h.nlev; ++m) {
       const int cb = ch->level_chunk[m], ce = ch->level_chunk[m + 1];
-      const hipError_t e = multi ? launch_level_multi<T>(a, cb, ce, s) : launch_level<T>(a, cb, ce, s);
+      const hipError_t e = launch_level<T>(a, cb, ce, s);
       if (e != hipSuccess) return kErrHip;
     }
     timing_end(s, stop);
@@ -435,20 +534,22 @@ int solve_impl(sptrsv_handle_t h, PlanState& ps, const Config& c, const void* b,
     timing_end(s, stop);
     return kOk;
   }
-  // value sync: x starts as the sentinel; in place, b is saved first
-  T* save = nullptr;
-  if (b == x) {
-    const size_t bytes = static_cast<size_t>(ld) * nrhs * sizeof(T);
-    if ((err = ensure_tmp(h, bytes))) return err;
-    save = static_cast<T*>(h->tmp);
-    a.b = save;
-  }
-  if (launch_fill_sentinel<T>(static_cast<T*>(x), save, n, nrhs, ld, s) != hipSuccess)
+  // value sync: xp starts as the sentinel (b == x needs no copy: a row reads
+  // its own b before any write of its own x, and x is only written)
+  if (launch_fill_sentinel<T>(static_cast<T*>(h->xp), static_cast<int64_t>(n) * nrhs, s) !=
+      hipSuccess)
     return kErrHip;
-  a.grid = persistent_grid(h, use_static ? 3 : (multi ? 2 : 0), c.grid, ch->d.count);
+  a.grid = persistent_grid(h, use_static ? 3 : 0, c.grid, ch->d.count);
+  if (use_static) {
+    const int W = a.grid * (h->wg / 64);
+    const int regions = (c.assign == SPTRSV_ASSIGN_XCD && W % 8 == 0) ? 8 : 1;
+    const WaveLists* wl = get_wave_lists(*ch, W, regions, &err);
+    if (!wl) return err;
+    a.wave_ptr = wl->ptr;
+    a.wave_list = wl->list;
+  }
   timing_begin(h, s, &stop);
-  const hipError_t e = use_static ? launch_self_static<T>(a, s)
-                                  : (multi ? launch_self_multi_value<T>(a, s) : launch_self_value<T>(a, s));
+  const hipError_t e = use_static ? launch_self_static<T>(a, s) : launch_self_value<T>(a, s);
   if (e != hipSuccess) return kErrHip;
   timing_end(s, stop);
   return kOk;
@@ -489,6 +590,7 @@ int init_handle_common(sptrsv_handle_t h, hipStream_t s) {
   h->scratch.epoch = dalloc<unsigned>(1, &err);
   h->scratch.flags = dalloc<unsigned>(h->n, &err);
   if (err) return err;
+  if ((err = ensure_xp(h, h->n))) return err;
   HIPCHK(launch_init_scratch(h->scratch, h->n, s));
   return kOk;
 }
@@ -502,15 +604,66 @@ int analyze_from_host(sptrsv_handle_t h, const void* vals, hipStream_t s) {
   if ((st = init_handle_common(h, s))) return st;
   if ((st = upload_plan(h->fwd, h->vb, s))) return st;
   if ((st = gather(h, h->fwd, vals, s))) return st;
-  h->hash = pattern_hash(h->n, h->rp_h.data(), h->col_h.data(), h->upper, h->unit);
-  {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tune_cache.find(tune_key(h));
-    if (it != g_tune_cache.end()) {
-      h->tuned = true;
-      h->tuned_cfg = it->second;
-    }
-  }
+  return read_status(h, s, true);
+}
+
+// Setup on the device (levels, level-ordered layout) from the caller's device
+// pattern; the plan stays on the device, only nlev, ilev and off_ptr come to
+// the host (for the chunk tables).  Returns kErrNotSupported for a pattern
+// the device route does not take; the caller then runs the host route.
+int analyze_on_device(sptrsv_handle_t h, const int* row_ptr, const int* col_idx, const void* vals,
+                      hipStream_t s) {
+  (void)hipGetDevice(&h->device);
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device) == hipSuccess &&
+      ncu > 0)
+    h->num_cu = ncu;
+  DeviceAnalysis da;
+  int st = device_analysis(h->n, h->nnz, row_ptr, col_idx, h->upper, h->unit, h->num_cu, s, da);
+  if (st) return st;
+  HostPlan& p = h->fwd.h;
+  p = HostPlan();
+  p.n = h->n;
+  p.nlev = da.nlev;
+  p.nnz = h->nnz;
+  p.noff = da.noff;
+  p.upper = h->upper;
+  p.unit_diag = h->unit;
+  p.ilev = std::move(da.ilev);
+  p.pos_ilev = p.ilev;
+  p.off_ptr = std::move(da.off_ptr_h);
+  p.max_row_len = da.max_row_len;
+  DevPlan& d = h->fwd.d;
+  d.n = h->n;
+  d.nlev = da.nlev;
+  d.noff = da.noff;
+  d.off_ptr = da.off_ptr;
+  d.off_col = da.off_col;
+  d.off_pos = da.off_pos;
+  d.off_src = da.off_src;
+  d.diag_src = da.diag_src;
+  d.pos_row = da.pos_row;
+  h->dev_level = da.level;
+  h->dev_depcnt = da.depcnt;
+  h->dev_jlev = da.jlev;
+  h->host_plan = false;
+  int err = kOk;
+  h->fwd.vals_buf = dalloc<char>((static_cast<size_t>(da.noff) + h->n) * h->vb, &err);
+  if (!h->fwd.vals_buf) return err;
+  d.off_val = h->fwd.vals_buf;
+  d.diag = static_cast<char*>(h->fwd.vals_buf) + static_cast<size_t>(da.noff) * h->vb;
+  h->fwd.built = true;
+  // the handle's own copy of the pattern, for what is built later
+  h->rp_dev = dalloc<int>(static_cast<size_t>(h->n) + 1, &err);
+  h->col_dev = dalloc<int>(static_cast<size_t>(h->nnz), &err);
+  if (err) return err;
+  HIPCHK(hipMemcpyAsync(h->rp_dev, row_ptr, (static_cast<size_t>(h->n) + 1) * sizeof(int),
+                        hipMemcpyDeviceToDevice, s));
+  if (h->nnz > 0)
+    HIPCHK(hipMemcpyAsync(h->col_dev, col_idx, static_cast<size_t>(h->nnz) * sizeof(int),
+                          hipMemcpyDeviceToDevice, s));
+  if ((st = init_handle_common(h, s))) return st;
+  if ((st = gather(h, h->fwd, vals, s))) return st;
   return read_status(h, s, true);
 }
 
@@ -532,10 +685,15 @@ void destroy_handle(sptrsv_handle_t h) {
   dfree(h->scratch.status);
   dfree(h->scratch.epoch);
   dfree(h->scratch.flags);
-  dfree(h->tmp);
+  dfree(h->xp);
   dfree(h->rp_cat);
   dfree(h->col_cat);
   dfree(h->vals_cat);
+  dfree(h->rp_dev);
+  dfree(h->col_dev);
+  dfree(h->dev_level);
+  dfree(h->dev_depcnt);
+  dfree(h->dev_jlev);
   for (auto& pr : h->ev_pool) {
     (void)hipEventDestroy(pr.first);
     (void)hipEventDestroy(pr.second);
@@ -547,39 +705,75 @@ void destroy_handle(sptrsv_handle_t h) {
 
 extern "C" {
 
-int sptrsv_analyze(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
-                   const void* vals, sptrsv_dtype dtype, sptrsv_uplo uplo, int unit_diag,
-                   hipStream_t stream, sptrsv_handle_t* out) {
+int sptrsv_analyze_ex(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                      const void* vals, sptrsv_dtype dtype, sptrsv_uplo uplo, int unit_diag,
+                      int setup, hipStream_t stream, sptrsv_handle_t* out) {
   if (!out) return kErrInvalidArg;
   *out = nullptr;
   if (n < 0 || nnz < 0 || (dtype != SPTRSV_F64 && dtype != SPTRSV_F32) ||
-      (uplo != SPTRSV_LOWER && uplo != SPTRSV_UPPER))
+      (uplo != SPTRSV_LOWER && uplo != SPTRSV_UPPER) ||
+      (setup != SPTRSV_SETUP_HOST && setup != SPTRSV_SETUP_DEVICE))
     return kErrInvalidArg;
   if (!row_ptr || (nnz > 0 && (!col_idx || !vals))) return kErrInvalidArg;
-  sptrsv_handle_t h = new (std::nothrow) sptrsv_handle_s;
+  const auto t0 = std::chrono::steady_clock::now();
+  auto fresh = [&]() {
+    sptrsv_handle_t h = new (std::nothrow) sptrsv_handle_s;
+    if (!h) return h;
+    h->n = n;
+    h->nnz = nnz;
+    h->dtype = dtype;
+    h->vb = dtype == SPTRSV_F64 ? 8 : 4;
+    h->upper = uplo == SPTRSV_UPPER;
+    h->unit = unit_diag != 0;
+    return h;
+  };
+  sptrsv_handle_t h = fresh();
   if (!h) return kErrOom;
-  h->n = n;
-  h->nnz = nnz;
-  h->dtype = dtype;
-  h->vb = dtype == SPTRSV_F64 ? 8 : 4;
-  h->upper = uplo == SPTRSV_UPPER;
-  h->unit = unit_diag != 0;
-  h->rp_h.resize(static_cast<size_t>(n) + 1);
-  h->col_h.resize(nnz);
-  if (hipMemcpyAsync(h->rp_h.data(), row_ptr, (static_cast<size_t>(n) + 1) * sizeof(int),
-                     hipMemcpyDeviceToHost, stream) != hipSuccess ||
-      (nnz > 0 && hipMemcpyAsync(h->col_h.data(), col_idx, static_cast<size_t>(nnz) * sizeof(int),
-                                 hipMemcpyDeviceToHost, stream) != hipSuccess) ||
-      hipStreamSynchronize(stream) != hipSuccess) {
-    destroy_handle(h);
-    return kErrHip;
+  int st = kErrNotSupported;
+  if (setup == SPTRSV_SETUP_DEVICE && n > 0) {
+    st = analyze_on_device(h, row_ptr, col_idx, vals, stream);
+    if (st == kOk) h->setup = SPTRSV_SETUP_DEVICE;
+    if (st == kErrNotSupported) {
+      // the host route decides (and reports the exact validation error)
+      destroy_handle(h);
+      if (!(h = fresh())) return kErrOom;
+    }
   }
-  const int st = analyze_from_host(h, vals, stream);
+  if (st == kErrNotSupported) {
+    h->rp_h.resize(static_cast<size_t>(n) + 1);
+    h->col_h.resize(nnz);
+    if (hipMemcpyAsync(h->rp_h.data(), row_ptr, (static_cast<size_t>(n) + 1) * sizeof(int),
+                       hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        (nnz > 0 && hipMemcpyAsync(h->col_h.data(), col_idx, static_cast<size_t>(nnz) * sizeof(int),
+                                   hipMemcpyDeviceToHost, stream) != hipSuccess) ||
+        hipStreamSynchronize(stream) != hipSuccess) {
+      destroy_handle(h);
+      return kErrHip;
+    }
+    st = analyze_from_host(h, vals, stream);
+    h->setup = SPTRSV_SETUP_HOST;
+  }
   if (st) {
     destroy_handle(h);
     return st;
   }
+  h->setup_ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   *out = h;
+  return kOk;
+}
+
+int sptrsv_analyze(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                   const void* vals, sptrsv_dtype dtype, sptrsv_uplo uplo, int unit_diag,
+                   hipStream_t stream, sptrsv_handle_t* out) {
+  return sptrsv_analyze_ex(n, nnz, row_ptr, col_idx, vals, dtype, uplo, unit_diag,
+                           SPTRSV_SETUP_HOST, stream, out);
+}
+
+int sptrsv_get_setup(sptrsv_handle_t h, int32_t* route, double* ms) {
+  if (!h) return kErrInvalidArg;
+  if (route) *route = h->setup;
+  if (ms) *ms = h->setup_ms;
   return kOk;
 }
 
@@ -775,7 +969,8 @@ int sptrsv_set_option(sptrsv_handle_t h, sptrsv_option key, int64_t v) {
       h->rpl = static_cast<int>(v);
       return kOk;
     case SPTRSV_OPT_ASSIGN:
-      if (v != SPTRSV_ASSIGN_STATIC && v != SPTRSV_ASSIGN_TICKET) return kErrInvalidArg;
+      if (v != SPTRSV_ASSIGN_STATIC && v != SPTRSV_ASSIGN_TICKET && v != SPTRSV_ASSIGN_XCD)
+        return kErrInvalidArg;
       h->assign = static_cast<int>(v);
       return kOk;
   }
@@ -803,6 +998,21 @@ int sptrsv_tune(sptrsv_handle_t h, const void* b, void* x, hipStream_t stream) {
   if (!h) return kErrInvalidArg;
   if (h->n == 0) return kOk;
   if (!b || !x || b == x) return kErrInvalidArg;
+  if (!h->hash_valid) {
+    if (const int st = ensure_host_plan(h)) return st;
+    h->hash = pattern_hash(h->n, h->rp_h.data(), h->col_h.data(), h->upper, h->unit);
+    h->hash_valid = true;
+  }
+  {
+    // a pattern tuned before in this process (same dtype and fixed algo)
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(tune_key(h));
+    if (it != g_tune_cache.end()) {
+      h->tuned = true;
+      h->tuned_cfg = it->second;
+      return kOk;
+    }
+  }
   // candidate schedules, restricted to the algorithm the options fix (all of
   // them under ALGO_AUTO): the lane rule (entries per lane), rows per lane
   // and, for the self-scheduled solve, the persistent grid and the sync
@@ -812,8 +1022,10 @@ int sptrsv_tune(sptrsv_handle_t h, const void* b, void* x, hipStream_t stream) {
   const bool level_ok = h->algo == SPTRSV_ALGO_AUTO || h->algo == SPTRSV_ALGO_LEVEL;
   for (int epl : {1, 2, 4, 8}) {
     if (self_ok) {
-      for (int grid : {ncu / 2, ncu, 2 * ncu, 4 * ncu})
+      for (int grid : {ncu / 2, ncu, 2 * ncu, 4 * ncu}) {
         cand.push_back({SPTRSV_ALGO_SELF, 0, epl, SPTRSV_SYNC_VALUE, 1, grid, SPTRSV_ASSIGN_STATIC});
+        cand.push_back({SPTRSV_ALGO_SELF, 0, epl, SPTRSV_SYNC_VALUE, 1, grid, SPTRSV_ASSIGN_XCD});
+      }
       for (int rpl : {1, 4})
         cand.push_back({SPTRSV_ALGO_SELF, 0, epl, SPTRSV_SYNC_VALUE, rpl, ncu, SPTRSV_ASSIGN_TICKET});
       if (epl == 1 || epl == 4)
@@ -914,6 +1126,7 @@ int sptrsv_export_analysis(sptrsv_handle_t h, int transpose, int32_t* level, int
     const int st = build_transpose(h, h->last_stream);
     if (st) return st;
   }
+  if (const int st = ensure_host_plan(h)) return st;
   const HostPlan& p = transpose ? h->trn.h : h->fwd.h;
   if (level) std::copy(p.level.begin(), p.level.end(), level);
   if (ilev) std::copy(p.ilev.begin(), p.ilev.end(), ilev);
@@ -987,7 +1200,7 @@ int sptrsv_graph_capture(sptrsv_handle_t h, const void* b, void* x, int transpos
       return err;
     if (h->n > 0 && c.algo == SPTRSV_ALGO_BLOCK && (err = build_block(h, transpose ? 1 : 0, stream)))
       return err;
-    for (int kind = 0; kind < 4; ++kind) (void)blocks_per_cu(h, kind);
+    for (int kind : {0, 1, 3}) (void)blocks_per_cu(h, kind);
   }
   auto* g = new (std::nothrow) sptrsv_graph_s;
   if (!g) return kErrOom;

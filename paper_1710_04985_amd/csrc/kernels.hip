@@ -1,27 +1,31 @@
 // Solve kernels for gfx950 (CDNA4, 64-lane wavefronts).
 //
-// Work unit: a chunk = up to 64 consecutive level-ordered positions of ONE
-// level; a wavefront takes a chunk and gives each row G = 2^lg lanes.  Lanes
-// of a row stride over its off-diagonal entries (coalesced, the entries of a
-// chunk are contiguous in the level-ordered copy), gather x at the entry's
-// column, accumulate with FMA in a fixed order, and the group is summed with
-// a butterfly of lane exchanges.  Every kernel that solves rows uses the same
-// row_dot and group_sum, so at equal G the level-scheduled and the
-// self-scheduled solves produce bit-identical x.
+// Work unit: a chunk = consecutive level-ordered positions of ONE level (see
+// the chunk encoding in analysis.hpp); a wavefront takes a chunk.  With one
+// right-hand side a row gets G = 2^lg lanes that stride its off-diagonal
+// entries (coalesced: the entries of a chunk are contiguous in the
+// level-ordered copy), gather x, accumulate with FMA in a fixed order, and a
+// butterfly of lane exchanges sums the group; with G = 1 a lane may own
+// several rows.  With several right-hand sides the lanes of a row take
+// columns instead and each walks the whole row.  Every kernel uses the same
+// per-row order, so at equal chunking the schedules agree bit for bit.
+//
+// The solution is kept in position order (xp, see SolveArgs): dependencies of
+// neighbouring rows of a level are neighbouring positions of earlier levels,
+// so the x gathers coalesce.  Each row is also written to the caller's x.
 //
 // Level-scheduled (Sec. 4.1, LEVR): one launch per level over its chunks;
 // the launch boundary is the global synchronisation between levels.
 //
-// Self-scheduled (Sec. 4.2, SLFR): one persistent launch.  Wavefronts claim
-// chunks from an atomic ticket in level order, the order of the paper's jlev
-// mapping, so every row a claimed row waits for was claimed earlier by a
-// running wavefront: the wait always ends (no co-residency assumption).
-// Readiness of x_j is signalled either by x_j itself (x pre-filled with a
-// signalling NaN that no arithmetic produces; x_j published by one
-// agent-scope atomic store, polled with agent-scope atomic loads -- no cache
-// maintenance), or by a per-row flag stamped with the solve's epoch and
-// ordered by agent-scope release/acquire fences (the paper's dependency
-// counter, without its per-solve reset).
+// Self-scheduled (Sec. 4.2, SLFR): one persistent launch; wavefronts take
+// chunks in level order, the order of the paper's jlev mapping, and wait for
+// the individual rows they depend on.  Readiness of a row is signalled by
+// its value itself: xp starts filled with a signalling NaN that no
+// arithmetic produces, each value is published by one agent-scope atomic
+// store and polled with agent-scope atomic loads, so no cache maintenance is
+// needed.  The paper's dependency counters are also available as per-row
+// flags stamped with the solve's epoch, ordered by agent-scope
+// release/acquire fences (flag sync).
 #include <hip/hip_runtime.h>
 
 #include "analysis.hpp"
@@ -70,9 +74,10 @@ __device__ __forceinline__ void raise_status(int* s, int bit) {
   __hip_atomic_fetch_or(s, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Bounded wait for x_j (value sync).  After spin_limit polls, or once another
-// wavefront has timed out, the wait gives up: TIMEOUT is raised and a quiet
-// NaN is used, so every dependent finishes and the grid drains.
+// Bounded wait for a published value (value sync).  After spin_limit polls,
+// or once another wavefront has timed out, the wait gives up: TIMEOUT is
+// raised and a quiet NaN is used, so every dependent finishes and the grid
+// drains.
 template <typename T>
 __device__ __attribute__((noinline)) T wait_value(const T* p, int spin_limit, int* status) {
   for (int s = 1; s <= spin_limit; ++s) {
@@ -107,11 +112,13 @@ template <typename T> struct KArgs {
   int64_t noff;
   const int* off_ptr;
   const int* off_col;
+  const int* off_pos;
   const T* off_val;
   const T* diag;
   const int* pos_row;
   const T* b;
   T* x;
+  T* xp;
   int ld;
   int nrhs;
   int* ticket;
@@ -122,30 +129,32 @@ template <typename T> struct KArgs {
 };
 
 // Continues `sum` over the lane's entries e, e+G, e+2G, ... < e1 of one row,
-// four entries in flight at a time.  kPoll: x is read with agent-scope atomic
-// loads and sentinel values are waited for.
+// four entries in flight at a time, reading x at xr[idx[entry] * xs].
+// kPoll: atomic agent-scope loads, sentinel values are waited for.
 template <typename T, bool kPoll>
-__device__ __forceinline__ T row_dot(const int* __restrict__ off_col,
-                                     const T* __restrict__ off_val, int e, int e1, int G,
-                                     const T* x, int spin_limit, int* status, T sum) {
+__device__ __forceinline__ T row_dot(const int* __restrict__ idx, const T* __restrict__ off_val,
+                                     int e, int e1, int G, const T* xr, int xs, int spin_limit,
+                                     int* status, T sum) {
   for (; e < e1; e += 4 * G) {
     int j[4];
     T v[4], xv[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int ee = e + u * G;
-      j[u] = ee < e1 ? off_col[ee] : -1;
+      j[u] = ee < e1 ? idx[ee] : -1;
       v[u] = ee < e1 ? off_val[ee] : T(0);
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      if (j[u] >= 0) xv[u] = kPoll ? load_agent(x + j[u]) : x[j[u]];
+      const T* p = xr + static_cast<int64_t>(j[u]) * xs;
+      if (j[u] >= 0) xv[u] = kPoll ? load_agent(p) : *p;
       else xv[u] = T(0);
     }
     if constexpr (kPoll) {
 #pragma unroll
       for (int u = 0; u < 4; ++u)
-        if (j[u] >= 0 && is_sentinel(xv[u])) xv[u] = wait_value(x + j[u], spin_limit, status);
+        if (j[u] >= 0 && is_sentinel(xv[u]))
+          xv[u] = wait_value(xr + static_cast<int64_t>(j[u]) * xs, spin_limit, status);
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
@@ -159,20 +168,18 @@ template <typename T> __device__ __forceinline__ T group_sum(T v, int lg) {
   return v;
 }
 
-template <typename T, bool kPoll> __device__ __forceinline__ void store_x(T* p, T v) {
+template <typename T, bool kPoll> __device__ __forceinline__ void publish(T* p, T v) {
   if constexpr (kPoll) store_agent(p, v);
   else *p = v;
 }
 
 __device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// Solves the rows of one chunk (see the chunk encoding in analysis.hpp).
+// Solves the rows of one chunk, one right-hand side.
 //  G = 1: lane l owns rows start+l, start+l+64, ... (up to kMaxRowsPerLane);
-//         the bounds, first four entries, x gathers, b and diagonal of all its
+//         bounds, first four entries, x gathers, b and diagonal of all its
 //         rows are issued before any wait, then each row is finished.
 //  G > 1: rows of G lanes; lanes stride the row, the group sums by butterfly.
-// Per row the accumulation order is the same in every kernel using this, so
-// level- and self-scheduled solves agree bit for bit at equal chunking.
 template <typename T, bool kPoll>
 __device__ __forceinline__ void solve_chunk(const KArgs<T>& a, int start, int meta, int lane) {
   const int cnt = meta & 0xffff, lg = meta >> 16;
@@ -205,7 +212,7 @@ __device__ __forceinline__ void solve_chunk(const KArgs<T>& a, int start, int me
 #pragma unroll
       for (int q = 0; q < E; ++q) {
         const int ee = e0[u] + q;
-        j[u][q] = ee < e1[u] ? a.off_col[ee] : -1;
+        j[u][q] = ee < e1[u] ? a.off_pos[ee] : -1;
         v[u][q] = ee < e1[u] ? a.off_val[ee] : T(0);
       }
     }
@@ -213,7 +220,7 @@ __device__ __forceinline__ void solve_chunk(const KArgs<T>& a, int start, int me
     for (int u = 0; u < R; ++u)
 #pragma unroll
       for (int q = 0; q < E; ++q)
-        xv[u][q] = j[u][q] >= 0 ? (kPoll ? load_agent(a.x + j[u][q]) : a.x[j[u][q]]) : T(0);
+        xv[u][q] = j[u][q] >= 0 ? (kPoll ? load_agent(a.xp + j[u][q]) : a.xp[j[u][q]]) : T(0);
 #pragma unroll
     for (int u = 0; u < R; ++u) {
       if (k[u] < 0) continue;
@@ -222,13 +229,15 @@ __device__ __forceinline__ void solve_chunk(const KArgs<T>& a, int start, int me
       for (int q = 0; q < E; ++q) {
         if (j[u][q] < 0) continue;
         T xx = xv[u][q];
-        if (kPoll && is_sentinel(xx)) xx = wait_value(a.x + j[u][q], a.spin_limit, a.status);
+        if (kPoll && is_sentinel(xx)) xx = wait_value(a.xp + j[u][q], a.spin_limit, a.status);
         sum = __builtin_fma(v[u][q], xx, sum);
       }
       if (e1[u] > e0[u] + E)
-        sum = row_dot<T, kPoll>(a.off_col, a.off_val, e0[u] + E, e1[u], 1, a.x, a.spin_limit,
+        sum = row_dot<T, kPoll>(a.off_pos, a.off_val, e0[u] + E, e1[u], 1, a.xp, 1, a.spin_limit,
                                 a.status, sum);
-      store_x<T, kPoll>(a.x + i[u], canonical((bi[u] - sum) / di[u]));
+      const T xi = canonical((bi[u] - sum) / di[u]);
+      publish<T, kPoll>(a.xp + k[u], xi);
+      a.x[i[u]] = xi;
     }
     return;
   }
@@ -237,12 +246,38 @@ __device__ __forceinline__ void solve_chunk(const KArgs<T>& a, int start, int me
   const int k = start + r;
   T sum = T(0);
   if (active)
-    sum = row_dot<T, kPoll>(a.off_col, a.off_val, a.off_ptr[k] + gl, a.off_ptr[k + 1], 1 << lg,
-                            a.x, a.spin_limit, a.status, T(0));
+    sum = row_dot<T, kPoll>(a.off_pos, a.off_val, a.off_ptr[k] + gl, a.off_ptr[k + 1], 1 << lg,
+                            a.xp, 1, a.spin_limit, a.status, T(0));
   sum = group_sum(sum, lg);
   if (active && gl == 0) {
     const int i = a.pos_row[k];
-    store_x<T, kPoll>(a.x + i, canonical((a.b[i] - sum) / a.diag[k]));
+    const T xi = canonical((a.b[i] - sum) / a.diag[k]);
+    publish<T, kPoll>(a.xp + k, xi);
+    a.x[i] = xi;
+  }
+}
+
+// Several right-hand sides: the 2^lg lanes of a row take columns q0 = lane %
+// 2^lg (+ multiples of 2^lg); each lane walks all entries of its row in order
+// for its column, so every column is solved as the one-lane-per-row single
+// solve.  The row's indices and values are fetched once for all columns.
+template <typename T, bool kPoll>
+__device__ __forceinline__ void solve_chunk_multi(const KArgs<T>& a, int start, int meta,
+                                                  int lane) {
+  const int cnt = meta & 0xffff, lg = meta >> 16;
+  const int r = lane >> lg, q0 = lane & ((1 << lg) - 1);
+  if (r >= cnt) return;
+  const int k = start + r;
+  const int i = a.pos_row[k];
+  const int e0 = a.off_ptr[k], e1 = a.off_ptr[k + 1];
+  const T d = a.diag[k];
+  for (int q = q0; q < a.nrhs; q += (1 << lg)) {
+    const int64_t off = static_cast<int64_t>(q) * a.ld;
+    const T sum = row_dot<T, kPoll>(a.off_pos, a.off_val, e0, e1, 1, a.xp + q, a.nrhs,
+                                    a.spin_limit, a.status, T(0));
+    const T xi = canonical((a.b[off + i] - sum) / d);
+    publish<T, kPoll>(a.xp + static_cast<int64_t>(k) * a.nrhs + q, xi);
+    a.x[off + i] = xi;
   }
 }
 
@@ -262,38 +297,43 @@ __device__ __forceinline__ int claim_chunk(int* ticket, int nchunks, int lane) {
 }
 
 // ---------------------------------------------------------------- level
-template <typename T>
+template <typename T, bool kMulti>
 __global__ void __launch_bounds__(256) k_level(KArgs<T> a, int chunk_begin, int chunk_end) {
   const int lane = threadIdx.x & 63;
   const int c = wave_uniform(chunk_begin + static_cast<int>((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
   if (c >= chunk_end) return;
-  solve_chunk<T, false>(a, a.chunk_start[c], a.chunk_meta[c], lane);
+  if constexpr (kMulti) solve_chunk_multi<T, false>(a, a.chunk_start[c], a.chunk_meta[c], lane);
+  else solve_chunk<T, false>(a, a.chunk_start[c], a.chunk_meta[c], lane);
 }
 
-// ----------------------------------------------------- self, value sync
-template <typename T>
+// ------------------------------------------------ self, value sync, ticket
+template <typename T, bool kMulti>
 __global__ void __launch_bounds__(256) k_self_value(KArgs<T> a) {
   const int lane = threadIdx.x & 63;
   for (;;) {
     const int c = claim_chunk(a.ticket, a.nchunks, lane);
     if (c < 0) return;
-    solve_chunk<T, true>(a, a.chunk_start[c], a.chunk_meta[c], lane);
+    if constexpr (kMulti) solve_chunk_multi<T, true>(a, a.chunk_start[c], a.chunk_meta[c], lane);
+    else solve_chunk<T, true>(a, a.chunk_start[c], a.chunk_meta[c], lane);
   }
 }
 
 // ------------------------------------- self, value sync, static pipeline
-// Wavefront w of W takes chunks w, w+W, w+2W, ... in that order (the grid is
-// launched cooperatively, so all W wavefronts are resident: the wavefront
+// Wavefront w takes the chunks of its own list in increasing order (lists are
+// fixed before the launch: round-robin, or by XCD region).  The grid is
+// launched cooperatively, so all wavefronts are resident: the wavefront
 // holding the lowest unfinished chunk has finished its earlier chunks and is
-// working on it, and that chunk's dependencies are done).  No claim atomics.
+// working on it, and that chunk's dependencies are done.  No claim atomics.
 // Each chunk moves through four stages, one chunk apart, so the dependent
 // index loads of later chunks are in flight while this one waits on x:
 //   A descriptor -> B row bounds, row, diagonal -> C first entries, b
-//   -> D gather x (poll), accumulate, store.
-// Per row the arithmetic is that of solve_chunk with one row per lane.
+//   -> D gather x (poll), accumulate, publish.
 // Each stage only stores raw loaded values; any arithmetic on them happens
 // one iteration later, so no wait for a load is needed before the next
-// stage's loads (and the x gathers) have been issued.
+// stage's loads (and the x gathers) have been issued.  Loads whose result is
+// discarded use clamped in-range indices instead of branches.
+// kMulti: the lanes of a row take columns (as in solve_chunk_multi); columns
+// beyond the first 2^lg are finished by the same lanes, unpipelined.
 template <typename T> struct StageB {   // descriptor, raw
   int c, start, meta;
 };
@@ -308,20 +348,18 @@ template <typename T> struct StageD {   // first entries of the lane, raw
   T v[4];
 };
 
-// kMulti: several right-hand sides (column stride ld).  The lanes of a row
-// take columns q0 = lane % KL (KL = 2^lg lanes per row) instead of entries;
-// every lane walks all entries of its row in order, so each column is solved
-// exactly as the single right-hand side with one lane per row.  Columns
-// beyond the first KL are finished by the same lanes, unpipelined.
 template <typename T, bool kMulti>
 __global__ void __launch_bounds__(256)
-k_self_static(KArgs<T> a, const int* __restrict__ cstart, const int* __restrict__ cmeta) {
+k_self_static(KArgs<T> a, const int* __restrict__ cstart, const int* __restrict__ cmeta,
+              const int* __restrict__ wptr, const int* __restrict__ wlist) {
   const int lane = threadIdx.x & 63;
-  const int W = static_cast<int>(gridDim.x * (blockDim.x >> 6));
   const int w = wave_uniform(static_cast<int>((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
-  const int nch = a.nchunks;
+  // this wavefront's chunks: wlist[wptr[w] .. wptr[w+1]), increasing
+  const int tb = wptr[w], te = wptr[w + 1];
+  const int llast = a.nchunks - 1;    // clamp for the list load past the end
   const int nlast = a.n - 1;          // clamp for loads whose result is discarded
   const int64_t olast = a.noff > 0 ? a.noff - 1 : 0;
+  const int xs = kMulti ? a.nrhs : 1;
   StageB<T> sb{-1, 0, 0};
   StageC<T> sc{-1, 0, -1, 0, 0, 0, T(1)};
   StageD<T> sd;
@@ -330,25 +368,29 @@ k_self_static(KArgs<T> a, const int* __restrict__ cstart, const int* __restrict_
   sd.k = -1;
 #pragma unroll
   for (int q = 0; q < 4; ++q) sd.j[q] = -1;
-  int next = w;                       // next chunk to enter stage A
+  int t = tb;                         // list index of the chunk entering stage A
+  int cur = wlist[tb < te ? tb : llast];   // that chunk (loaded one iteration ahead)
   for (;;) {
-    // ---- A: descriptor of a new chunk (uniform index, read-only table)
+    // ---- A: descriptor of a new chunk (uniform index, read-only tables)
     StageB<T> nb{-1, 0, 0};
     {
-      const int cn = wave_uniform(next < nch ? next : nch - 1);
+      const bool live = t < te;
+      const int cn = wave_uniform(cur);
       nb.start = cstart[cn];
       nb.meta = cmeta[cn];
-      if (next < nch) {
-        nb.c = next;
-        next += W;
+      if (live) {
+        nb.c = cn;
+        ++t;
       }
+      cur = wlist[t < te ? t : llast];
     }
     // ---- D (issue): gather x for the chunk whose entries arrived last time
-    const int64_t xoff_d = kMulti ? static_cast<int64_t>(lane & ((1 << sd.lg) - 1)) * a.ld : 0;
+    const int qd = kMulti ? (lane & ((1 << sd.lg) - 1)) : 0;
+    const T* xq = a.xp + qd;
     T xv[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q)
-      xv[q] = load_agent(a.x + (sd.j[q] >= 0 ? xoff_d + sd.j[q] : 0));
+      xv[q] = load_agent(xq + static_cast<int64_t>(sd.j[q] >= 0 ? sd.j[q] : 0) * xs);
     // ---- B: row bounds, row and diagonal of the chunk described last time
     StageC<T> nc{sb.c, sb.meta, -1, 0, 0, 0, T(1)};
     {
@@ -381,7 +423,7 @@ k_self_static(KArgs<T> a, const int* __restrict__ cstart, const int* __restrict_
         const int ee = nd.e + q * G;
         const bool ok = live && ee < nd.e1;
         const int64_t ec = ok ? ee : olast;
-        const int jj = a.off_col[ec];
+        const int jj = a.off_pos[ec];
         const T vv = a.off_val[ec];
         nd.j[q] = ok ? jj : -1;
         nd.v[q] = ok ? vv : T(0);
@@ -390,39 +432,46 @@ k_self_static(KArgs<T> a, const int* __restrict__ cstart, const int* __restrict_
       const T bb = a.b[boff + sc.i];
       nd.bi = (live && (kMulti || gl == 0)) ? bb : T(0);
     }
-    // ---- D (finish): wait, accumulate, rest of the row, group sum, store
+    // ---- D (finish): wait, accumulate, rest of the row, group sum, publish
     if (sd.c >= 0) {
       const int G = kMulti ? 1 : 1 << sd.lg;
-      T* xq = a.x + xoff_d;
       T sum = T(0);
       if (sd.k >= 0) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           if (sd.j[q] < 0) continue;
           T xx = xv[q];
-          if (is_sentinel(xx)) xx = wait_value(xq + sd.j[q], a.spin_limit, a.status);
+          if (is_sentinel(xx))
+            xx = wait_value(xq + static_cast<int64_t>(sd.j[q]) * xs, a.spin_limit, a.status);
           sum = __builtin_fma(sd.v[q], xx, sum);
         }
         if (sd.e + 4 * G < sd.e1)
-          sum = row_dot<T, true>(a.off_col, a.off_val, sd.e + 4 * G, sd.e1, G, xq, a.spin_limit,
-                                 a.status, sum);
+          sum = row_dot<T, true>(a.off_pos, a.off_val, sd.e + 4 * G, sd.e1, G, xq, xs,
+                                 a.spin_limit, a.status, sum);
       }
       if constexpr (kMulti) {
         if (sd.k >= 0) {
-          store_agent(xq + sd.i, canonical((sd.bi - sum) / sd.d));
+          const T xi = canonical((sd.bi - sum) / sd.d);
+          store_agent(a.xp + static_cast<int64_t>(sd.k) * xs + qd, xi);
+          a.x[static_cast<int64_t>(qd) * a.ld + sd.i] = xi;
           // columns beyond the first 2^lg, same lane, unpipelined
           const int KL = 1 << sd.lg;
-          for (int q = (lane & (KL - 1)) + KL; q < a.nrhs; q += KL) {
+          for (int q = qd + KL; q < a.nrhs; q += KL) {
             const int64_t off = static_cast<int64_t>(q) * a.ld;
-            const T s2 = row_dot<T, true>(a.off_col, a.off_val, sd.e, sd.e1, 1, a.x + off,
+            const T s2 = row_dot<T, true>(a.off_pos, a.off_val, sd.e, sd.e1, 1, a.xp + q, xs,
                                           a.spin_limit, a.status, T(0));
-            store_agent(a.x + off + sd.i, canonical((a.b[off + sd.i] - s2) / sd.d));
+            const T x2 = canonical((a.b[off + sd.i] - s2) / sd.d);
+            store_agent(a.xp + static_cast<int64_t>(sd.k) * xs + q, x2);
+            a.x[off + sd.i] = x2;
           }
         }
       } else {
         sum = group_sum(sum, sd.lg);
-        if (sd.k >= 0 && (lane & (G - 1)) == 0)
-          store_agent(a.x + sd.i, canonical((sd.bi - sum) / sd.d));
+        if (sd.k >= 0 && (lane & (G - 1)) == 0) {
+          const T xi = canonical((sd.bi - sum) / sd.d);
+          store_agent(a.xp + sd.k, xi);
+          a.x[sd.i] = xi;
+        }
       }
     } else if (sc.c < 0 && sb.c < 0 && nb.c < 0) {
       return;                         // pipeline drained
@@ -439,7 +488,7 @@ k_self_static(KArgs<T> a, const int* __restrict__ cstart, const int* __restrict_
 // t + blockDim, ... for larger levels); the level barrier is a workgroup
 // barrier.  kLds: x of the system lives in LDS (the barrier then waits for
 // LDS traffic only, so the global loads below stay in flight across it);
-// otherwise x is read from global memory after a full workgroup barrier.
+// otherwise x is read from the caller's x after a full workgroup barrier.
 // Row data of the next two levels are loaded ahead in two raw stages (row
 // bounds, then entries and b), as in the static self-scheduled kernel.
 // One row per thread, entries in stored order: the arithmetic of the other
@@ -542,8 +591,8 @@ k_block(KArgs<T> a, const int* __restrict__ seg_row0, const int* __restrict__ se
 
 // ------------------------------------------------------ self, flag sync
 // Rows of a chunk: wait for the flags of all their dependencies, acquire,
-// solve with plain loads (same per-row order as solve_chunk), release, stamp
-// the rows' flags with this solve's epoch.
+// solve reading the caller's x (same per-row order as solve_chunk), release,
+// stamp the rows' flags with this solve's epoch.
 template <typename T>
 __global__ void __launch_bounds__(256) k_self_flag(KArgs<T> a) {
   const int lane = threadIdx.x & 63;
@@ -585,7 +634,7 @@ __global__ void __launch_bounds__(256) k_self_flag(KArgs<T> a) {
       T sum = T(0);
       if (active)
         sum = row_dot<T, false>(a.off_col, a.off_val, a.off_ptr[k] + gl, a.off_ptr[k + 1], G, a.x,
-                                0, a.status, T(0));
+                                1, 0, a.status, T(0));
       sum = group_sum(sum, lg);
       if (active && gl == 0) {
         const int i = a.pos_row[k];
@@ -597,49 +646,6 @@ __global__ void __launch_bounds__(256) k_self_flag(KArgs<T> a) {
       for (int rr = r0; rr < cnt; rr += rstep)
         __hip_atomic_store(a.flags + a.pos_row[start + rr], epoch, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
-  }
-}
-
-// -------------------------------------------------- multi-RHS (columns)
-// Lanes of a row take right-hand sides (KL = 2^lg lanes, RHS q = lane % KL
-// + multiples of KL); each lane runs the whole row for its column, so the
-// row's indices and values are loaded once per wavefront for all columns.
-template <typename T, bool kPoll>
-__device__ __forceinline__ void multi_rows(const KArgs<T>& a, int c, int lane) {
-  const int start = a.chunk_start[c];
-  const int meta = a.chunk_meta[c];
-  const int cnt = meta & 0xffff, lg = meta >> 16;
-  const int r = lane >> lg, q0 = lane & ((1 << lg) - 1);
-  if (r >= cnt) return;
-  const int k = start + r;
-  const int i = a.pos_row[k];
-  const int e0 = a.off_ptr[k], e1 = a.off_ptr[k + 1];
-  const T d = a.diag[k];
-  for (int q = q0; q < a.nrhs; q += (1 << lg)) {
-    const size_t off = static_cast<size_t>(q) * a.ld;
-    const T sum = row_dot<T, kPoll>(a.off_col, a.off_val, e0, e1, 1, a.x + off, a.spin_limit,
-                                    a.status, T(0));
-    const T xi = canonical((a.b[off + i] - sum) / d);
-    if (kPoll) store_agent(a.x + off + i, xi);
-    else a.x[off + i] = xi;
-  }
-}
-
-template <typename T>
-__global__ void __launch_bounds__(256) k_level_multi(KArgs<T> a, int chunk_begin, int chunk_end) {
-  const int lane = threadIdx.x & 63;
-  const int c = wave_uniform(chunk_begin + static_cast<int>((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
-  if (c >= chunk_end) return;
-  multi_rows<T, false>(a, c, lane);
-}
-
-template <typename T>
-__global__ void __launch_bounds__(256) k_self_multi_value(KArgs<T> a) {
-  const int lane = threadIdx.x & 63;
-  for (;;) {
-    const int c = claim_chunk(a.ticket, a.nchunks, lane);
-    if (c < 0) return;
-    multi_rows<T, true>(a, c, lane);
   }
 }
 
@@ -663,17 +669,14 @@ __global__ void __launch_bounds__(256) k_gather(int64_t noff, int n, const int* 
   }
 }
 
-// x := sentinel over n rows of each column (column stride ld); when save is
-// given, the previous contents are copied there first (in-place solves).
 template <typename T>
-__global__ void __launch_bounds__(256) k_fill_sentinel(T* x, T* save, int n, int ld) {
+__global__ void __launch_bounds__(256) k_fill_sentinel(T* xp, int64_t count) {
   using U = typename Bits<T>::U;
-  const size_t off = static_cast<size_t>(blockIdx.y) * ld;
-  U* xc = reinterpret_cast<U*>(x + off);
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    if (save) save[off + i] = x[off + i];
-    xc[i] = Bits<T>::kSentinel;
-  }
+  U* u = reinterpret_cast<U*>(xp);
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < count;
+       t += stride)
+    u[t] = Bits<T>::kSentinel;
 }
 
 // grad_vals[e] = -grad_b[i] * x[col[e]] over the caller's CSR, 4 lanes a row
@@ -706,18 +709,20 @@ __global__ void __launch_bounds__(256) k_init_scratch(int* ticket, int* status, 
 
 template <typename T> KArgs<T> make_args(const SolveArgs& s) {
   KArgs<T> a;
-  a.chunk_start = s.chunks->start;
-  a.chunk_meta = s.chunks->meta;
-  a.nchunks = s.chunks->count;
+  a.chunk_start = s.chunks ? s.chunks->start : nullptr;
+  a.chunk_meta = s.chunks ? s.chunks->meta : nullptr;
+  a.nchunks = s.chunks ? s.chunks->count : 0;
   a.n = s.plan->n;
   a.noff = s.plan->noff;
   a.off_ptr = s.plan->off_ptr;
   a.off_col = s.plan->off_col;
+  a.off_pos = s.plan->off_pos;
   a.off_val = static_cast<const T*>(s.plan->off_val);
   a.diag = static_cast<const T*>(s.plan->diag);
   a.pos_row = s.plan->pos_row;
   a.b = static_cast<const T*>(s.b);
   a.x = static_cast<T*>(s.x);
+  a.xp = static_cast<T*>(s.xp);
   a.ld = s.ld;
   a.nrhs = s.nrhs;
   a.ticket = s.scratch.ticket;
@@ -734,6 +739,12 @@ inline int blocks_for(int64_t work, int per_block, int cap) {
   return static_cast<int>(b < cap ? b : cap);
 }
 
+template <typename F> int occupancy(F kernel, int wg) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, wg, 0) != hipSuccess) return 1;
+  return nb > 0 ? nb : 1;
+}
+
 }  // namespace
 
 template <typename T>
@@ -746,11 +757,9 @@ hipError_t launch_gather(const DevPlan& p, const T* vals, int* status, hipStream
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_fill_sentinel(T* x, T* save, int n, int nrhs, int ld, hipStream_t s) {
-  if (n == 0 || nrhs == 0) return hipSuccess;
-  dim3 grid(blocks_for(n, 256, 8192), nrhs);
-  k_fill_sentinel<T><<<grid, 256, 0, s>>>(x, save, n, ld);
+template <typename T> hipError_t launch_fill_sentinel(T* xp, int64_t count, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  k_fill_sentinel<T><<<blocks_for(count, 256, 8192), 256, 0, s>>>(xp, count);
   return hipGetLastError();
 }
 
@@ -758,21 +767,16 @@ template <typename T>
 hipError_t launch_level(const SolveArgs& sa, int cb, int ce, hipStream_t s) {
   if (ce <= cb) return hipSuccess;
   const int wpb = sa.wg / 64;
-  k_level<T><<<blocks_for(ce - cb, wpb, 1 << 30), sa.wg, 0, s>>>(make_args<T>(sa), cb, ce);
-  return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_level_multi(const SolveArgs& sa, int cb, int ce, hipStream_t s) {
-  if (ce <= cb) return hipSuccess;
-  const int wpb = sa.wg / 64;
-  k_level_multi<T><<<blocks_for(ce - cb, wpb, 1 << 30), sa.wg, 0, s>>>(make_args<T>(sa), cb, ce);
+  const int grid = blocks_for(ce - cb, wpb, 1 << 30);
+  if (sa.nrhs > 1) k_level<T, true><<<grid, sa.wg, 0, s>>>(make_args<T>(sa), cb, ce);
+  else k_level<T, false><<<grid, sa.wg, 0, s>>>(make_args<T>(sa), cb, ce);
   return hipGetLastError();
 }
 
 template <typename T> hipError_t launch_self_value(const SolveArgs& sa, hipStream_t s) {
   if (sa.chunks->count == 0) return hipSuccess;
-  k_self_value<T><<<sa.grid, sa.wg, 0, s>>>(make_args<T>(sa));
+  if (sa.nrhs > 1) k_self_value<T, true><<<sa.grid, sa.wg, 0, s>>>(make_args<T>(sa));
+  else k_self_value<T, false><<<sa.grid, sa.wg, 0, s>>>(make_args<T>(sa));
   return hipGetLastError();
 }
 
@@ -781,7 +785,9 @@ template <typename T> hipError_t launch_self_static(const SolveArgs& sa, hipStre
   KArgs<T> ka = make_args<T>(sa);
   const int* cs = sa.chunks->start;
   const int* cm = sa.chunks->meta;
-  void* args[] = {&ka, &cs, &cm};
+  const int* wp = sa.wave_ptr;
+  const int* wl = sa.wave_list;
+  void* args[] = {&ka, &cs, &cm, &wp, &wl};
   const void* fn = sa.nrhs > 1 ? reinterpret_cast<const void*>(k_self_static<T, true>)
                                : reinterpret_cast<const void*>(k_self_static<T, false>);
   return hipLaunchCooperativeKernel(fn, dim3(sa.grid), dim3(sa.wg), args, 0, s);
@@ -811,12 +817,6 @@ template <typename T> hipError_t launch_self_flag(const SolveArgs& sa, hipStream
   return hipGetLastError();
 }
 
-template <typename T> hipError_t launch_self_multi_value(const SolveArgs& sa, hipStream_t s) {
-  if (sa.chunks->count == 0) return hipSuccess;
-  k_self_multi_value<T><<<sa.grid, sa.wg, 0, s>>>(make_args<T>(sa));
-  return hipGetLastError();
-}
-
 template <typename T>
 hipError_t launch_grad_vals(int n, const int* row_ptr, const int* col, int unit_diag,
                             const T* grad_b, const T* x, T* grad_vals, hipStream_t s) {
@@ -832,52 +832,31 @@ hipError_t launch_init_scratch(DevScratch sc, int n, hipStream_t s) {
   return hipGetLastError();
 }
 
+// the multi-RHS forms use at least as many registers: size for the smaller
 template <typename T> int self_value_blocks_per_cu(int wg) {
-  int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_self_value<T>, wg, 0) != hipSuccess)
-    return 1;
-  return nb > 0 ? nb : 1;
+  const int a = occupancy(k_self_value<T, false>, wg), b = occupancy(k_self_value<T, true>, wg);
+  return a < b ? a : b;
 }
-template <typename T> int self_flag_blocks_per_cu(int wg) {
-  int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_self_flag<T>, wg, 0) != hipSuccess)
-    return 1;
-  return nb > 0 ? nb : 1;
-}
+template <typename T> int self_flag_blocks_per_cu(int wg) { return occupancy(k_self_flag<T>, wg); }
 template <typename T> int self_static_blocks_per_cu(int wg) {
-  int nb = 0;
-  // the multi-RHS form uses at least as many registers: size for the larger
-  int nb1 = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_self_static<T, false>, wg, 0) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb1, k_self_static<T, true>, wg, 0) != hipSuccess)
-    return 1;
-  nb = nb < nb1 ? nb : nb1;
-  return nb > 0 ? nb : 1;
-}
-template <typename T> int self_multi_blocks_per_cu(int wg) {
-  int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_self_multi_value<T>, wg, 0) != hipSuccess)
-    return 1;
-  return nb > 0 ? nb : 1;
+  const int a = occupancy(k_self_static<T, false>, wg), b = occupancy(k_self_static<T, true>, wg);
+  return a < b ? a : b;
 }
 
-#define SPTRSV_INSTANTIATE(T)                                                                   \
-  template hipError_t launch_gather<T>(const DevPlan&, const T*, int*, hipStream_t);            \
-  template hipError_t launch_fill_sentinel<T>(T*, T*, int, int, int, hipStream_t);              \
-  template hipError_t launch_level<T>(const SolveArgs&, int, int, hipStream_t);                 \
-  template hipError_t launch_level_multi<T>(const SolveArgs&, int, int, hipStream_t);           \
-  template hipError_t launch_self_value<T>(const SolveArgs&, hipStream_t);                      \
-  template hipError_t launch_self_flag<T>(const SolveArgs&, hipStream_t);                       \
-  template hipError_t launch_self_static<T>(const SolveArgs&, hipStream_t);                     \
-  template hipError_t launch_block<T>(const SolveArgs&, const int*, const int*, const int*, int,   \
-                                      int, int, hipStream_t);                                     \
-  template int self_static_blocks_per_cu<T>(int);                                               \
-  template hipError_t launch_self_multi_value<T>(const SolveArgs&, hipStream_t);                \
-  template hipError_t launch_grad_vals<T>(int, const int*, const int*, int, const T*, const T*, \
-                                          T*, hipStream_t);                                     \
-  template int self_value_blocks_per_cu<T>(int);                                                \
-  template int self_flag_blocks_per_cu<T>(int);                                                 \
-  template int self_multi_blocks_per_cu<T>(int);
+#define SPTRSV_INSTANTIATE(T)                                                                    \
+  template hipError_t launch_gather<T>(const DevPlan&, const T*, int*, hipStream_t);             \
+  template hipError_t launch_fill_sentinel<T>(T*, int64_t, hipStream_t);                         \
+  template hipError_t launch_level<T>(const SolveArgs&, int, int, hipStream_t);                  \
+  template hipError_t launch_self_value<T>(const SolveArgs&, hipStream_t);                       \
+  template hipError_t launch_self_flag<T>(const SolveArgs&, hipStream_t);                        \
+  template hipError_t launch_self_static<T>(const SolveArgs&, hipStream_t);                      \
+  template hipError_t launch_block<T>(const SolveArgs&, const int*, const int*, const int*, int, \
+                                      int, int, hipStream_t);                                    \
+  template hipError_t launch_grad_vals<T>(int, const int*, const int*, int, const T*, const T*,  \
+                                          T*, hipStream_t);                                      \
+  template int self_value_blocks_per_cu<T>(int);                                                 \
+  template int self_flag_blocks_per_cu<T>(int);                                                  \
+  template int self_static_blocks_per_cu<T>(int);
 
 SPTRSV_INSTANTIATE(double)
 SPTRSV_INSTANTIATE(float)

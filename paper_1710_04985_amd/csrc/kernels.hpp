@@ -13,7 +13,8 @@ struct DevPlan {
   int nlev = 0;
   int64_t noff = 0;
   int* off_ptr = nullptr;   // [n+1]
-  int* off_col = nullptr;   // [noff]
+  int* off_col = nullptr;   // [noff] column (caller's row number of the dependency)
+  int* off_pos = nullptr;   // [noff] position of the dependency in this plan
   int* off_src = nullptr;   // [noff]
   int* diag_src = nullptr;  // [n]
   int* pos_row = nullptr;   // [n]
@@ -30,7 +31,7 @@ struct DevChunks {
 
 // Per-handle scratch shared by the kernels.
 struct DevScratch {
-  int* ticket = nullptr;     // work counter of the persistent kernels
+  int* ticket = nullptr;     // work counter of the ticket kernels
   int* status = nullptr;     // bit 0: timeout, bit 1: zero pivot
   unsigned* epoch = nullptr; // current flag epoch (flag sync)
   unsigned* flags = nullptr; // [n] per-row ready flags (flag sync)
@@ -38,39 +39,46 @@ struct DevScratch {
 
 enum : int { kStatusTimeout = 1, kStatusZeroPivot = 2 };
 
+// Arguments of one solve.  The solve kernels (except flag sync and block)
+// keep the solution in position order in xp: xp[k * nrhs + q] is column q of
+// the row solved at position k; dependencies are read there through off_pos
+// (rows of one level depend on neighbouring positions of earlier levels, so
+// these gathers coalesce) and every row is also written to the caller's x.
 struct SolveArgs {
   const DevPlan* plan;
   const DevChunks* chunks;
   DevScratch scratch;
-  const void* b;     // right-hand side (already copied aside when b == x)
-  void* x;
+  const void* b;     // caller's right-hand side(s), column stride ld
+  void* x;           // caller's solution(s), column stride ld
+  void* xp;          // [n * nrhs] position-ordered solution (internal)
   int nrhs = 1;
   int ld = 0;
   int spin_limit = 1 << 22;
   int grid = 0;      // persistent workgroups
-  int wg = 256;      // threads per workgroup
+  int wg = 64;       // threads per workgroup
+  const int* wave_ptr = nullptr;   // static schedule: per-wavefront chunk lists (CSR)
+  const int* wave_list = nullptr;
 };
 
 template <typename T> hipError_t launch_gather(const DevPlan& p, const T* vals, int* status,
                                                hipStream_t s);
-// x := sentinel (value sync); save != nullptr keeps a copy of x (in place)
-template <typename T> hipError_t launch_fill_sentinel(T* x, T* save, int n, int nrhs, int ld,
-                                                      hipStream_t s);
-// one launch per level for [chunk_begin, chunk_end) of one level
+// xp[0 .. count) := the readiness sentinel (value sync)
+template <typename T> hipError_t launch_fill_sentinel(T* xp, int64_t count, hipStream_t s);
+// one launch per level for [chunk_begin, chunk_end) of one level (any nrhs)
 template <typename T> hipError_t launch_level(const SolveArgs& a, int chunk_begin, int chunk_end,
                                               hipStream_t s);
+// self-scheduled, value sync, chunks claimed from a ticket (any nrhs)
 template <typename T> hipError_t launch_self_value(const SolveArgs& a, hipStream_t s);
+// self-scheduled, flag sync, ticket (one right-hand side; reads and writes x)
 template <typename T> hipError_t launch_self_flag(const SolveArgs& a, hipStream_t s);
+// self-scheduled, value sync, static round-robin chunks over a cooperative
+// (all-resident) grid, pipelined (any nrhs)
+template <typename T> hipError_t launch_self_static(const SolveArgs& a, hipStream_t s);
 // one workgroup of `threads` per independent system; lds_rows > 0: x of each
 // system in LDS (lds_rows >= the largest system), else in global memory
 template <typename T> hipError_t launch_block(const SolveArgs& a, const int* seg_row0,
                                               const int* seg_base, const int* lev_pos, int nseg,
                                               int threads, int lds_rows, hipStream_t s);
-// value sync, static round-robin chunks, cooperative launch (all resident)
-template <typename T> hipError_t launch_self_static(const SolveArgs& a, hipStream_t s);
-template <typename T> hipError_t launch_level_multi(const SolveArgs& a, int chunk_begin,
-                                                    int chunk_end, hipStream_t s);
-template <typename T> hipError_t launch_self_multi_value(const SolveArgs& a, hipStream_t s);
 template <typename T> hipError_t launch_grad_vals(int n, const int* row_ptr, const int* col,
                                                   int unit_diag, const T* grad_b, const T* x,
                                                   T* grad_vals, hipStream_t s);
@@ -80,7 +88,6 @@ hipError_t launch_init_scratch(DevScratch sc, int n, hipStream_t s);
 // occupancy of the persistent kernels: workgroups per CU at `wg` threads
 template <typename T> int self_value_blocks_per_cu(int wg);
 template <typename T> int self_flag_blocks_per_cu(int wg);
-template <typename T> int self_multi_blocks_per_cu(int wg);
 template <typename T> int self_static_blocks_per_cu(int wg);
 
 }  // namespace sptrsv

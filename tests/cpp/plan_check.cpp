@@ -31,6 +31,10 @@ extern "C" int check_plan(int n, const int* rp, const int* col, int upper, int u
       const int s = p.off_src[o];
       if (s < rp[i] || s >= rp[i + 1] || col[s] != p.off_col[o] || col[s] == i || used[s]++) return 6;
       if (upper ? p.off_col[o] <= i : p.off_col[o] >= i) return 7;
+      // the dependency's position: solved at an earlier level
+      const int q = p.off_pos[o];
+      if (q < 0 || q >= n || p.pos_row[q] != p.off_col[o] || p.level[p.off_col[o]] >= p.level[i])
+        return 17;
     }
     const int d = p.diag_src[k];
     if (unit) {
@@ -57,5 +61,19 @@ extern "C" int check_plan(int n, const int* rp, const int* col, int upper, int u
     }
   }
   if (next != n || t.level_chunk[p.nlev] != (int)t.start.size()) return 15;
+  // wave lists: every chunk exactly once, increasing inside each list
+  for (int W : {1, 3, 8, 16, 64}) {
+    for (int regions : {1, 8}) {
+      std::vector<int> ptr, list;
+      build_wave_lists(t, W, regions, ptr, list);
+      if ((int)ptr.size() != W + 1 || ptr[0] != 0 || ptr[W] != (int)t.start.size()) return 18;
+      std::vector<int> seen(t.start.size(), 0);
+      for (int w = 0; w < W; ++w)
+        for (int q = ptr[w]; q < ptr[w + 1]; ++q) {
+          if (list[q] < 0 || list[q] >= (int)t.start.size() || seen[list[q]]++) return 19;
+          if (q > ptr[w] && list[q] <= list[q - 1]) return 20;
+        }
+    }
+  }
   return 0;
 }

@@ -53,6 +53,44 @@ def pin_levels_closed_form(o):
                 assert np.array_equal(level, _grid_level(dims, upper)), (dims, upper, fn.__name__)
 
 
+def _stencil_level(dims, upper):
+    """Closed form for the 9-point (2-D) and 27-point (3-D) triangles with
+    lexicographic numbering, derived from the longest stencil chains: the
+    diagonal neighbour (x+1, y-1) forces two levels per y step when nx >= 2,
+    and (x+1, y+1, z-1) forces a + 2 per z step, so
+    level = x + a*y (+ b*z), a = 1 + [nx>=2], b = 1 + [nx>=2] + a*[ny>=2];
+    mirrored (n_d - 1 - coordinate) for the upper triangle."""
+    n = int(np.prod(dims))
+    idx = np.arange(n)
+    c, rem = [], idx
+    for d in dims:
+        cc = rem % d
+        c.append((d - 1 - cc) if upper else cc)
+        rem = rem // d
+    a = 1 + (dims[0] >= 2)
+    lev = c[0] + a * c[1]
+    if len(dims) == 3:
+        b = 1 + (dims[0] >= 2) + a * (dims[1] >= 2)
+        lev = lev + b * c[2]
+    return lev
+
+
+def pin_levels_stencil9_27(o):
+    """Levels of the 9-point and 27-point triangles (Sec. 5.1 stencils)."""
+    for dims in [(5, 4), (1, 6), (7, 1), (2, 2), (6, 3)]:
+        for upper in (False, True):
+            T = W.stencil_triangle(dims, 9, upper=upper)
+            level, nlev = o.levels_row(T.row_ptr, T.col_idx, upper)
+            want = _stencil_level(dims, upper)
+            assert np.array_equal(level, want), (dims, upper)
+            assert nlev == int(want.max()) + 1
+    for dims in [(4, 3, 5), (3, 1, 4), (1, 3, 3), (1, 1, 5), (2, 2, 2), (5, 4, 3)]:
+        for upper in (False, True):
+            T = W.stencil_triangle(dims, 27, upper=upper)
+            level, nlev = o.levels_row(T.row_ptr, T.col_idx, upper)
+            assert np.array_equal(level, _stencil_level(dims, upper)), (dims, upper)
+
+
 def _read_golden(name):
     out = {}
     with open(os.path.join(GOLDEN, name)) as f:
@@ -318,6 +356,6 @@ def pin_validate(o):
     assert o.validate(rp2, ci[1:], v[1:], unit_diag=True) == O.OK
 
 
-ALL_PINS = [pin_levels_closed_form, pin_fig1_example, pin_levels_bruteforce, pin_levels_special,
+ALL_PINS = [pin_levels_closed_form, pin_levels_stencil9_27, pin_fig1_example, pin_levels_bruteforce, pin_levels_special,
             pin_level_sets, pin_depcnt, pin_solve_dense, pin_solve_exact_cases,
             pin_backward_error, pin_planted, pin_transpose, pin_multi, pin_adjoint, pin_validate]

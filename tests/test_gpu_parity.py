@@ -35,7 +35,9 @@ def _small_cases():
              ("powerlaw_50k", W.powerlaw_lower(50000, 21, window=5000)),
              ("ilu0_12", W.ilu0_lower((12, 12, 12))),
              ("rand_upper", W.random_triangle(300, 5, density=0.05, upper=True, shuffle_rows=True)),
-             ("rand_lower", W.random_triangle(257, 6, density=0.08, shuffle_rows=True))]
+             ("rand_lower", W.random_triangle(257, 6, density=0.08, shuffle_rows=True)),
+             ("st9_30x20_L", W.stencil_triangle((30, 20), 9)),
+             ("st27_12x11x10_U", W.stencil_triangle((12, 11, 10), 27, upper=True))]
     return cases
 
 
@@ -45,6 +47,8 @@ SCHEDULES = [("level", dict(algo=1)), ("self_value", dict(algo=2, sync=0)),
              ("self_ticket", dict(algo=2, sync=0, assign=1)),
              ("self_static_g4_grid3", dict(algo=2, sync=0, assign=0, group=4, grid=3)),
              ("self_static_wg256", dict(algo=2, sync=0, assign=0, wg=256, grid=2)),
+             ("self_xcd_grid16", dict(algo=2, sync=0, assign=2, grid=16)),
+             ("self_xcd_grid5", dict(algo=2, sync=0, assign=2, grid=5)),
              ("self_flag", dict(algo=2, sync=1)), ("self_value_g1", dict(algo=2, group=1)),
              ("self_value_g8", dict(algo=2, group=8)), ("level_g64", dict(algo=1, group=64)),
              ("self_flag_g16", dict(algo=2, sync=1, group=16)),
@@ -119,8 +123,8 @@ def test_level_equals_self_bitwise(sp, name, T, group, rpl):
         hb = sp.Handle(*dev_tri(T), uplo="U" if T.upper else "L").configure(algo=3)
         for _ in range(5):
             assert bits_equal(hb.solve(b), ref)
-    for sync, assign in ((0, 0), (0, 1), (1, 1)):
-        if assign == 0 and rpl != 1:
+    for sync, assign in ((0, 0), (0, 1), (1, 1), (0, 2)):
+        if assign in (0, 2) and rpl != 1:
             continue                  # static assignment keeps one row per lane
         hs = sp.Handle(*dev_tri(T), uplo="U" if T.upper else "L").configure(
             algo=2, group=group, sync=sync, rows_per_lane=rpl, assign=assign)
@@ -190,7 +194,7 @@ def test_unit_diag(sp):
 
 @pytest.mark.parametrize("nrhs", [1, 3, 16, 70])
 @pytest.mark.parametrize("opts", [dict(algo=1), dict(algo=2), dict(algo=2, assign=1),
-                                  dict(algo=2, grid=3)])
+                                  dict(algo=2, grid=3), dict(algo=2, assign=2, grid=32)])
 def test_multi_rhs(sp, nrhs, opts):
     o = oracle.get()
     T = W.laplacian_triangle((14, 13, 12), upper=True)

@@ -107,6 +107,83 @@ def laplacian_triangle(dims, upper=False, diag=None, off=-1.0, name="") -> Trian
                     meta={"dims": dims})
 
 
+def _stencil_offsets(dims, points):
+    """Neighbour offsets of the 5/9-point (2-D) or 7/27-point (3-D) stencil."""
+    import itertools
+    d = len(dims)
+    if points in (5, 7):
+        offs = []
+        for ax in range(d):
+            for sgn in (-1, 1):
+                o = [0] * d
+                o[ax] = sgn
+                offs.append(tuple(o))
+        return offs
+    if points in (9, 27):
+        return [o for o in itertools.product((-1, 0, 1), repeat=d) if any(o)]
+    raise ValueError("stencil points must be 5/9 (2-D) or 7/27 (3-D)")
+
+
+def stencil_triangle(dims, points, upper=False, diag=None, off=-1.0, name="") -> Triangle:
+    """Lower or upper triangle (diagonal included) of a Laplacian-type stencil
+    operator on a regular grid (Sec. 5.1): 5- or 9-point in 2-D, 7- or
+    27-point in 3-D, lexicographic order (x fastest), off-diagonals `off`,
+    diagonal `diag` (default: the number of neighbours).  An offset belongs to
+    the lower triangle when its last nonzero component (z, then y, then x) is
+    negative."""
+    dims = tuple(int(v) for v in dims)
+    offs = _stencil_offsets(dims, points)
+    if diag is None:
+        diag = float(len(offs))
+    n = int(np.prod(dims))
+    idx = np.arange(n, dtype=np.int64)
+    coords, strides, stride, rem = [], [], 1, idx
+    for dd in dims:
+        coords.append(rem % dd)
+        rem = rem // dd
+        strides.append(stride)
+        stride *= dd
+
+    def is_lower(o):
+        for v in reversed(o):
+            if v:
+                return v < 0
+        return False
+
+    sel = [o for o in offs if is_lower(o) != upper]
+    # ascending column order: sort by linear offset
+    sel.sort(key=lambda o: sum(v * st for v, st in zip(o, strides)))
+    cand_c, cand_m, cand_v = [], [], []
+    lin = [sum(v * st for v, st in zip(o, strides)) for o in sel]
+    before = [o for o, l in zip(sel, lin) if l < 0]
+    after = [o for o, l in zip(sel, lin) if l > 0]
+    for group in (before, None, after):
+        if group is None:
+            cand_c.append(idx)
+            cand_m.append(np.ones(n, dtype=bool))
+            cand_v.append(np.full(n, diag))
+            continue
+        for o in group:
+            m = np.ones(n, dtype=bool)
+            for ax, v in enumerate(o):
+                if v < 0:
+                    m &= coords[ax] >= -v
+                elif v > 0:
+                    m &= coords[ax] < dims[ax] - v
+            cand_c.append(idx + sum(v * st for v, st in zip(o, strides)))
+            cand_m.append(m)
+            cand_v.append(np.full(n, off))
+    rp, ci, v = _assemble(np.stack(cand_c, 1), np.stack(cand_m, 1), np.stack(cand_v, 1), n)
+    return Triangle(n, rp, ci, v, upper=upper,
+                    name=name or "stencil%d_%s_%s" % (points, "x".join(map(str, dims)), "U" if upper else "L"),
+                    meta={"dims": dims, "points": points})
+
+
+# grids of the paper's Table 2 (2-D n = 2^20, 3-D n = 2^21) and their aspect ratios
+TABLE2_2D = [(1024, 1024), (512, 2048), (256, 4096), (128, 8192), (64, 16384)]
+TABLE2_3D = [(128, 128, 128), (64, 128, 256), (64, 64, 512), (32, 64, 1024), (32, 32, 2048)]
+
+
 def ilu0_lower(dims, name="") -> Triangle:
     """Unit lower factor L of ILU(0) of the 5-point (2-D, diagonal 4) or
     7-point (3-D, diagonal 6) Laplacian with off-diagonals -1, natural order.
