@@ -217,7 +217,7 @@ def main():
     infoL = hL.info()
     if infoL["sync"] == sp.SYNC_FLAG:
         kernel_name = "k_self_flag<double>"
-    elif infoL["assign"] == sp.ASSIGN_STATIC:
+    elif infoL["assign"] in (sp.ASSIGN_STATIC, sp.ASSIGN_XCD):
         kernel_name = "k_self_static<double,false>"
     else:
         kernel_name = "k_self_value<double>"

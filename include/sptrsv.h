@@ -69,12 +69,23 @@ typedef enum {
     SPTRSV_ALGO_AUTO = 0,   /* autotuner's choice (heuristic, or timed by sptrsv_tune) */
     SPTRSV_ALGO_LEVEL = 1,  /* level-scheduled: one launch per level (Sec. 4.1) */
     SPTRSV_ALGO_SELF = 2,   /* self-scheduled: one persistent launch (Sec. 4.2) */
-    SPTRSV_ALGO_BLOCK = 3   /* level-scheduled inside one workgroup per independent
+    SPTRSV_ALGO_BLOCK = 3,  /* level-scheduled inside one workgroup per independent
                                system (each system of a batched handle; the whole
                                triangle otherwise): the level barrier is a workgroup
                                barrier, not a launch; x of a system is kept in LDS when
                                the largest system fits.  One right-hand side (several:
                                the level-scheduled solve is used). */
+    SPTRSV_ALGO_COLUMN_LEVEL = 4, /* column-wise, level-scheduled (Sec. 3.2 sweep, Sec. 4.1
+                               LEVC): one launch per level; each finished x_k is pushed
+                               into the accumulators of the rows depending on it with
+                               agent-scope atomic adds */
+    SPTRSV_ALGO_COLUMN_SELF = 5   /* column-wise, self-scheduled (Sec. 4.2 SLFC): one
+                               cooperative launch; a row starts once its arrival counter
+                               reaches its dependency count.  Both column forms add
+                               updates in an order fixed by timing: results agree with
+                               the row-wise solves to rounding, not bit for bit.  One
+                               right-hand side (several: the row-wise self-scheduled
+                               solve is used).  Never chosen by ALGO_AUTO. */
 } sptrsv_algo;
 
 typedef enum {
@@ -104,8 +115,14 @@ typedef enum {
 typedef enum {
     SPTRSV_ASSIGN_STATIC = 0,     /* chunk c goes to wavefront c mod W of a cooperatively
                                      launched (all-resident) grid, pipelined four chunks
-                                     deep; value sync, one or several right-hand sides.  Under HIP graph
-                                     capture the ticket form is used instead. */
+                                     deep; value sync, one or several right-hand sides.  The
+                                     cooperative launch is captured by sptrsv_graph_capture
+                                     (which prepares the per-wavefront chunk lists); under a
+                                     capture the caller opens itself, the ticket form is used
+                                     unless those lists already exist.  A replayed graph
+                                     relies on the whole grid being resident, which holds
+                                     when no other work shares the GPU; otherwise the wait
+                                     limit turns a stall into SPTRSV_ERR_TIMEOUT. */
     SPTRSV_ASSIGN_TICKET = 1,     /* wavefronts claim chunks from an atomic ticket: needs no
                                      co-residency, costs one serialised atomic per chunk */
     SPTRSV_ASSIGN_XCD = 2         /* as STATIC, but each level's chunks are cut into 8

@@ -22,7 +22,7 @@ from ._lib import SpTRSVError, check, lib
 __all__ = ["Handle", "BatchedHandle", "SpTRSVFunction", "sptrsv", "SpTRSVError",
            "ALGO_AUTO", "ALGO_LEVEL", "ALGO_SELF", "SYNC_VALUE", "SYNC_FLAG"]
 
-ALGO_AUTO, ALGO_LEVEL, ALGO_SELF, ALGO_BLOCK = 0, 1, 2, 3
+ALGO_AUTO, ALGO_LEVEL, ALGO_SELF, ALGO_BLOCK, ALGO_COLUMN_LEVEL, ALGO_COLUMN_SELF = 0, 1, 2, 3, 4, 5
 SYNC_VALUE, SYNC_FLAG = 0, 1
 OPT = {"algo": 0, "group": 1, "entries_per_lane": 2, "sync": 3, "spin_limit": 4,
        "grid": 5, "timing": 6, "wg": 7, "rows_per_lane": 8, "assign": 9}

@@ -185,6 +185,23 @@ void build_plan(int n, const int* row_ptr, const int* col, const int* src, bool 
   });
 }
 
+void build_push(const HostPlan& p, std::vector<int>& ptr, std::vector<int>& dst,
+                std::vector<int>& src) {
+  const int n = p.n;
+  ptr.assign(static_cast<size_t>(n) + 1, 0);
+  for (int64_t o = 0; o < p.noff; ++o) ++ptr[p.off_pos[o] + 1];
+  for (int k = 0; k < n; ++k) ptr[k + 1] += ptr[k];
+  dst.resize(p.noff);
+  src.resize(p.noff);
+  std::vector<int> fill(ptr.begin(), ptr.end() - 1);
+  for (int k2 = 0; k2 < n; ++k2)
+    for (int o = p.off_ptr[k2]; o < p.off_ptr[k2 + 1]; ++o) {
+      const int at = fill[p.off_pos[o]]++;
+      dst[at] = k2;
+      src[at] = o;
+    }
+}
+
 void build_chunks(const HostPlan& p, int group, int entries_per_lane, int rows_fixed,
                   int rows_per_lane, ChunkTable& t) {
   t = ChunkTable();

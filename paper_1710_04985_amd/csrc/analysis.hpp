@@ -74,6 +74,14 @@ struct HostPlan {
 void build_plan(int n, const int* row_ptr, const int* col, const int* src, bool upper,
                 bool unit_diag, HostPlan& plan);
 
+// Push lists of a plan (column-wise solves, Sec. 3.2): the transposition of
+// the off-diagonal lists in position space.  For the column solved at
+// position k, entries [ptr[k], ptr[k+1]) give the positions dst[] of the rows
+// that depend on it, ascending, and src[] the index of each dependency in the
+// plan's off-diagonal arrays.
+void build_push(const HostPlan& plan, std::vector<int>& ptr, std::vector<int>& dst,
+                std::vector<int>& src);
+
 // Work chunks: runs of consecutive positions inside ONE level, processed by
 // one 64-lane wavefront.  A chunk holds `count` rows of G = 2^lg lanes each:
 // count * G <= 64 when G > 1; with G = 1 a lane may own up to rows_per_lane

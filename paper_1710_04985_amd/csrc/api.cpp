@@ -17,6 +17,7 @@
 
 #include "analysis.hpp"
 #include "analysis_gpu.hpp"
+#include "column.hpp"
 #include "kernels.hpp"
 
 using namespace sptrsv;
@@ -36,10 +37,19 @@ struct ChunkEntry {
   std::map<std::pair<int, int>, WaveLists> waves;   // (wavefronts, regions)
 };
 
+// Push lists of one plan (column-wise solves) and their chunk tables.
+struct PushState {
+  bool built = false;
+  DevPush d;
+  std::vector<int> h_ptr;
+  std::map<std::pair<int, int>, ChunkEntry> chunks;   // (group, epl)
+};
+
 struct PlanState {
   bool built = false;
   HostPlan h;
   DevPlan d;
+  PushState push;
   void* vals_buf = nullptr;       // [noff + n] values: off-diagonals then diagonal
   // (group, epl, rows_fixed, rows_per_lane)
   std::map<std::tuple<int, int, int, int>, ChunkEntry> chunks;
@@ -92,6 +102,8 @@ struct sptrsv_handle_s {
   int* dev_level = nullptr;
   int* dev_depcnt = nullptr;
   int* dev_jlev = nullptr;
+  void* col_acc = nullptr;         // column-wise solves: accumulators [n]
+  int* col_cnt = nullptr;          // and arrival counts [n]
   int setup = SPTRSV_SETUP_HOST;  // route the analysis took
   double setup_ms = 0.0;           // wall time of the analysis call
   BlockState blk[2];               // block-ordered plans of T and T^T
@@ -155,16 +167,20 @@ void dfree(void* p) {
   if (p) (void)hipFree(p);
 }
 
-void free_chunks(PlanState& ps) {
-  for (auto& kv : ps.chunks) {
-    dfree(kv.second.d.start);
-    dfree(kv.second.d.meta);
-    for (auto& w : kv.second.waves) {
-      dfree(w.second.ptr);
-      dfree(w.second.list);
-    }
+void free_entry(ChunkEntry& e) {
+  dfree(e.d.start);
+  dfree(e.d.meta);
+  for (auto& w : e.waves) {
+    dfree(w.second.ptr);
+    dfree(w.second.list);
   }
+}
+
+void free_chunks(PlanState& ps) {
+  for (auto& kv : ps.chunks) free_entry(kv.second);
   ps.chunks.clear();
+  for (auto& kv : ps.push.chunks) free_entry(kv.second);
+  ps.push.chunks.clear();
 }
 
 // Per-wavefront chunk lists of a static schedule over W wavefronts (built on
@@ -203,6 +219,11 @@ void free_plan(PlanState& ps) {
   dfree(ps.d.diag_src);
   dfree(ps.d.pos_row);
   dfree(ps.vals_buf);
+  dfree(ps.push.d.ptr);
+  dfree(ps.push.d.dst);
+  dfree(ps.push.d.src);
+  dfree(ps.push.d.val);
+  ps.push = PushState();
   ps.d = DevPlan();
   ps.vals_buf = nullptr;
   ps.built = false;
@@ -347,6 +368,10 @@ int build_block(sptrsv_handle_t h, int dir, hipStream_t s) {
   return kOk;
 }
 
+// Uploads chunk table t into a new entry (synchronous copies: the table may
+// be built the first time a solve is issued, and t dies with the caller).
+bool upload_chunks(const ChunkTable& t, ChunkEntry& e, int* err);
+
 ChunkEntry* get_chunks(sptrsv_handle_t h, PlanState& ps, int group, int epl, int rows_fixed,
                        int rpl, int* err) {
   (void)h;
@@ -356,21 +381,42 @@ ChunkEntry* get_chunks(sptrsv_handle_t h, PlanState& ps, int group, int epl, int
   ChunkTable t;
   build_chunks(ps.h, group, epl, rows_fixed, rpl, t);
   ChunkEntry e;
+  if (!upload_chunks(t, e, err)) return nullptr;
+  return &(ps.chunks[key] = e);
+}
+
+// Chunks over the push lists of a plan: rows of one level get lanes by the
+// length of their push list.
+ChunkEntry* get_push_chunks(PlanState& ps, int group, int epl, int* err) {
+  auto key = std::make_pair(group, epl);
+  auto it = ps.push.chunks.find(key);
+  if (it != ps.push.chunks.end()) return &it->second;
+  HostPlan view;
+  view.n = ps.h.n;
+  view.nlev = ps.h.nlev;
+  view.pos_ilev = ps.h.pos_ilev;
+  view.off_ptr = ps.push.h_ptr;
+  ChunkTable t;
+  build_chunks(view, group, epl, 0, 1, t);
+  ChunkEntry e;
+  if (!upload_chunks(t, e, err)) return nullptr;
+  return &(ps.push.chunks[key] = e);
+}
+
+bool upload_chunks(const ChunkTable& t, ChunkEntry& e, int* err) {
   e.level_chunk = t.level_chunk;
   e.h_start = t.start;
   e.h_meta = t.meta;
   e.max_lg = t.max_lg;
   e.d.count = static_cast<int>(t.start.size());
   int st;
-  // synchronous copies: the table may be built the first time a solve is
-  // issued, and the host vectors die with this call
   e.d.start = dalloc<int>(t.start.size(), &st);
   e.d.meta = dalloc<int>(t.meta.size(), &st);
   if (!e.d.start || !e.d.meta) {
     dfree(e.d.start);
     dfree(e.d.meta);
     *err = kErrOom;
-    return nullptr;
+    return false;
   }
   if (!t.start.empty() &&
       (hipMemcpy(e.d.start, t.start.data(), t.start.size() * sizeof(int), hipMemcpyHostToDevice) !=
@@ -380,9 +426,9 @@ ChunkEntry* get_chunks(sptrsv_handle_t h, PlanState& ps, int group, int epl, int
     dfree(e.d.start);
     dfree(e.d.meta);
     *err = kErrHip;
-    return nullptr;
+    return false;
   }
-  return &(ps.chunks[key] = e);
+  return true;
 }
 
 // Schedule of the next solve: the autotuner's choice if one is current,
@@ -417,7 +463,7 @@ int ensure_xp(sptrsv_handle_t h, int64_t elems) {
 }
 
 // Resident workgroups per CU of persistent kernel `kind` (0 value sync, 1 flag
-// sync, 3 static value sync); queried once per (kind, wg) and
+// sync, 3 static value sync, 4 column-wise); queried once per (kind, wg) and
 // cached, so that solves under graph capture make no occupancy query.
 int blocks_per_cu(sptrsv_handle_t h, int kind) {
   const auto key = std::make_pair(kind, h->wg);
@@ -427,7 +473,8 @@ int blocks_per_cu(sptrsv_handle_t h, int kind) {
   const bool dbl = h->dtype == SPTRSV_F64;
   if (kind == 0) per_cu = dbl ? self_value_blocks_per_cu<double>(h->wg) : self_value_blocks_per_cu<float>(h->wg);
   else if (kind == 1) per_cu = dbl ? self_flag_blocks_per_cu<double>(h->wg) : self_flag_blocks_per_cu<float>(h->wg);
-  else per_cu = dbl ? self_static_blocks_per_cu<double>(h->wg) : self_static_blocks_per_cu<float>(h->wg);
+  else if (kind == 3) per_cu = dbl ? self_static_blocks_per_cu<double>(h->wg) : self_static_blocks_per_cu<float>(h->wg);
+  else per_cu = dbl ? column_self_blocks_per_cu<double>(h->wg) : column_self_blocks_per_cu<float>(h->wg);
   h->occupancy[key] = per_cu;
   return per_cu;
 }
@@ -466,26 +513,151 @@ void timing_end(hipStream_t s, hipEvent_t stop) {
   if (stop) (void)hipEventRecord(stop, s);
 }
 
+// Wave-list key of the static schedule: (wavefronts, regions).
+std::pair<int, int> static_key(sptrsv_handle_t h, const ChunkEntry& ch, const Config& c) {
+  const int grid = persistent_grid(h, 3, c.grid, ch.d.count);
+  const int W = grid * (h->wg / 64);
+  const int regions = (c.assign == SPTRSV_ASSIGN_XCD && W % 8 == 0) ? 8 : 1;
+  return {W, regions};
+}
+
+bool static_lists_ready(sptrsv_handle_t h, const ChunkEntry& ch, const Config& c) {
+  return ch.waves.count(static_key(h, ch, c)) != 0;
+}
+
+const WaveLists* static_lists(sptrsv_handle_t h, ChunkEntry& ch, const Config& c, int* err) {
+  const auto key = static_key(h, ch, c);
+  return get_wave_lists(ch, key.first, key.second, err);
+}
+
+bool is_column(int algo) {
+  return algo == SPTRSV_ALGO_COLUMN_LEVEL || algo == SPTRSV_ALGO_COLUMN_SELF;
+}
+
+// Push lists of plan ps, their values, and the column solves' scratch
+// (blocking; built on first use).
+int build_push_state(sptrsv_handle_t h, PlanState& ps, hipStream_t s) {
+  if (ps.push.built) return kOk;
+  if (&ps == &h->fwd)
+    if (const int st = ensure_host_plan(h)) return st;
+  std::vector<int> dst, src;
+  build_push(ps.h, ps.push.h_ptr, dst, src);
+  DevPush& d = ps.push.d;
+  d.nnz = static_cast<int64_t>(dst.size());
+  int err = kOk;
+  d.ptr = dalloc<int>(ps.push.h_ptr.size(), &err);
+  d.dst = dalloc<int>(dst.size(), &err);
+  d.src = dalloc<int>(src.size(), &err);
+  d.val = dalloc<char>(dst.size() * h->vb, &err);
+  if (!h->col_acc) h->col_acc = dalloc<char>(static_cast<size_t>(h->n) * h->vb, &err);
+  if (!h->col_cnt) h->col_cnt = dalloc<int>(static_cast<size_t>(h->n), &err);
+  if (err) return err;
+  HIPCHK(hipMemcpy(d.ptr, ps.push.h_ptr.data(), ps.push.h_ptr.size() * sizeof(int),
+                   hipMemcpyHostToDevice));
+  if (!dst.empty()) {
+    HIPCHK(hipMemcpy(d.dst, dst.data(), dst.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(d.src, src.data(), src.size() * sizeof(int), hipMemcpyHostToDevice));
+  }
+  const hipError_t e = h->dtype == SPTRSV_F64 ? launch_push_gather<double>(ps.d, d, s)
+                                               : launch_push_gather<float>(ps.d, d, s);
+  if (e != hipSuccess) return kErrHip;
+  HIPCHK(hipStreamSynchronize(s));
+  ps.push.built = true;
+  return kOk;
+}
+
+// Re-gathers the push values of every built plan after a value update.
+int regather_push(sptrsv_handle_t h, hipStream_t s) {
+  for (PlanState* ps : {&h->fwd, &h->trn}) {
+    if (!ps->push.built) continue;
+    const hipError_t e = h->dtype == SPTRSV_F64 ? launch_push_gather<double>(ps->d, ps->push.d, s)
+                                                 : launch_push_gather<float>(ps->d, ps->push.d, s);
+    if (e != hipSuccess) return kErrHip;
+  }
+  return kOk;
+}
+
+// Column-wise solve, one right-hand side: LEVC (a launch per level) or SLFC
+// (one cooperative launch, chunk c on wavefront c mod W, or by XCD region).
 template <typename T>
-int solve_impl(sptrsv_handle_t h, PlanState& ps, const Config& c, const void* b, void* x,
+int solve_column(sptrsv_handle_t h, PlanState& ps, const Config& c, const void* b, void* x,
+                 hipStream_t s) {
+  if (!ps.push.built) {
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cap) != hipSuccess) return kErrHip;
+    if (cap != hipStreamCaptureStatusNone) return kErrNotSupported;
+    if (const int st = build_push_state(h, ps, s)) return st;
+  }
+  int err = kOk;
+  ChunkEntry* ch = get_push_chunks(ps, c.group, c.epl, &err);
+  if (!ch) return err;
+  ColumnArgs a;
+  a.plan = &ps.d;
+  a.push = &ps.push.d;
+  a.chunks = &ch->d;
+  a.b = b;
+  a.x = x;
+  a.acc = h->col_acc;
+  a.cnt = h->col_cnt;
+  a.status = h->scratch.status;
+  a.spin_limit = h->spin_limit;
+  a.wg = h->wg;
+  if (launch_column_init<T>(a, s) != hipSuccess) return kErrHip;
+  hipEvent_t stop;
+  if (c.algo == SPTRSV_ALGO_COLUMN_LEVEL) {
+    timing_begin(h, s, &stop);
+    for (int m = 0; m < ps.h.nlev; ++m)
+      if (launch_column_level<T>(a, ch->level_chunk[m], ch->level_chunk[m + 1], s) != hipSuccess)
+        return kErrHip;
+    timing_end(s, stop);
+    return kOk;
+  }
+  a.grid = persistent_grid(h, 4, c.grid, ch->d.count);
+  const int W = a.grid * (h->wg / 64);
+  const int regions = (c.assign == SPTRSV_ASSIGN_XCD && W % 8 == 0) ? 8 : 1;
+  const WaveLists* wl = get_wave_lists(*ch, W, regions, &err);
+  if (!wl) return err;
+  a.wave_ptr = wl->ptr;
+  a.wave_list = wl->list;
+  timing_begin(h, s, &stop);
+  if (launch_column_self<T>(a, s) != hipSuccess) return kErrHip;
+  timing_end(s, stop);
+  return kOk;
+}
+
+template <typename T>
+int solve_impl(sptrsv_handle_t h, PlanState& ps, const Config& c_in, const void* b, void* x,
                int nrhs, int ld, hipStream_t s) {
   const int n = h->n;
   h->last_stream = s;
   if (n == 0 || nrhs == 0) return kOk;
   const bool multi = nrhs > 1;
+  if (is_column(c_in.algo) && !multi) return solve_column<T>(h, ps, c_in, b, x, s);
+  // several right-hand sides under a column-wise schedule: row-wise, self-scheduled
+  Config c = c_in;
+  if (is_column(c.algo)) {
+    c.algo = SPTRSV_ALGO_SELF;
+    c.sync = SPTRSV_SYNC_VALUE;
+  }
   int kl = 1;
   while (kl < nrhs && kl < 64) kl <<= 1;
   int err = kOk;
   // static assignment keeps one row per lane (its pipeline holds one row)
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &cap) != hipSuccess) return kErrHip;
-  const bool use_static = c.algo == SPTRSV_ALGO_SELF &&
-                          (multi || c.sync == SPTRSV_SYNC_VALUE) &&
-                          (c.assign == SPTRSV_ASSIGN_STATIC || c.assign == SPTRSV_ASSIGN_XCD) &&
-                          cap == hipStreamCaptureStatusNone;
+  const bool capturing = cap != hipStreamCaptureStatusNone;
+  bool use_static = c.algo == SPTRSV_ALGO_SELF && (multi || c.sync == SPTRSV_SYNC_VALUE) &&
+                    (c.assign == SPTRSV_ASSIGN_STATIC || c.assign == SPTRSV_ASSIGN_XCD);
   ChunkEntry* ch = multi ? get_chunks(h, ps, 0, 0, 64 / kl, 1, &err)
                          : get_chunks(h, ps, c.group, c.epl, 0, use_static ? 1 : c.rpl, &err);
   if (!ch) return err;
+  // under capture the per-wavefront lists cannot be uploaded: the static
+  // form is captured only when they exist (sptrsv_graph_capture builds them)
+  if (use_static && capturing && !static_lists_ready(h, *ch, c)) {
+    use_static = false;
+    if (!multi && c.rpl != 1 && !(ch = get_chunks(h, ps, c.group, c.epl, 0, c.rpl, &err)))
+      return err;
+  }
   if ((err = ensure_xp(h, static_cast<int64_t>(n) * nrhs))) return err;
   SolveArgs a;
   a.plan = &ps.d;
@@ -541,9 +713,7 @@ int solve_impl(sptrsv_handle_t h, PlanState& ps, const Config& c, const void* b,
     return kErrHip;
   a.grid = persistent_grid(h, use_static ? 3 : 0, c.grid, ch->d.count);
   if (use_static) {
-    const int W = a.grid * (h->wg / 64);
-    const int regions = (c.assign == SPTRSV_ASSIGN_XCD && W % 8 == 0) ? 8 : 1;
-    const WaveLists* wl = get_wave_lists(*ch, W, regions, &err);
+    const WaveLists* wl = static_lists(h, *ch, c, &err);
     if (!wl) return err;
     a.wave_ptr = wl->ptr;
     a.wave_list = wl->list;
@@ -694,6 +864,8 @@ void destroy_handle(sptrsv_handle_t h) {
   dfree(h->dev_level);
   dfree(h->dev_depcnt);
   dfree(h->dev_jlev);
+  dfree(h->col_acc);
+  dfree(h->col_cnt);
   for (auto& pr : h->ev_pool) {
     (void)hipEventDestroy(pr.first);
     (void)hipEventDestroy(pr.second);
@@ -860,6 +1032,7 @@ int sptrsv_update_values(sptrsv_handle_t h, const void* vals, hipStream_t stream
   if (!st && h->trn.built) st = gather(h, h->trn, h->fwd.vals_buf, stream);
   if (!st && h->blk[0].built) st = gather(h, h->blk[0].ps, h->fwd.vals_buf, stream);
   if (!st && h->blk[1].built) st = gather(h, h->blk[1].ps, h->trn.vals_buf, stream);
+  if (!st) st = regather_push(h, stream);
   h->last_stream = stream;
   return st;
 }
@@ -880,6 +1053,7 @@ int sptrsv_update_values_batched(sptrsv_handle_t h, const void* const* vals, hip
   if (!st && h->trn.built) st = gather(h, h->trn, h->fwd.vals_buf, stream);
   if (!st && h->blk[0].built) st = gather(h, h->blk[0].ps, h->fwd.vals_buf, stream);
   if (!st && h->blk[1].built) st = gather(h, h->blk[1].ps, h->trn.vals_buf, stream);
+  if (!st) st = regather_push(h, stream);
   h->last_stream = stream;
   return st;
 }
@@ -933,7 +1107,7 @@ int sptrsv_set_option(sptrsv_handle_t h, sptrsv_option key, int64_t v) {
   switch (key) {
     case SPTRSV_OPT_ALGO:
       if (v != SPTRSV_ALGO_AUTO && v != SPTRSV_ALGO_LEVEL && v != SPTRSV_ALGO_SELF &&
-          v != SPTRSV_ALGO_BLOCK)
+          v != SPTRSV_ALGO_BLOCK && !is_column(static_cast<int>(v)))
         return kErrInvalidArg;
       h->algo = static_cast<int>(v);
       return kOk;
@@ -1035,6 +1209,14 @@ int sptrsv_tune(sptrsv_handle_t h, const void* b, void* x, hipStream_t stream) {
       for (int rpl : {1, 4})
         cand.push_back({SPTRSV_ALGO_LEVEL, 0, epl, SPTRSV_SYNC_VALUE, rpl, 0, SPTRSV_ASSIGN_TICKET});
   }
+  if (h->algo == SPTRSV_ALGO_COLUMN_SELF)
+    for (int epl : {1, 2, 4, 8})
+      for (int grid : {ncu / 2, ncu, 2 * ncu, 4 * ncu})
+        for (int as : {SPTRSV_ASSIGN_STATIC, SPTRSV_ASSIGN_XCD})
+          cand.push_back({SPTRSV_ALGO_COLUMN_SELF, 0, epl, SPTRSV_SYNC_VALUE, 1, grid, as});
+  if (h->algo == SPTRSV_ALGO_COLUMN_LEVEL)
+    for (int epl : {1, 2, 4, 8})
+      cand.push_back({SPTRSV_ALGO_COLUMN_LEVEL, 0, epl, SPTRSV_SYNC_VALUE, 1, 0, SPTRSV_ASSIGN_STATIC});
   if (h->algo == SPTRSV_ALGO_AUTO || h->algo == SPTRSV_ALGO_BLOCK) {
     const int st0 = build_block(h, 0, stream);
     if (st0) return st0;
@@ -1054,7 +1236,9 @@ int sptrsv_tune(sptrsv_handle_t h, const void* b, void* x, hipStream_t stream) {
                                     : solve_impl<float>(h, h->fwd, c, b, x, 1, h->n, stream);
     };
     // level-scheduled trials cost a launch per level: skip them on very deep DAGs
-    if (c.algo == SPTRSV_ALGO_LEVEL && h->fwd.h.nlev > 20000 && cand.size() > 1) continue;
+    if ((c.algo == SPTRSV_ALGO_LEVEL || c.algo == SPTRSV_ALGO_COLUMN_LEVEL) &&
+        h->fwd.h.nlev > 20000 && cand.size() > 1)
+      continue;
     if (hipEventRecord(e0, stream) != hipSuccess) { st = kErrHip; break; }
     if ((st = run())) break;   // warm-up (also builds the chunk table)
     if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
@@ -1192,15 +1376,32 @@ int sptrsv_graph_capture(sptrsv_handle_t h, const void* b, void* x, int transpos
     const int st = build_transpose(h, stream);
     if (st) return st;
   }
-  // make sure the chunk table exists before capture (its upload is synchronous)
+  // make sure the chunk table, the occupancy figures and the static schedule's
+  // per-wavefront lists exist before capture (their uploads are synchronous)
   {
     const Config c = resolve(h);
     int err = kOk;
-    if (h->n > 0 && !get_chunks(h, transpose ? h->trn : h->fwd, c.group, c.epl, 0, c.rpl, &err))
-      return err;
+    PlanState& ps = transpose ? h->trn : h->fwd;
+    if (h->n > 0 && !get_chunks(h, ps, c.group, c.epl, 0, c.rpl, &err)) return err;
+    for (int kind : {0, 1, 3, 4}) (void)blocks_per_cu(h, kind);
+    if (h->n > 0 && c.algo == SPTRSV_ALGO_SELF && c.sync == SPTRSV_SYNC_VALUE &&
+        (c.assign == SPTRSV_ASSIGN_STATIC || c.assign == SPTRSV_ASSIGN_XCD)) {
+      ChunkEntry* ch = get_chunks(h, ps, c.group, c.epl, 0, 1, &err);
+      if (!ch || !static_lists(h, *ch, c, &err)) return err;
+    }
     if (h->n > 0 && c.algo == SPTRSV_ALGO_BLOCK && (err = build_block(h, transpose ? 1 : 0, stream)))
       return err;
-    for (int kind : {0, 1, 3}) (void)blocks_per_cu(h, kind);
+    if (h->n > 0 && is_column(c.algo)) {
+      if ((err = build_push_state(h, ps, stream))) return err;
+      ChunkEntry* ch = get_push_chunks(ps, c.group, c.epl, &err);
+      if (!ch) return err;
+      if (c.algo == SPTRSV_ALGO_COLUMN_SELF) {
+        const int grid = persistent_grid(h, 4, c.grid, ch->d.count);
+        const int W = grid * (h->wg / 64);
+        if (!get_wave_lists(*ch, W, (c.assign == SPTRSV_ASSIGN_XCD && W % 8 == 0) ? 8 : 1, &err))
+          return err;
+      }
+    }
   }
   auto* g = new (std::nothrow) sptrsv_graph_s;
   if (!g) return kErrOom;

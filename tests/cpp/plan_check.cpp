@@ -61,6 +61,38 @@ extern "C" int check_plan(int n, const int* rp, const int* col, int upper, int u
     }
   }
   if (next != n || t.level_chunk[p.nlev] != (int)t.start.size()) return 15;
+  // push lists: the exact transposition of the off-diagonal lists in position
+  // space, ascending dependents; their chunks tile the positions as above
+  {
+    std::vector<int> pptr, pdst, psrc;
+    build_push(p, pptr, pdst, psrc);
+    if ((int)pptr.size() != n + 1 || pptr[0] != 0 || pptr[n] != p.noff) return 21;
+    std::vector<int> hit(p.noff, 0);
+    for (int k = 0; k < n; ++k)
+      for (int e = pptr[k]; e < pptr[k + 1]; ++e) {
+        const int o = psrc[e], k2 = pdst[e];
+        if (o < 0 || o >= p.noff || hit[o]++ || p.off_pos[o] != k) return 22;
+        if (k2 < 0 || k2 >= n || o < p.off_ptr[k2] || o >= p.off_ptr[k2 + 1]) return 23;
+        if (e > pptr[k] && pdst[e - 1] >= k2) return 24;
+        if (p.level[p.pos_row[k2]] <= p.level[p.pos_row[k]]) return 25;
+      }
+    HostPlan view;
+    view.n = n;
+    view.nlev = p.nlev;
+    view.pos_ilev = p.pos_ilev;
+    view.off_ptr = pptr;
+    ChunkTable pt;
+    build_chunks(view, group, epl, 0, 1, pt);
+    int nx = 0;
+    for (int m = 0; m < p.nlev; ++m)
+      for (int c = pt.level_chunk[m]; c < pt.level_chunk[m + 1]; ++c) {
+        const int cnt = pt.meta[c] & 0xffff, lg = pt.meta[c] >> 16;
+        if (pt.start[c] != nx || cnt < 1 || (cnt << lg) > 64) return 26;
+        if (pt.start[c] < p.pos_ilev[m] || pt.start[c] + cnt > p.pos_ilev[m + 1]) return 27;
+        nx += cnt;
+      }
+    if (nx != n) return 28;
+  }
   // wave lists: every chunk exactly once, increasing inside each list
   for (int W : {1, 3, 8, 16, 64}) {
     for (int regions : {1, 8}) {
