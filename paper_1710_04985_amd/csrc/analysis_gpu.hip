@@ -64,25 +64,31 @@ __global__ void __launch_bounds__(256) k_fill_int(int* p, int64_t count, int v) 
 // Levels of Sec. 4.1 (0-based), computed without global synchronisation: the
 // self-scheduled sweep with max(level)+1 in place of the dot product.  Rows
 // are taken in dependency order (ascending for lower, descending for upper)
-// in chunks of 64, one row per lane; workgroup w (one wavefront) takes chunks
-// w, w+W, ... in order on a cooperatively launched, all-resident grid.
+// in chunks of 64, one row per lane; each workgroup (one wavefront) claims
+// the next chunk from a ticket, so chunks are taken in order by running
+// wavefronts and no co-residency is assumed.
 // level[] starts at -1; a row publishes its level with one agent-scope atomic
 // store.  A round polls the row's dependencies outside the chunk (in stored
 // order, resuming at the first one not yet published), then resolves the
 // chain inside the chunk through LDS, one link per step.  A lane keeps up to
 // kInChunk in-chunk dependencies (6-bit lane numbers) packed in a register and
 // rescans its row otherwise.  The lowest unfinished row always has every
-// dependency published and its chunk under way, so the sweep progresses.
+// dependency published and its chunk held by a running wavefront, so the
+// sweep progresses.
 constexpr int kInChunk = 10;
 
 __global__ void __launch_bounds__(64)
 k_levels(int n, const int* __restrict__ rp, const int* __restrict__ col, int upper,
-         int* level, int* flags, int* maxlev, int spin_limit) {
+         int* level, int* flags, int* maxlev, int* ticket, int spin_limit) {
   __shared__ int sl[64];
   const int lane = threadIdx.x;
   const int nch = (n + 63) / 64;
   int wmax = -1;
-  for (int c = blockIdx.x; c < nch; c += gridDim.x) {
+  for (;;) {
+    int c = 0;
+    if (lane == 0) c = atomicAdd(ticket, 1);
+    c = __builtin_amdgcn_readfirstlane(c);
+    if (c >= nch) break;
     const int c0 = c * 64;            // dependency-order index of lane 0
     const int r = c0 + lane;
     const bool live = r < n;
@@ -91,12 +97,17 @@ k_levels(int n, const int* __restrict__ rp, const int* __restrict__ col, int upp
     // in-chunk dependencies
     unsigned long long pk = 0;
     int nin = 0;
-    for (int e2 = a; e2 < e1; ++e2) {
-      const int j = col[e2];
-      const int rj = upper ? n - 1 - j : j;
-      if (j == i || rj < c0) continue;
-      if (nin < kInChunk) pk |= static_cast<unsigned long long>(rj - c0) << (6 * nin);
-      ++nin;
+    for (int e2 = a; e2 < e1; e2 += 8) {
+      int jj[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) jj[q] = e2 + q < e1 ? col[e2 + q] : i;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int rj = upper ? n - 1 - jj[q] : jj[q];
+        if (jj[q] == i || rj < c0) continue;
+        if (nin < kInChunk) pk |= static_cast<unsigned long long>(rj - c0) << (6 * nin);
+        ++nin;
+      }
     }
     int e = a;                        // cursor over the entries outside the chunk
     int lvl = 0;
@@ -105,16 +116,36 @@ k_levels(int n, const int* __restrict__ rp, const int* __restrict__ col, int upp
     for (int round = 0;; ++round) {
       bool gready = true;
       if (!done) {
-        for (; e < e1; ++e) {
-          const int j = col[e];
-          const int rj = upper ? n - 1 - j : j;
-          if (j == i || rj >= c0) continue;
-          const int v = __hip_atomic_load(level + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          if (v < 0) {
+        // eight entries at a time: their columns, then their levels, in flight together
+        while (e < e1) {
+          int v8[8];
+          bool need[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            const int j = e + q < e1 ? col[e + q] : i;
+            const int rj = upper ? n - 1 - j : j;
+            need[q] = j != i && rj < c0;
+            v8[q] = need[q] ? __hip_atomic_load(level + j, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT)
+                            : 0;
+          }
+          int adv = 0;
+          bool stop = false;
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            if (stop || e + q >= e1) continue;
+            if (need[q] && v8[q] < 0) {
+              stop = true;
+            } else {
+              if (need[q]) lvl = v8[q] + 1 > lvl ? v8[q] + 1 : lvl;
+              ++adv;
+            }
+          }
+          e += adv;
+          if (stop) {
             gready = false;
             break;
           }
-          lvl = v + 1 > lvl ? v + 1 : lvl;
         }
       }
       for (int step = 0; step < 65; ++step) {
@@ -258,7 +289,7 @@ template <typename T> int dmalloc(T** p, int64_t count) {
 
 struct Temps {
   int* flags = nullptr;
-  int* counters = nullptr;   // [0] max row length, [1] max level
+  int* counters = nullptr;   // [0] max row length, [1] max level, [2] chunk ticket
   unsigned long long* key = nullptr;
   unsigned long long* key_s = nullptr;
   int* rows = nullptr;
@@ -309,13 +340,13 @@ int device_analysis(int n, int64_t nnz, const int* row_ptr, const int* col, bool
   out.n = n;
   Temps tp;
   DALLOC(tp.flags, 1);
-  DALLOC(tp.counters, 2);
+  DALLOC(tp.counters, 3);
   DALLOC(out.depcnt, n);
   DALLOC(out.level, n);
-  int zero2[2] = {0, -1};
+  int zero2[3] = {0, -1, 0};
   int zero = 0;
   DCHK(hipMemcpyAsync(tp.flags, &zero, sizeof(int), hipMemcpyHostToDevice, s));
-  DCHK(hipMemcpyAsync(tp.counters, zero2, 2 * sizeof(int), hipMemcpyHostToDevice, s));
+  DCHK(hipMemcpyAsync(tp.counters, zero2, 3 * sizeof(int), hipMemcpyHostToDevice, s));
   k_check<<<blocks(n), 256, 0, s>>>(n, nnz, row_ptr, col, upper, unit_diag, out.depcnt, tp.flags,
                                      tp.counters);
   DCHK(hipGetLastError());
@@ -335,18 +366,12 @@ int device_analysis(int n, int64_t nnz, const int* row_ptr, const int* col, bool
     DCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_levels, 64, 0));
     const int nch = (n + 63) / 64;
     const int grid = std::max(1, std::min(nch, std::max(1, per_cu) * num_cu));
-    int un = upper ? 1 : 0;
-    int spin = 1 << 24;
-    int* lv = out.level;
-    int* fl = tp.flags;
-    int* ml = tp.counters + 1;
-    void* args[] = {&n, const_cast<int**>(&row_ptr), const_cast<int**>(&col), &un, &lv, &fl, &ml,
-                    &spin};
-    DCHK(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_levels), dim3(grid), dim3(64),
-                                    args, 0, s));
+    k_levels<<<grid, 64, 0, s>>>(n, row_ptr, col, upper ? 1 : 0, out.level, tp.flags,
+                                 tp.counters + 1, tp.counters + 2, 1 << 24);
+    DCHK(hipGetLastError());
   }
-  int counters[2];
-  DCHK(hipMemcpyAsync(counters, tp.counters, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+  int counters[3];
+  DCHK(hipMemcpyAsync(counters, tp.counters, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
   DCHK(hipMemcpyAsync(&flags, tp.flags, sizeof(int), hipMemcpyDeviceToHost, s));
   DCHK(hipStreamSynchronize(s));
   if (flags & kFlagTimeout) {

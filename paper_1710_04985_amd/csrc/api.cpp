@@ -480,13 +480,16 @@ int blocks_per_cu(sptrsv_handle_t h, int kind) {
 }
 
 // Workgroups of a persistent launch: the explicit choice, else one
-// wavefront per CU; never more than resident capacity or than chunks need.
+// wavefront per CU; never more than chunks need, than the occupancy figure
+// allows, or than 8 wavefronts per CU (a quarter of a CU's wave slots, so
+// the all-resident schedules keep a wide margin below capacity).
 int persistent_grid(sptrsv_handle_t h, int kind, int grid, int nchunks) {
   const int per_cu = blocks_per_cu(h, kind);
   const int waves_per_block = h->wg / 64;
   const int need = (nchunks + waves_per_block - 1) / waves_per_block;
   int g = grid > 0 ? grid : (h->num_cu + waves_per_block - 1) / waves_per_block;
-  g = std::min(g, per_cu * h->num_cu);
+  const int cap_per_cu = std::max(1, std::min(per_cu, 8 / waves_per_block));
+  g = std::min(g, cap_per_cu * h->num_cu);
   return std::max(1, std::min(g, need));
 }
 

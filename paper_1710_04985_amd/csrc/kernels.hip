@@ -74,22 +74,6 @@ __device__ __forceinline__ void raise_status(int* s, int bit) {
   __hip_atomic_fetch_or(s, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Bounded wait for a published value (value sync).  After spin_limit polls,
-// or once another wavefront has timed out, the wait gives up: TIMEOUT is
-// raised and a quiet NaN is used, so every dependent finishes and the grid
-// drains.
-template <typename T>
-__device__ __attribute__((noinline)) T wait_value(const T* p, int spin_limit, int* status) {
-  for (int s = 1; s <= spin_limit; ++s) {
-    __builtin_amdgcn_s_sleep(1);
-    const T v = load_agent(p);
-    if (!is_sentinel(v)) return v;
-    if ((s & 15) == 1 && (load_status(status) & kStatusTimeout)) break;
-  }
-  raise_status(status, kStatusTimeout);
-  return __builtin_nan("");
-}
-
 // Bounded wait for flag[j] == epoch (flag sync); false on timeout.
 __device__ __attribute__((noinline)) bool wait_flag(const unsigned* f, unsigned epoch,
                                                     int spin_limit, int* status) {
@@ -102,6 +86,57 @@ __device__ __attribute__((noinline)) bool wait_flag(const unsigned* f, unsigned 
   }
   raise_status(status, kStatusTimeout);
   return false;
+}
+
+// Joint bounded wait for the dependencies j[0..N) whose values in xv are
+// still the sentinel.  Every round polls all N values (unconditionally, so
+// the number of loads in flight is fixed), and two rounds overlap: round r+1
+// is issued before round r's results are examined.  A value published while
+// a poll is in flight is then seen about one interval later instead of one
+// full round trip later, and the wait ends about one round trip after the
+// last pending value is published.  After spin_limit rounds, or once another
+// wavefront has timed out, TIMEOUT is raised and the pending values become
+// quiet NaNs, so the grid drains.
+template <typename T, int N>
+__device__ __forceinline__ void wait_values(const T* xr, int xs, const int (&j)[N], T (&xv)[N],
+                                            int spin_limit, int* status) {
+  unsigned pend = 0;
+#pragma unroll
+  for (int q = 0; q < N; ++q)
+    if (j[q] >= 0 && is_sentinel(xv[q])) pend |= 1u << q;
+  if (!pend) return;
+  const T* p[N];
+#pragma unroll
+  for (int q = 0; q < N; ++q) p[q] = xr + static_cast<int64_t>(j[q] >= 0 ? j[q] : 0) * xs;
+  // two register sets polled in turn, so no copy forces a wait on the newer set
+  T pa[N], pb[N];
+  auto take = [&](const T (&v)[N]) {
+#pragma unroll
+    for (int q = 0; q < N; ++q)
+      if (((pend >> q) & 1u) && !is_sentinel(v[q])) {
+        xv[q] = v[q];
+        pend &= ~(1u << q);
+      }
+  };
+#pragma unroll
+  for (int q = 0; q < N; ++q) pa[q] = load_agent(p[q]);
+  for (int s = 1; s <= spin_limit; s += 2) {
+    __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+    for (int q = 0; q < N; ++q) pb[q] = load_agent(p[q]);
+    take(pa);
+    if (!pend) return;
+    __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+    for (int q = 0; q < N; ++q) pa[q] = load_agent(p[q]);
+    take(pb);
+    if (!pend) return;
+    if ((s & 15) == 1 && (load_status(status) & kStatusTimeout)) break;
+  }
+  raise_status(status, kStatusTimeout);
+#pragma unroll
+  for (int q = 0; q < N; ++q)
+    if ((pend >> q) & 1u) xv[q] = __builtin_nan("");
 }
 
 template <typename T> struct KArgs {
@@ -150,12 +185,7 @@ __device__ __forceinline__ T row_dot(const int* __restrict__ idx, const T* __res
       if (j[u] >= 0) xv[u] = kPoll ? load_agent(p) : *p;
       else xv[u] = T(0);
     }
-    if constexpr (kPoll) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (j[u] >= 0 && is_sentinel(xv[u]))
-          xv[u] = wait_value(xr + static_cast<int64_t>(j[u]) * xs, spin_limit, status);
-    }
+    if constexpr (kPoll) wait_values<T, 4>(xr, xs, j, xv, spin_limit, status);
 #pragma unroll
     for (int u = 0; u < 4; ++u)
       if (j[u] >= 0) sum = __builtin_fma(v[u], xv[u], sum);
@@ -225,12 +255,11 @@ __device__ __forceinline__ void solve_chunk(const KArgs<T>& a, int start, int me
     for (int u = 0; u < R; ++u) {
       if (k[u] < 0) continue;
       T sum = T(0);
+      if (kPoll) wait_values<T, E>(a.xp, 1, j[u], xv[u], a.spin_limit, a.status);
 #pragma unroll
       for (int q = 0; q < E; ++q) {
         if (j[u][q] < 0) continue;
-        T xx = xv[u][q];
-        if (kPoll && is_sentinel(xx)) xx = wait_value(a.xp + j[u][q], a.spin_limit, a.status);
-        sum = __builtin_fma(v[u][q], xx, sum);
+        sum = __builtin_fma(v[u][q], xv[u][q], sum);
       }
       if (e1[u] > e0[u] + E)
         sum = row_dot<T, kPoll>(a.off_pos, a.off_val, e0[u] + E, e1[u], 1, a.xp, 1, a.spin_limit,
@@ -437,13 +466,11 @@ k_self_static(KArgs<T> a, const int* __restrict__ cstart, const int* __restrict_
       const int G = kMulti ? 1 : 1 << sd.lg;
       T sum = T(0);
       if (sd.k >= 0) {
+        wait_values<T, 4>(xq, xs, sd.j, xv, a.spin_limit, a.status);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           if (sd.j[q] < 0) continue;
-          T xx = xv[q];
-          if (is_sentinel(xx))
-            xx = wait_value(xq + static_cast<int64_t>(sd.j[q]) * xs, a.spin_limit, a.status);
-          sum = __builtin_fma(sd.v[q], xx, sum);
+          sum = __builtin_fma(sd.v[q], xv[q], sum);
         }
         if (sd.e + 4 * G < sd.e1)
           sum = row_dot<T, true>(a.off_pos, a.off_val, sd.e + 4 * G, sd.e1, G, xq, xs,
