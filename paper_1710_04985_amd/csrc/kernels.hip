@@ -164,31 +164,56 @@ template <typename T> struct KArgs {
 };
 
 // Continues `sum` over the lane's entries e, e+G, e+2G, ... < e1 of one row,
-// four entries in flight at a time, reading x at xr[idx[entry] * xs].
+// four entries at a time, reading x at xr[idx[entry] * xs].  The indices and
+// values of the next four entries are loaded while the x gathers of the
+// current four are in flight, so a long row costs about one load round trip
+// per four entries of the lane.  Accumulation is in entry order.
 // kPoll: atomic agent-scope loads, sentinel values are waited for.
 template <typename T, bool kPoll>
 __device__ __forceinline__ T row_dot(const int* __restrict__ idx, const T* __restrict__ off_val,
                                      int e, int e1, int G, const T* xr, int xs, int spin_limit,
                                      int* status, T sum) {
-  for (; e < e1; e += 4 * G) {
-    int j[4];
-    T v[4], xv[4];
+  constexpr int B = 4;
+  if (e >= e1) return sum;
+  int j[B];
+  T v[B];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int ee = e + u * G;
-      j[u] = ee < e1 ? idx[ee] : -1;
-      v[u] = ee < e1 ? off_val[ee] : T(0);
-    }
+  for (int u = 0; u < B; ++u) {
+    const int ee = e + u * G;
+    j[u] = ee < e1 ? idx[ee] : -1;
+    v[u] = ee < e1 ? off_val[ee] : T(0);
+  }
+  for (;;) {
+    T xv[B];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < B; ++u) {
       const T* p = xr + static_cast<int64_t>(j[u]) * xs;
       if (j[u] >= 0) xv[u] = kPoll ? load_agent(p) : *p;
       else xv[u] = T(0);
     }
-    if constexpr (kPoll) wait_values<T, 4>(xr, xs, j, xv, spin_limit, status);
+    // next batch, only if the lane has one (its loads overlap the gathers above)
+    const bool more = e + B * G < e1;
+    int jn[B];
+    T vn[B];
+    if (more) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < B; ++u) {
+        const int ee = e + (B + u) * G;
+        jn[u] = ee < e1 ? idx[ee] : -1;
+        vn[u] = ee < e1 ? off_val[ee] : T(0);
+      }
+    }
+    if constexpr (kPoll) wait_values<T, B>(xr, xs, j, xv, spin_limit, status);
+#pragma unroll
+    for (int u = 0; u < B; ++u)
       if (j[u] >= 0) sum = __builtin_fma(v[u], xv[u], sum);
+    if (!more) break;
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      j[u] = jn[u];
+      v[u] = vn[u];
+    }
+    e += B * G;
   }
   return sum;
 }
