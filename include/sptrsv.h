@@ -109,7 +109,13 @@ typedef enum {
                                      default 64) */
     SPTRSV_OPT_ROWS_PER_LANE = 8, /* rows one lane owns when a row gets one lane (1..4,
                                      default 1): fewer, larger work chunks */
-    SPTRSV_OPT_ASSIGN = 9         /* sptrsv_assign: how self-scheduled wavefronts get chunks */
+    SPTRSV_OPT_ASSIGN = 9,        /* sptrsv_assign: how self-scheduled wavefronts get chunks */
+    SPTRSV_OPT_POLL = 10          /* how a waiting lane polls its dependencies (value sync):
+                                     1 (default) = two rounds in flight over all of its
+                                     slots, so a value is seen soon after it lands; 0 = one
+                                     round at a time over the pending slots only (less
+                                     polling traffic, better when most dependencies are
+                                     already available) */
 } sptrsv_option;
 
 typedef enum {
@@ -257,11 +263,11 @@ int sptrsv_get_info(sptrsv_handle_t h, int32_t *n, int64_t *nnz, int32_t *nlev,
 /* The schedule the next solve will use (resolved: the autotuner's choice if
  * current, else the options): sptrsv_algo, lanes per row (0 = by row
  * length), entries per lane of the length rule, sptrsv_sync, rows per lane,
- * persistent workgroups (0 = default), sptrsv_assign.  Any pointer may be
- * NULL. */
+ * persistent workgroups (0 = default), sptrsv_assign, polling mode
+ * (SPTRSV_OPT_POLL).  Any pointer may be NULL. */
 int sptrsv_get_schedule(sptrsv_handle_t h, int32_t *algo, int32_t *group,
                         int32_t *entries_per_lane, int32_t *sync, int32_t *rows_per_lane,
-                        int32_t *grid, int32_t *assign);
+                        int32_t *grid, int32_t *assign, int32_t *poll);
 
 /* Copy the analysis to HOST buffers (any may be NULL): level int32[n],
  * ilev int32[nlev+1], jlev int32[n] (rows by (level, row)), depcnt int32[n]

@@ -74,6 +74,7 @@ struct Config {
   int rpl;    // rows per lane
   int grid;   // persistent workgroups, 0 = default
   int assign; // sptrsv_assign
+  int poll = 1;  // waits: 1 overlapped rounds over all slots, 0 single rounds of pending ones
 };
 
 std::mutex g_tune_mu;
@@ -127,6 +128,7 @@ struct sptrsv_handle_s {
   int wg = 64;
   int rpl = 1;
   int assign = SPTRSV_ASSIGN_STATIC;
+  int poll = 1;
   // autotuner result
   bool tuned = false;
   Config tuned_cfg{SPTRSV_ALGO_SELF, 0, 4, SPTRSV_SYNC_VALUE, 1, 0, SPTRSV_ASSIGN_STATIC};
@@ -437,6 +439,7 @@ bool upload_chunks(const ChunkTable& t, ChunkEntry& e, int* err) {
 Config resolve(sptrsv_handle_t h) {
   if (h->tuned) return h->tuned_cfg;
   Config c{h->algo, h->group, h->epl, h->sync, h->rpl, h->grid, h->assign};
+  c.poll = h->poll;
   if (c.algo == SPTRSV_ALGO_AUTO) c.algo = SPTRSV_ALGO_SELF;
   return c;
 }
@@ -672,6 +675,7 @@ int solve_impl(sptrsv_handle_t h, PlanState& ps, const Config& c_in, const void*
   a.nrhs = nrhs;
   a.ld = ld;
   a.spin_limit = h->spin_limit;
+  a.poll = c.poll;
   a.wg = h->wg;
   hipEvent_t stop;
   if (c.algo == SPTRSV_ALGO_BLOCK && !multi) {
@@ -1150,6 +1154,10 @@ int sptrsv_set_option(sptrsv_handle_t h, sptrsv_option key, int64_t v) {
         return kErrInvalidArg;
       h->assign = static_cast<int>(v);
       return kOk;
+    case SPTRSV_OPT_POLL:
+      if (v != 0 && v != 1) return kErrInvalidArg;
+      h->poll = static_cast<int>(v);
+      return kOk;
   }
   return kErrInvalidArg;
 }
@@ -1167,6 +1175,7 @@ int sptrsv_get_option(sptrsv_handle_t h, sptrsv_option key, int64_t* v) {
     case SPTRSV_OPT_WG: *v = h->wg; return kOk;
     case SPTRSV_OPT_ROWS_PER_LANE: *v = h->rpl; return kOk;
     case SPTRSV_OPT_ASSIGN: *v = h->assign; return kOk;
+    case SPTRSV_OPT_POLL: *v = h->poll; return kOk;
   }
   return kErrInvalidArg;
 }
@@ -1200,8 +1209,13 @@ int sptrsv_tune(sptrsv_handle_t h, const void* b, void* x, hipStream_t stream) {
   for (int epl : {1, 2, 4, 8}) {
     if (self_ok) {
       for (int grid : {ncu / 2, ncu, 2 * ncu, 4 * ncu}) {
-        cand.push_back({SPTRSV_ALGO_SELF, 0, epl, SPTRSV_SYNC_VALUE, 1, grid, SPTRSV_ASSIGN_STATIC});
-        cand.push_back({SPTRSV_ALGO_SELF, 0, epl, SPTRSV_SYNC_VALUE, 1, grid, SPTRSV_ASSIGN_XCD});
+        for (int poll : {1, 0}) {
+          Config c1{SPTRSV_ALGO_SELF, 0, epl, SPTRSV_SYNC_VALUE, 1, grid, SPTRSV_ASSIGN_STATIC};
+          Config c2{SPTRSV_ALGO_SELF, 0, epl, SPTRSV_SYNC_VALUE, 1, grid, SPTRSV_ASSIGN_XCD};
+          c1.poll = c2.poll = poll;
+          cand.push_back(c1);
+          cand.push_back(c2);
+        }
       }
       for (int rpl : {1, 4})
         cand.push_back({SPTRSV_ALGO_SELF, 0, epl, SPTRSV_SYNC_VALUE, rpl, ncu, SPTRSV_ASSIGN_TICKET});
@@ -1293,7 +1307,7 @@ int sptrsv_get_info(sptrsv_handle_t h, int32_t* n, int64_t* nnz, int32_t* nlev, 
 
 int sptrsv_get_schedule(sptrsv_handle_t h, int32_t* algo, int32_t* group,
                         int32_t* entries_per_lane, int32_t* sync, int32_t* rows_per_lane,
-                        int32_t* grid, int32_t* assign) {
+                        int32_t* grid, int32_t* assign, int32_t* poll) {
   if (!h) return kErrInvalidArg;
   const Config c = resolve(h);
   if (algo) *algo = c.algo;
@@ -1303,6 +1317,7 @@ int sptrsv_get_schedule(sptrsv_handle_t h, int32_t* algo, int32_t* group,
   if (rows_per_lane) *rows_per_lane = c.rpl;
   if (grid) *grid = c.grid;
   if (assign) *assign = c.assign;
+  if (poll) *poll = c.poll;
   return kOk;
 }
 

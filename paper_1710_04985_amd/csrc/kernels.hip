@@ -89,17 +89,22 @@ __device__ __attribute__((noinline)) bool wait_flag(const unsigned* f, unsigned 
 }
 
 // Joint bounded wait for the dependencies j[0..N) whose values in xv are
-// still the sentinel.  Every round polls all N values (unconditionally, so
-// the number of loads in flight is fixed), and two rounds overlap: round r+1
-// is issued before round r's results are examined.  A value published while
-// a poll is in flight is then seen about one interval later instead of one
-// full round trip later, and the wait ends about one round trip after the
-// last pending value is published.  After spin_limit rounds, or once another
-// wavefront has timed out, TIMEOUT is raised and the pending values become
-// quiet NaNs, so the grid drains.
+// still the sentinel.  Two polling modes (a schedule option):
+//  overlap: every round polls all N values (unconditionally, so the number of
+//    loads in flight is fixed) and two rounds overlap: round r+1 is issued
+//    before round r's results are examined, so a value published while a poll
+//    is in flight is seen about one interval later instead of one full round
+//    trip later.  Best when most of a lane's dependencies are pending
+//    (mesh-like triangles).
+//  single: one round at a time, polling only the values still pending.  Less
+//    polling traffic; best when most dependencies are already available
+//    (irregular triangles whose dependencies span many levels).
+// Either way the wait ends soon after the last pending value is published.
+// After spin_limit rounds, or once another wavefront has timed out, TIMEOUT
+// is raised and the pending values become quiet NaNs, so the grid drains.
 template <typename T, int N>
 __device__ __forceinline__ void wait_values(const T* xr, int xs, const int (&j)[N], T (&xv)[N],
-                                            int spin_limit, int* status) {
+                                            int spin_limit, int* status, bool overlap) {
   unsigned pend = 0;
 #pragma unroll
   for (int q = 0; q < N; ++q)
@@ -108,8 +113,6 @@ __device__ __forceinline__ void wait_values(const T* xr, int xs, const int (&j)[
   const T* p[N];
 #pragma unroll
   for (int q = 0; q < N; ++q) p[q] = xr + static_cast<int64_t>(j[q] >= 0 ? j[q] : 0) * xs;
-  // two register sets polled in turn, so no copy forces a wait on the newer set
-  T pa[N], pb[N];
   auto take = [&](const T (&v)[N]) {
 #pragma unroll
     for (int q = 0; q < N; ++q)
@@ -118,20 +121,34 @@ __device__ __forceinline__ void wait_values(const T* xr, int xs, const int (&j)[
         pend &= ~(1u << q);
       }
   };
-#pragma unroll
-  for (int q = 0; q < N; ++q) pa[q] = load_agent(p[q]);
-  for (int s = 1; s <= spin_limit; s += 2) {
-    __builtin_amdgcn_s_sleep(1);
-#pragma unroll
-    for (int q = 0; q < N; ++q) pb[q] = load_agent(p[q]);
-    take(pa);
-    if (!pend) return;
-    __builtin_amdgcn_s_sleep(1);
+  if (overlap) {
+    // two register sets polled in turn, so no copy forces a wait on the newer set
+    T pa[N], pb[N];
 #pragma unroll
     for (int q = 0; q < N; ++q) pa[q] = load_agent(p[q]);
-    take(pb);
-    if (!pend) return;
-    if ((s & 15) == 1 && (load_status(status) & kStatusTimeout)) break;
+    for (int s = 1; s <= spin_limit; s += 2) {
+      __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+      for (int q = 0; q < N; ++q) pb[q] = load_agent(p[q]);
+      take(pa);
+      if (!pend) return;
+      __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+      for (int q = 0; q < N; ++q) pa[q] = load_agent(p[q]);
+      take(pb);
+      if (!pend) return;
+      if ((s & 15) == 1 && (load_status(status) & kStatusTimeout)) break;
+    }
+  } else {
+    for (int s = 1; s <= spin_limit; ++s) {
+      __builtin_amdgcn_s_sleep(1);
+      T nv[N];
+#pragma unroll
+      for (int q = 0; q < N; ++q) nv[q] = (pend >> q) & 1u ? load_agent(p[q]) : xv[q];
+      take(nv);
+      if (!pend) return;
+      if ((s & 15) == 1 && (load_status(status) & kStatusTimeout)) break;
+    }
   }
   raise_status(status, kStatusTimeout);
 #pragma unroll
@@ -161,6 +178,7 @@ template <typename T> struct KArgs {
   unsigned* epoch;
   unsigned* flags;
   int spin_limit;
+  int poll;          // 1: overlapped polling of all slots, 0: single rounds of pending ones
 };
 
 // Continues `sum` over the lane's entries e, e+G, e+2G, ... < e1 of one row,
@@ -172,7 +190,7 @@ template <typename T> struct KArgs {
 template <typename T, bool kPoll>
 __device__ __forceinline__ T row_dot(const int* __restrict__ idx, const T* __restrict__ off_val,
                                      int e, int e1, int G, const T* xr, int xs, int spin_limit,
-                                     int* status, T sum) {
+                                     int* status, bool overlap, T sum) {
   constexpr int B = 4;
   if (e >= e1) return sum;
   int j[B];
@@ -203,7 +221,7 @@ __device__ __forceinline__ T row_dot(const int* __restrict__ idx, const T* __res
         vn[u] = ee < e1 ? off_val[ee] : T(0);
       }
     }
-    if constexpr (kPoll) wait_values<T, B>(xr, xs, j, xv, spin_limit, status);
+    if constexpr (kPoll) wait_values<T, B>(xr, xs, j, xv, spin_limit, status, overlap);
 #pragma unroll
     for (int u = 0; u < B; ++u)
       if (j[u] >= 0) sum = __builtin_fma(v[u], xv[u], sum);
@@ -280,7 +298,7 @@ __device__ __forceinline__ void solve_chunk(const KArgs<T>& a, int start, int me
     for (int u = 0; u < R; ++u) {
       if (k[u] < 0) continue;
       T sum = T(0);
-      if (kPoll) wait_values<T, E>(a.xp, 1, j[u], xv[u], a.spin_limit, a.status);
+      if (kPoll) wait_values<T, E>(a.xp, 1, j[u], xv[u], a.spin_limit, a.status, a.poll != 0);
 #pragma unroll
       for (int q = 0; q < E; ++q) {
         if (j[u][q] < 0) continue;
@@ -288,7 +306,7 @@ __device__ __forceinline__ void solve_chunk(const KArgs<T>& a, int start, int me
       }
       if (e1[u] > e0[u] + E)
         sum = row_dot<T, kPoll>(a.off_pos, a.off_val, e0[u] + E, e1[u], 1, a.xp, 1, a.spin_limit,
-                                a.status, sum);
+                                a.status, a.poll != 0, sum);
       const T xi = canonical((bi[u] - sum) / di[u]);
       publish<T, kPoll>(a.xp + k[u], xi);
       a.x[i[u]] = xi;
@@ -301,7 +319,7 @@ __device__ __forceinline__ void solve_chunk(const KArgs<T>& a, int start, int me
   T sum = T(0);
   if (active)
     sum = row_dot<T, kPoll>(a.off_pos, a.off_val, a.off_ptr[k] + gl, a.off_ptr[k + 1], 1 << lg,
-                            a.xp, 1, a.spin_limit, a.status, T(0));
+                            a.xp, 1, a.spin_limit, a.status, a.poll != 0, T(0));
   sum = group_sum(sum, lg);
   if (active && gl == 0) {
     const int i = a.pos_row[k];
@@ -328,7 +346,7 @@ __device__ __forceinline__ void solve_chunk_multi(const KArgs<T>& a, int start, 
   for (int q = q0; q < a.nrhs; q += (1 << lg)) {
     const int64_t off = static_cast<int64_t>(q) * a.ld;
     const T sum = row_dot<T, kPoll>(a.off_pos, a.off_val, e0, e1, 1, a.xp + q, a.nrhs,
-                                    a.spin_limit, a.status, T(0));
+                                    a.spin_limit, a.status, a.poll != 0, T(0));
     const T xi = canonical((a.b[off + i] - sum) / d);
     publish<T, kPoll>(a.xp + static_cast<int64_t>(k) * a.nrhs + q, xi);
     a.x[off + i] = xi;
@@ -491,7 +509,7 @@ k_self_static(KArgs<T> a, const int* __restrict__ cstart, const int* __restrict_
       const int G = kMulti ? 1 : 1 << sd.lg;
       T sum = T(0);
       if (sd.k >= 0) {
-        wait_values<T, 4>(xq, xs, sd.j, xv, a.spin_limit, a.status);
+        wait_values<T, 4>(xq, xs, sd.j, xv, a.spin_limit, a.status, a.poll != 0);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           if (sd.j[q] < 0) continue;
@@ -499,7 +517,7 @@ k_self_static(KArgs<T> a, const int* __restrict__ cstart, const int* __restrict_
         }
         if (sd.e + 4 * G < sd.e1)
           sum = row_dot<T, true>(a.off_pos, a.off_val, sd.e + 4 * G, sd.e1, G, xq, xs,
-                                 a.spin_limit, a.status, sum);
+                                 a.spin_limit, a.status, a.poll != 0, sum);
       }
       if constexpr (kMulti) {
         if (sd.k >= 0) {
@@ -511,7 +529,7 @@ k_self_static(KArgs<T> a, const int* __restrict__ cstart, const int* __restrict_
           for (int q = qd + KL; q < a.nrhs; q += KL) {
             const int64_t off = static_cast<int64_t>(q) * a.ld;
             const T s2 = row_dot<T, true>(a.off_pos, a.off_val, sd.e, sd.e1, 1, a.xp + q, xs,
-                                          a.spin_limit, a.status, T(0));
+                                          a.spin_limit, a.status, a.poll != 0, T(0));
             const T x2 = canonical((a.b[off + sd.i] - s2) / sd.d);
             store_agent(a.xp + static_cast<int64_t>(sd.k) * xs + q, x2);
             a.x[off + sd.i] = x2;
@@ -686,7 +704,7 @@ __global__ void __launch_bounds__(256) k_self_flag(KArgs<T> a) {
       T sum = T(0);
       if (active)
         sum = row_dot<T, false>(a.off_col, a.off_val, a.off_ptr[k] + gl, a.off_ptr[k + 1], G, a.x,
-                                1, 0, a.status, T(0));
+                                1, 0, a.status, false, T(0));
       sum = group_sum(sum, lg);
       if (active && gl == 0) {
         const int i = a.pos_row[k];
@@ -782,6 +800,7 @@ template <typename T> KArgs<T> make_args(const SolveArgs& s) {
   a.epoch = s.scratch.epoch;
   a.flags = s.scratch.flags;
   a.spin_limit = s.spin_limit;
+  a.poll = s.poll;
   return a;
 }
 

@@ -54,6 +54,7 @@ struct SolveArgs {
   int nrhs = 1;
   int ld = 0;
   int spin_limit = 1 << 22;
+  int poll = 1;      // waits: 1 = two overlapped rounds over all slots, 0 = pending only
   int grid = 0;      // persistent workgroups
   int wg = 64;       // threads per workgroup
   const int* wave_ptr = nullptr;   // static schedule: per-wavefront chunk lists (CSR)

@@ -56,7 +56,10 @@ SCHEDULES = [("level", dict(algo=1)), ("self_value", dict(algo=2, sync=0)),
              ("self_value_rpl1_grid8", dict(algo=2, rows_per_lane=1, grid=8)),
              ("level_rpl2", dict(algo=1, rows_per_lane=2, group=1)),
              ("self_flag_rpl3_wg256", dict(algo=2, sync=1, rows_per_lane=3, wg=256, grid=4)),
-             ("self_value_wg256_grid1", dict(algo=2, wg=256, grid=1))]
+             ("self_value_wg256_grid1", dict(algo=2, wg=256, grid=1)),
+             ("self_static_poll0", dict(algo=2, sync=0, assign=0, poll=0)),
+             ("self_xcd_poll0_grid16", dict(algo=2, sync=0, assign=2, grid=16, poll=0)),
+             ("self_ticket_poll0", dict(algo=2, sync=0, assign=1, poll=0))]
 
 
 @pytest.mark.parametrize("name,T", CASES, ids=[c[0] for c in CASES])
@@ -123,11 +126,11 @@ def test_level_equals_self_bitwise(sp, name, T, group, rpl):
         hb = sp.Handle(*dev_tri(T), uplo="U" if T.upper else "L").configure(algo=3)
         for _ in range(5):
             assert bits_equal(hb.solve(b), ref)
-    for sync, assign in ((0, 0), (0, 1), (1, 1), (0, 2)):
+    for sync, assign, poll in ((0, 0, 1), (0, 1, 1), (1, 1, 1), (0, 2, 1), (0, 0, 0), (0, 1, 0)):
         if assign in (0, 2) and rpl != 1:
             continue                  # static assignment keeps one row per lane
         hs = sp.Handle(*dev_tri(T), uplo="U" if T.upper else "L").configure(
-            algo=2, group=group, sync=sync, rows_per_lane=rpl, assign=assign)
+            algo=2, group=group, sync=sync, rows_per_lane=rpl, assign=assign, poll=poll)
         for _ in range(20):
             assert bits_equal(hs.solve(b), ref)
         hs.status()
@@ -319,15 +322,15 @@ def test_empty_and_single(sp):
         assert host(h.solve(dev(np.array([2.0]))))[0] == 0.5
 
 
-@pytest.mark.parametrize("sync,assign", [(0, 0), (0, 1), (1, 1)])
-def test_watchdog_timeout_is_reported_and_recovers(sp, sync, assign):
+@pytest.mark.parametrize("sync,assign,poll", [(0, 0, 1), (0, 0, 0), (0, 1, 1), (1, 1, 1)])
+def test_watchdog_timeout_is_reported_and_recovers(sp, sync, assign, poll):
     """A spin limit of one poll (forced from the host) makes waits give up:
     the kernel drains, TIMEOUT is reported; with the default limit the same
     handle solves correctly again."""
     n = 20000
     P = W.bidiagonal_fast(n, 1.0, 1.0)
     b = np.ones(n)
-    h = sp.Handle(*dev_tri(P)).configure(algo=2, sync=sync, assign=assign, spin_limit=1)
+    h = sp.Handle(*dev_tri(P)).configure(algo=2, sync=sync, assign=assign, spin_limit=1, poll=poll)
     h.solve(dev(b))
     with pytest.raises(sp.SpTRSVError) as e:
         h.status()
