@@ -153,6 +153,8 @@ def _multi(sp, torch, reps, nrhs=16):
     hl = sp.Handle(*d).configure(algo=sp.ALGO_LEVEL)
     res["nlev"] = hs.info()["nlev"]
     Xo = o.solve_multi(T.row_ptr, T.col_idx, T.vals, B)
+    hs.tune_multi(Bd)
+    res["tuned_self"] = hs.info()
     for tag, h in (("self", hs), ("level", hl)):
         h.solve_multi(Bd, out=Xd)
         h.status()

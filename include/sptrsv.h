@@ -249,11 +249,22 @@ int sptrsv_get_option(sptrsv_handle_t h, sptrsv_option key, int64_t *value);
 
 /* Time short trials of the candidate schedules on (b, x) -- both device
  * vectors of n elements, x overwritten -- and keep the fastest (lanes per row
- * rule, rows per lane, sync, persistent grid; and the algorithm when ALGO is
- * AUTO, else only candidates of the fixed ALGO).  Results are cached per
+ * rule, rows per lane, sync, persistent grid, assignment, polling mode; and
+ * the algorithm when ALGO is AUTO, else only candidates of the fixed ALGO).  Results are cached per
  * pattern hash in the process.  Changing a schedule option afterwards drops
  * the tuned choice. */
 int sptrsv_tune(sptrsv_handle_t h, const void *b, void *x, hipStream_t stream);
+
+/* Autotuner for solves with nrhs >= 2 right-hand sides (column-major, column
+ * stride ld >= n): times the self-scheduled solve over persistent grids of
+ * 1, 2, 4 and 8 wavefronts per CU, static and XCD-regional assignment and
+ * both polling modes (and the level-scheduled solve, unless the algorithm
+ * option excludes it) on the caller's B and X, and keeps the fastest for
+ * this nrhs.  Without it, multi-RHS solves use the single-RHS schedule with
+ * 4 wavefronts per CU (1 for nrhs < 4) unless SPTRSV_OPT_GRID is set.
+ * B != X.  Blocking.  Changing a schedule option discards the choice. */
+int sptrsv_tune_multi(sptrsv_handle_t h, int32_t nrhs, int32_t ld, const void *B, void *X,
+                      hipStream_t stream);
 
 /* n, nnz, nlev of T; the algorithm and lanes per row the next solve uses
  * (resolved if AUTO); any pointer may be NULL. */

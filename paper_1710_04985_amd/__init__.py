@@ -106,6 +106,15 @@ class _Base:
         check(lib.sptrsv_tune(self._h, _ptr(b), _ptr(x), _stream(stream)))
         return self.info()
 
+    def tune_multi(self, B, X=None, stream=None):
+        """Tunes the schedule of solve_multi for B's number of columns (B is
+        (nrhs, n), the column-major n x nrhs matrix); X is scratch output."""
+        _need_cuda(B, "B", self.dtype)
+        if B.dim() != 2 or B.shape[1] != self.n or B.shape[0] < 2:
+            raise ValueError("B must be (nrhs >= 2, n)")
+        X = torch.empty_like(B) if X is None else X
+        check(lib.sptrsv_tune_multi(self._h, B.shape[0], self.n, _ptr(B), _ptr(X), _stream(stream)))
+
     def info(self):
         n, nlev, algo, group = (ctypes.c_int32() for _ in range(4))
         nnz = ctypes.c_int64()

@@ -132,6 +132,7 @@ struct sptrsv_handle_s {
   // autotuner result
   bool tuned = false;
   Config tuned_cfg{SPTRSV_ALGO_SELF, 0, 4, SPTRSV_SYNC_VALUE, 1, 0, SPTRSV_ASSIGN_STATIC};
+  std::map<int, Config> tuned_multi;   // sptrsv_tune_multi's choice per nrhs
   uint64_t hash = 0;               // pattern hash, computed by the first sptrsv_tune
   bool hash_valid = false;
   // timing
@@ -444,6 +445,18 @@ Config resolve(sptrsv_handle_t h) {
   return c;
 }
 
+// Schedule of a solve with nrhs > 1 right-hand sides: sptrsv_tune_multi's
+// choice for this nrhs if there is one, else the single-RHS schedule with a
+// grid sized for several columns unless the grid option is set (each chunk
+// then holds 64/nrhs rows, so a level has many more chunks to spread).
+Config resolve_multi(sptrsv_handle_t h, int nrhs) {
+  auto it = h->tuned_multi.find(nrhs);
+  if (it != h->tuned_multi.end()) return it->second;
+  Config c = resolve(h);
+  if (h->grid == 0) c.grid = nrhs >= 4 ? 4 * h->num_cu : h->num_cu;
+  return c;
+}
+
 uint64_t tune_key(sptrsv_handle_t h) {
   return h->hash ^ (h->dtype == SPTRSV_F32 ? 0x9e3779b97f4a7c15ull : 0) ^
          (static_cast<uint64_t>(h->algo) << 56);
@@ -741,7 +754,7 @@ int solve_dispatch(sptrsv_handle_t h, bool transpose, const void* b, void* x, in
     if (st) return st;
   }
   PlanState& ps = transpose ? h->trn : h->fwd;
-  const Config c = resolve(h);
+  const Config c = nrhs > 1 ? resolve_multi(h, nrhs) : resolve(h);
   if (c.algo == SPTRSV_ALGO_BLOCK && nrhs == 1) {
     const int st = build_block(h, transpose ? 1 : 0, s);
     if (st) return st;
@@ -1109,8 +1122,10 @@ int sptrsv_set_option(sptrsv_handle_t h, sptrsv_option key, int64_t v) {
   if (!h) return kErrInvalidArg;
   if (key == SPTRSV_OPT_ALGO || key == SPTRSV_OPT_GROUP || key == SPTRSV_OPT_ENTRIES_PER_LANE ||
       key == SPTRSV_OPT_SYNC || key == SPTRSV_OPT_ROWS_PER_LANE || key == SPTRSV_OPT_GRID ||
-      key == SPTRSV_OPT_ASSIGN)
+      key == SPTRSV_OPT_ASSIGN || key == SPTRSV_OPT_POLL) {
     h->tuned = false;   // an explicit schedule option overrides the tuner's choice
+    h->tuned_multi.clear();
+  }
   switch (key) {
     case SPTRSV_OPT_ALGO:
       if (v != SPTRSV_ALGO_AUTO && v != SPTRSV_ALGO_LEVEL && v != SPTRSV_ALGO_SELF &&
@@ -1290,6 +1305,64 @@ int sptrsv_tune(sptrsv_handle_t h, const void* b, void* x, hipStream_t stream) {
   h->tuned_cfg = best_c;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tune_cache[tune_key(h)] = best_c;
+  return kOk;
+}
+
+int sptrsv_tune_multi(sptrsv_handle_t h, int32_t nrhs, int32_t ld, const void* B, void* X,
+                      hipStream_t stream) {
+  if (!h || nrhs < 2 || ld < h->n || ld < 1) return kErrInvalidArg;
+  if (h->n == 0) return kOk;
+  if (!B || !X || B == X) return kErrInvalidArg;
+  const int ncu = h->num_cu;
+  std::vector<Config> cand;
+  const bool self_ok = h->algo == SPTRSV_ALGO_AUTO || h->algo == SPTRSV_ALGO_SELF ||
+                       is_column(h->algo);
+  if (self_ok)
+    for (int grid : {ncu, 2 * ncu, 4 * ncu, 8 * ncu})
+      for (int as : {SPTRSV_ASSIGN_STATIC, SPTRSV_ASSIGN_XCD})
+        for (int poll : {1, 0}) {
+          Config c{SPTRSV_ALGO_SELF, 0, 4, SPTRSV_SYNC_VALUE, 1, grid, as};
+          c.poll = poll;
+          cand.push_back(c);
+        }
+  if (h->algo == SPTRSV_ALGO_AUTO || h->algo == SPTRSV_ALGO_LEVEL || h->algo == SPTRSV_ALGO_BLOCK ||
+      cand.empty())
+    cand.push_back({SPTRSV_ALGO_LEVEL, 0, 4, SPTRSV_SYNC_VALUE, 1, 0, SPTRSV_ASSIGN_TICKET});
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  const int saved_timing = h->timing;
+  h->timing = 0;
+  float best = 1e30f;
+  Config best_c = cand[0];
+  int st = kOk;
+  for (const Config& c : cand) {
+    auto run = [&]() {
+      return h->dtype == SPTRSV_F64 ? solve_impl<double>(h, h->fwd, c, B, X, nrhs, ld, stream)
+                                    : solve_impl<float>(h, h->fwd, c, B, X, nrhs, ld, stream);
+    };
+    if (c.algo == SPTRSV_ALGO_LEVEL && h->fwd.h.nlev > 20000 && cand.size() > 1) continue;
+    if ((st = run())) break;   // warm-up (also builds the chunk table)
+    if (hipEventRecord(e0, stream) != hipSuccess) { st = kErrHip; break; }
+    for (int r = 0; r < 2 && !st; ++r) st = run();
+    if (st) break;
+    if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+      st = kErrHip;
+      break;
+    }
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (ms < best) {
+      best = ms;
+      best_c = c;
+    }
+  }
+  h->timing = saved_timing;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st) return st;
+  if ((st = read_status(h, stream, true))) return st;
+  h->tuned_multi[nrhs] = best_c;
   return kOk;
 }
 

@@ -217,6 +217,12 @@ def test_multi_rhs(sp, nrhs, opts):
     B = dev(F)
     h.solve_multi(B, out=B)
     assert bits_equal(host(B), X)
+    # the multi-RHS tuner's schedule gives the same columns
+    if nrhs >= 2:
+        h.tune_multi(dev(F))
+        X2 = host(h.solve_multi(dev(F)))
+        h.status()
+        assert bits_equal(X2, X)
 
 
 def test_batched(sp):
