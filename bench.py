@@ -16,7 +16,7 @@ in HBM before the timed region.
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 
 Prints one JSON line.  --suite also writes per-configuration lines for the
-other workloads to gpurun_out/bench_suite.jsonl.
+other workloads to bench_suite.jsonl in the output folder (--out-dir).
 """
 from __future__ import annotations
 
@@ -53,9 +53,11 @@ def parse():
                     help="also run a plain device copy of this size (counter calibration)")
     ap.add_argument("--suite", action="store_true")
     ap.add_argument("--setup", action="store_true",
-                    help="also time the host and device setup routes (gpurun_out/bench_setup.jsonl)")
+                    help="also time the host and device setup routes (bench_setup.jsonl)")
     ap.add_argument("--table2", action="store_true",
-                    help="also run the Table 2 grid sweep (gpurun_out/bench_table2.jsonl)")
+                    help="also run the Table 2 grid sweep (bench_table2.jsonl)")
+    ap.add_argument("--out-dir", default="gpurun_out",
+                    help="folder (relative to this file) for the extra JSON lines")
     return ap.parse_args()
 
 
@@ -202,6 +204,33 @@ def main():
     ms_self = timed(hL, hU, args.steps, args.warmup)
     ms_level = timed(lvL, lvU, args.steps, args.warmup)
 
+    # the same step replayed from HIP graphs (one per triangle): the
+    # level-scheduled solve's per-level launches become graph nodes
+    def timed_graph(hl, hu, steps, warmup):
+        gs = torch.cuda.Stream()
+        with torch.cuda.stream(gs):
+            g1 = hl.capture(b, y1, stream=gs)
+            g2 = hu.capture(y1, y2, stream=gs)
+            for _ in range(warmup):
+                g1.launch(gs)
+                g2.launch(gs)
+            gs.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(gs)
+            for _ in range(steps):
+                g1.launch(gs)
+                g2.launch(gs)
+            e1.record(gs)
+            e1.synchronize()
+        hl.status()
+        hu.status()
+        g1.close()
+        g2.close()
+        return e0.elapsed_time(e1) / steps
+
+    ms_self_graph = timed_graph(hL, hU, args.steps, args.warmup)
+    ms_level_graph = timed_graph(lvL, lvU, args.steps, args.warmup)
+
     # per-kernel durations of the self-scheduled solve kernel (HIP events the
     # library records on the solve stream around the kernel launch)
     for h in (hL, hU):
@@ -246,7 +275,9 @@ def main():
                    "solver": "self-scheduled", "tuned": tuned},
         "solves_per_s": round(2.0 / (ms_self * 1e-3), 2),
         "level_scheduled": {"ms_per_step": round(ms_level, 5), "gbs": round(gbs_level, 3),
-                            "solves_per_s": round(2.0 / (ms_level * 1e-3), 2)},
+                            "solves_per_s": round(2.0 / (ms_level * 1e-3), 2),
+                            "graph_ms_per_step": round(ms_level_graph, 5)},
+        "self_graph_ms_per_step": round(ms_self_graph, 5),
         "speedup_self_vs_level": round(ms_level / ms_self, 3),
         "max_rel_err_vs_oracle": float("%.3e" % err),
         "analysis_ms": round(analysis_ms, 2),
@@ -273,15 +304,18 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         out["copy_probe_bytes"] = nbytes
+    out_dir = os.path.join(os.path.dirname(os.path.abspath(__file__)), args.out_dir)
+    if args.suite or args.setup or args.table2:
+        os.makedirs(out_dir, exist_ok=True)
     if args.suite:
         import bench_suite
-        bench_suite.run(sp, torch, out_path=os.path.join("gpurun_out", "bench_suite.jsonl"))
+        bench_suite.run(sp, torch, out_path=os.path.join(out_dir, "bench_suite.jsonl"))
     if args.setup:
         import bench_suite
-        bench_suite.setup_routes(sp, torch, out_path=os.path.join("gpurun_out", "bench_setup.jsonl"))
+        bench_suite.setup_routes(sp, torch, out_path=os.path.join(out_dir, "bench_setup.jsonl"))
     if args.table2:
         import bench_suite
-        bench_suite.table2(sp, torch, out_path=os.path.join("gpurun_out", "bench_table2.jsonl"))
+        bench_suite.table2(sp, torch, out_path=os.path.join(out_dir, "bench_table2.jsonl"))
     print(json.dumps(out), flush=True)
 
 
