@@ -68,13 +68,15 @@ __global__ void __launch_bounds__(256) k_fill_int(int* p, int64_t count, int v) 
 // the next chunk from a ticket, so chunks are taken in order by running
 // wavefronts and no co-residency is assumed.
 // level[] starts at -1; a row publishes its level with one agent-scope atomic
-// store.  A round polls the row's dependencies outside the chunk (in stored
-// order, resuming at the first one not yet published), then resolves the
-// chain inside the chunk through LDS, one link per step.  A lane keeps up to
-// kInChunk in-chunk dependencies (6-bit lane numbers) packed in a register and
-// rescans its row otherwise.  The lowest unfinished row always has every
-// dependency published and its chunk held by a running wavefront, so the
-// sweep progresses.
+// store.  Rows are sorted on this route, so a row's dependencies inside the
+// chunk are the off-diagonals next to its diagonal and those in earlier
+// chunks one contiguous range.  A round polls the earlier-chunk range
+// (sixteen loads in flight, resuming at the first one not yet published),
+// then resolves the chain inside the chunk through LDS, one link per step.
+// A lane keeps up to kInChunk in-chunk dependencies (6-bit lane numbers)
+// packed in a register and rescans its in-chunk range otherwise.  The lowest
+// unfinished row always has every dependency published and its chunk held by
+// a running wavefront, so the sweep progresses.
 constexpr int kInChunk = 10;
 
 __global__ void __launch_bounds__(64)
@@ -94,50 +96,66 @@ k_levels(int n, const int* __restrict__ rp, const int* __restrict__ col, int upp
     const bool live = r < n;
     const int i = live ? (upper ? n - 1 - r : r) : 0;
     const int a = live ? rp[i] : 0, e1 = live ? rp[i + 1] : 0;
-    // in-chunk dependencies
+    // Rows are sorted on this route (k_check): the in-chunk dependencies are
+    // the off-diagonals next to the diagonal, those in earlier chunks the
+    // contiguous range [oa, ob)
     unsigned long long pk = 0;
-    int nin = 0;
-    for (int e2 = a; e2 < e1; e2 += 8) {
-      int jj[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) jj[q] = e2 + q < e1 ? col[e2 + q] : i;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int rj = upper ? n - 1 - jj[q] : jj[q];
-        if (jj[q] == i || rj < c0) continue;
-        if (nin < kInChunk) pk |= static_cast<unsigned long long>(rj - c0) << (6 * nin);
-        ++nin;
+    int nin = 0, oa = a, ob = a, ib = a, ie = a;
+    if (live) {
+      if (!upper) {
+        int e = e1;
+        if (e > a && col[e - 1] == i) --e;          // diagonal last
+        ie = e;
+        while (e > a && col[e - 1] >= c0) {         // in-chunk: c0 <= j < i
+          if (nin < kInChunk) pk |= static_cast<unsigned long long>(col[e - 1] - c0) << (6 * nin);
+          ++nin;
+          --e;
+        }
+        ib = e;
+        oa = a;
+        ob = e;
+      } else {
+        int e = a;
+        if (e < e1 && col[e] == i) ++e;             // diagonal first
+        ib = e;
+        const int jmax = n - 1 - c0;                // in-chunk: i < j <= n-1-c0
+        while (e < e1 && col[e] <= jmax) {
+          if (nin < kInChunk)
+            pk |= static_cast<unsigned long long>(n - 1 - col[e] - c0) << (6 * nin);
+          ++nin;
+          ++e;
+        }
+        ie = e;
+        oa = e;
+        ob = e1;
       }
     }
-    int e = a;                        // cursor over the entries outside the chunk
+    int e = oa;                       // cursor over the earlier-chunk dependencies
     int lvl = 0;
     bool done = !live;
     sl[lane] = -1;
     for (int round = 0;; ++round) {
       bool gready = true;
       if (!done) {
-        // eight entries at a time: their columns, then their levels, in flight together
-        while (e < e1) {
-          int v8[8];
-          bool need[8];
+        // sixteen at a time: their columns, then their levels, in flight together
+        while (e < ob) {
+          int v16[16];
 #pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            const int j = e + q < e1 ? col[e + q] : i;
-            const int rj = upper ? n - 1 - j : j;
-            need[q] = j != i && rj < c0;
-            v8[q] = need[q] ? __hip_atomic_load(level + j, __ATOMIC_RELAXED,
+          for (int q = 0; q < 16; ++q) {
+            const int j = e + q < ob ? col[e + q] : -1;
+            v16[q] = j >= 0 ? __hip_atomic_load(level + j, __ATOMIC_RELAXED,
                                                 __HIP_MEMORY_SCOPE_AGENT)
                             : 0;
           }
           int adv = 0;
           bool stop = false;
 #pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            if (stop || e + q >= e1) continue;
-            if (need[q] && v8[q] < 0) {
+          for (int q = 0; q < 16; ++q) {
+            if (stop || e + q >= ob) continue;
+            if (v16[q] < 0) {
               stop = true;
             } else {
-              if (need[q]) lvl = v8[q] + 1 > lvl ? v8[q] + 1 : lvl;
+              lvl = v16[q] + 1 > lvl ? v16[q] + 1 : lvl;
               ++adv;
             }
           }
@@ -166,10 +184,8 @@ k_levels(int n, const int* __restrict__ rp, const int* __restrict__ col, int upp
               l2 = v + 1 > l2 ? v + 1 : l2;
             }
           } else {
-            for (int e2 = a; e2 < e1; ++e2) {
-              const int j = col[e2];
-              const int rj = upper ? n - 1 - j : j;
-              if (j == i || rj < c0) continue;
+            for (int e2 = ib; e2 < ie; ++e2) {
+              const int rj = upper ? n - 1 - col[e2] : col[e2];
               const int v = sl[rj - c0];
               if (v < 0) {
                 ready = false;
