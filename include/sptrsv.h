@@ -5,11 +5,17 @@
  * CUDA" (arXiv:1710.04985).  The library solves  T x = b  with T a sparse
  * lower or upper triangle in CSR form (Sec. 3, eq. (1)), after a setup
  * ("analysis") phase that computes the level sets of the dependency DAG
- * (Sec. 4.1, Sec. 4.4).  Two solve schedules are provided:
+ * (Sec. 4.1, Sec. 4.4), on the host or on the device.  Solve schedules:
  *   - level-scheduled (Sec. 4.1, Algorithm LEVR): one kernel launch per level;
  *   - self-scheduled (Sec. 4.2, Algorithm SLFR): one persistent launch whose
  *     waves take rows in level order and wait on per-row readiness instead of
- *     a global synchronisation between levels.
+ *     a global synchronisation between levels;
+ *   - block: level by level inside one workgroup per independent system;
+ *   - column-wise (Sec. 3.2; Algorithms LEVC and SLFC): finished unknowns
+ *     push their updates into the rows that depend on them.
+ * Transposed solves, several right-hand sides, batches of independent
+ * triangles, the gradient with respect to the values, HIP graph capture and
+ * an autotuner complete the interface.
  *
  * Conventions shared by every entry point
  *   - Indices are int32, 0-based.  The diagonal is stored INSIDE each row
@@ -24,12 +30,16 @@
  *   - Every function returns an int status: SPTRSV_OK (0) or a negative
  *     sptrsv_status.  Handles are opaque and owned by the library until
  *     sptrsv_destroy.
- *   - Solves are asynchronous on the given HIP stream (NULL = default stream)
- *     and perform no allocation, host synchronisation or memset, so they can
- *     be captured in a HIP graph once the handle has been prepared (first
- *     transpose solve or explicit sptrsv_prepare_transpose; option changes
- *     made before capture).  Calls on one handle must be issued on one stream
- *     at a time: the handle's scratch (ticket, flags, epoch) is shared.
+ *   - Solves are asynchronous on the given HIP stream (NULL = default stream).
+ *     The first solve with a given schedule builds and uploads its work
+ *     tables (chunks, per-wavefront lists; for the column-wise solves the
+ *     push lists and their scratch; for T^T its analysis) with synchronous
+ *     copies; later solves with that schedule perform no allocation, host
+ *     synchronisation or memset, so they can be captured in a HIP graph.
+ *     sptrsv_graph_capture prepares all of this itself.  Calls on one handle
+ *     must be issued on one stream at a time: the handle's scratch (ticket,
+ *     status, flags, epoch, the position-ordered solution, accumulators) is
+ *     shared.
  *   - n = 0 is valid and every solve on it is a no-op.
  *   - Dependencies are taken from the pattern (Sec. 4.4): an explicitly
  *     stored zero off-diagonal still counts as a dependency.
@@ -248,9 +258,10 @@ int sptrsv_set_option(sptrsv_handle_t h, sptrsv_option key, int64_t value);
 int sptrsv_get_option(sptrsv_handle_t h, sptrsv_option key, int64_t *value);
 
 /* Time short trials of the candidate schedules on (b, x) -- both device
- * vectors of n elements, x overwritten -- and keep the fastest (lanes per row
- * rule, rows per lane, sync, persistent grid, assignment, polling mode; and
- * the algorithm when ALGO is AUTO, else only candidates of the fixed ALGO).  Results are cached per
+ * vectors of n elements, x overwritten -- and keep the fastest (lanes per
+ * row rule, rows per lane, sync, persistent grid, assignment, polling mode;
+ * and the algorithm when ALGO is AUTO, else only candidates of the fixed
+ * ALGO; the column-wise solves only when fixed).  Results are cached per
  * pattern hash in the process.  Changing a schedule option afterwards drops
  * the tuned choice. */
 int sptrsv_tune(sptrsv_handle_t h, const void *b, void *x, hipStream_t stream);

@@ -136,6 +136,28 @@ def test_level_equals_self_bitwise(sp, name, T, group, rpl):
         hs.status()
 
 
+@pytest.mark.parametrize("opts", [dict(algo=2, assign=0), dict(algo=2, assign=2, poll=0),
+                                  dict(algo=2, assign=1), dict(algo=2, sync=1), dict(algo=3),
+                                  dict(algo=5)])
+def test_alternating_right_hand_sides(sp, opts):
+    """Consecutive solves on one handle with different b: every solve must
+    produce its own answer (a value left over from the previous solve would
+    be read as published if readiness ever leaked across solves)."""
+    T = W.laplacian_triangle((24, 22, 20))
+    hl = sp.Handle(*dev_tri(T)).configure(algo=1)
+    bs = [dev(W.uniform_vector(T.n, 40 + k)) for k in range(3)]
+    refs = [hl.solve(b) for b in bs]
+    h = sp.Handle(*dev_tri(T)).configure(**opts)
+    for it in range(12):
+        k = it % 3
+        x = h.solve(bs[k])
+        if opts.get("algo") == 5:
+            assert relerr(host(x), host(refs[k])) <= TOL64, it
+        else:
+            assert bits_equal(x, refs[k]), it
+    h.status()
+
+
 @pytest.mark.parametrize("opts", [dict(algo=1), dict(algo=2, sync=0), dict(algo=2, sync=1)])
 def test_in_place(sp, opts):
     o = oracle.get()
