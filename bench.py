@@ -231,6 +231,25 @@ def main():
     ms_self_graph = timed_graph(hL, hU, args.steps, args.warmup)
     ms_level_graph = timed_graph(lvL, lvU, args.steps, args.warmup)
 
+    # cold steps: a 1 GiB write evicts the L2s and the last-level cache first
+    flush = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+    cold = []
+    for k in range(5):
+        flush.fill_(float(k))
+        torch.cuda.synchronize()
+        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        c0.record()
+        step(hL, hU, y1, y2)
+        c1.record()
+        c1.synchronize()
+        cold.append(c0.elapsed_time(c1))
+    del flush
+    ms_cold = float(np.median(cold))
+
+    # critical-path bound: one producer-to-consumer hop per level
+    hop_same = min(sp.probe_hop(same_xcd=True) for _ in range(3))
+    hop_cross = min(sp.probe_hop(same_xcd=False) for _ in range(3))
+
     # per-kernel durations of the self-scheduled solve kernel (HIP events the
     # library records on the solve stream around the kernel launch)
     for h in (hL, hU):
@@ -278,6 +297,7 @@ def main():
                             "solves_per_s": round(2.0 / (ms_level * 1e-3), 2),
                             "graph_ms_per_step": round(ms_level_graph, 5)},
         "self_graph_ms_per_step": round(ms_self_graph, 5),
+        "self_cold_ms_per_step": round(ms_cold, 5),
         "speedup_self_vs_level": round(ms_level / ms_self, 3),
         "max_rel_err_vs_oracle": float("%.3e" % err),
         "analysis_ms": round(analysis_ms, 2),
@@ -287,6 +307,10 @@ def main():
                      "traffic": committed_traffic(kernel_name),
                      "kernel": kernel_name,
                      "kernel_ms": round(kernel_ms, 5), "bytes_per_launch": lbL},
+        "critical_path": {"nlev": nlev, "hop_ns_same_xcd": round(hop_same, 1),
+                          "hop_ns_cross_xcd": round(hop_cross, 1),
+                          "bound_ms_per_triangle": round(nlev * hop_same * 1e-6, 5),
+                          "kernel_over_bound": round(kernel_ms / (nlev * hop_same * 1e-6), 3)},
     }
     if not args.no_cpu_baseline:
         t_cpu, reps = cpu_baseline(TL, TU, bL, args.cpu_seconds)

@@ -277,6 +277,18 @@ int sptrsv_tune(sptrsv_handle_t h, const void *b, void *x, hipStream_t stream);
 int sptrsv_tune_multi(sptrsv_handle_t h, int32_t nrhs, int32_t ld, const void *B, void *X,
                       hipStream_t stream);
 
+/* Measures the producer-to-consumer hop of the self-scheduled solves: two
+ * wavefronts on different CUs bounce a counter through two device words,
+ * each side publishing with an agent-scope atomic store and polling the
+ * other's with agent-scope atomic loads; *ns_per_hop = elapsed time / (2 *
+ * (iters - 1)) (the first round trip warms up).  same_xcd != 0 places the
+ * peer workgroup eight workgroups after the first, which the dispatcher
+ * sends to the same XCD, else on the next XCD.  iters >= 2.  Uses the
+ * current device; allocates and frees 256 bytes; blocking.  A hop
+ * multiplied by the level count bounds a self-scheduled solve from below.
+ * Errors: INVALID_ARG, HIP, OOM, TIMEOUT (a wait exceeded 2^26 polls). */
+int sptrsv_probe_hop(int same_xcd, int32_t iters, double *ns_per_hop);
+
 /* n, nnz, nlev of T; the algorithm and lanes per row the next solve uses
  * (resolved if AUTO); any pointer may be NULL. */
 int sptrsv_get_info(sptrsv_handle_t h, int32_t *n, int64_t *nnz, int32_t *nlev,

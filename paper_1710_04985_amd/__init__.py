@@ -190,6 +190,14 @@ class Graph:
             pass
 
 
+def probe_hop(same_xcd=False, iters=2000):
+    """Nanoseconds for one value to travel from a publishing wavefront to a
+    polling one on another CU (same XCD or the next one)."""
+    ns = ctypes.c_double()
+    check(lib.sptrsv_probe_hop(int(bool(same_xcd)), int(iters), ctypes.byref(ns)))
+    return ns.value
+
+
 class Handle(_Base):
     """Analysis of one CSR triangle (diagonal stored inside the rows).
 

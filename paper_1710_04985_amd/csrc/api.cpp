@@ -18,6 +18,7 @@
 #include "analysis.hpp"
 #include "analysis_gpu.hpp"
 #include "column.hpp"
+#include "probe.hpp"
 #include "kernels.hpp"
 
 using namespace sptrsv;
@@ -1364,6 +1365,40 @@ int sptrsv_tune_multi(sptrsv_handle_t h, int32_t nrhs, int32_t ld, const void* B
   if ((st = read_status(h, stream, true))) return st;
   h->tuned_multi[nrhs] = best_c;
   return kOk;
+}
+
+int sptrsv_probe_hop(int same_xcd, int32_t iters, double* ns_per_hop) {
+  if (!ns_per_hop || iters < 2) return kErrInvalidArg;
+  *ns_per_hop = 0.0;
+  int dev = 0, khz = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+    return kErrHip;
+  void* buf = nullptr;
+  if (hipMalloc(&buf, 256) != hipSuccess) return kErrOom;
+  int* a = static_cast<int*>(buf);
+  int* b = a + 16;                       // another 64-byte line
+  int* status = a + 32;
+  long long* ticks = reinterpret_cast<long long*>(a + 48);
+  int st = kOk;
+  if (hipMemset(buf, 0, 256) != hipSuccess ||
+      launch_pingpong(a, b, same_xcd ? 8 : 1, iters, 1 << 26, ticks, status, nullptr) !=
+          hipSuccess ||
+      hipDeviceSynchronize() != hipSuccess) {
+    st = kErrHip;
+  } else {
+    int flag = 0;
+    long long t = 0;
+    if (hipMemcpy(&flag, status, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(&t, ticks, sizeof(t), hipMemcpyDeviceToHost) != hipSuccess)
+      st = kErrHip;
+    else if (flag)
+      st = kErrTimeout;
+    else
+      *ns_per_hop = static_cast<double>(t) * 1e6 / khz / (2.0 * (iters - 1));
+  }
+  (void)hipFree(buf);
+  return st;
 }
 
 int sptrsv_get_info(sptrsv_handle_t h, int32_t* n, int64_t* nnz, int32_t* nlev, int32_t* algo,
