@@ -408,3 +408,10 @@ def test_tune_and_timing(sp):
     ms, cnt = h.kernel_time()
     assert cnt == 4 and ms > 0
     assert relerr(host(x), o.solve(T.row_ptr, T.col_idx, T.vals, host(b))) <= TOL64
+
+
+def test_probe_hop(sp):
+    """The hop probe returns a plausible latency for both placements."""
+    for same in (True, False):
+        ns = sp.probe_hop(same_xcd=same, iters=200)
+        assert 10.0 < ns < 1e5, (same, ns)
