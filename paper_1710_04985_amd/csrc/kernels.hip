@@ -62,6 +62,15 @@ template <typename T> __device__ __forceinline__ bool is_sentinel(T v) {
   return __builtin_bit_cast(typename Bits<T>::U, v) == Bits<T>::kSentinel;
 }
 
+// fused multiply-add in the value type (FP64 or FP32: one rounding, no
+// widening)
+__device__ __forceinline__ double fma_t(double a, double b, double c) {
+  return __builtin_fma(a, b, c);
+}
+__device__ __forceinline__ float fma_t(float a, float b, float c) {
+  return __builtin_fmaf(a, b, c);
+}
+
 // quiets a signalling NaN, leaves every other value unchanged
 __device__ __forceinline__ double canonical(double v) { return __builtin_canonicalize(v); }
 __device__ __forceinline__ float canonical(float v) { return __builtin_canonicalizef(v); }
@@ -224,7 +233,7 @@ __device__ __forceinline__ T row_dot(const int* __restrict__ idx, const T* __res
     if constexpr (kPoll) wait_values<T, B>(xr, xs, j, xv, spin_limit, status, overlap);
 #pragma unroll
     for (int u = 0; u < B; ++u)
-      if (j[u] >= 0) sum = __builtin_fma(v[u], xv[u], sum);
+      if (j[u] >= 0) sum = fma_t(v[u], xv[u], sum);
     if (!more) break;
 #pragma unroll
     for (int u = 0; u < B; ++u) {
@@ -302,7 +311,7 @@ __device__ __forceinline__ void solve_chunk(const KArgs<T>& a, int start, int me
 #pragma unroll
       for (int q = 0; q < E; ++q) {
         if (j[u][q] < 0) continue;
-        sum = __builtin_fma(v[u][q], xv[u][q], sum);
+        sum = fma_t(v[u][q], xv[u][q], sum);
       }
       if (e1[u] > e0[u] + E)
         sum = row_dot<T, kPoll>(a.off_pos, a.off_val, e0[u] + E, e1[u], 1, a.xp, 1, a.spin_limit,
@@ -513,7 +522,7 @@ k_self_static(KArgs<T> a, const int* __restrict__ cstart, const int* __restrict_
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           if (sd.j[q] < 0) continue;
-          sum = __builtin_fma(sd.v[q], xv[q], sum);
+          sum = fma_t(sd.v[q], xv[q], sum);
         }
         if (sd.e + 4 * G < sd.e1)
           sum = row_dot<T, true>(a.off_pos, a.off_val, sd.e + 4 * G, sd.e1, G, xq, xs,
@@ -625,7 +634,7 @@ k_block(KArgs<T> a, const int* __restrict__ seg_row0, const int* __restrict__ se
     return en;
   };
   auto finish = [&](int e, int e1, int i, T d, T bi, T sum) {
-    for (; e < e1; ++e) sum = __builtin_fma(a.off_val[e], blk_x<T, kLds>(xs, a.x, a.off_col[e], r0), sum);
+    for (; e < e1; ++e) sum = fma_t(a.off_val[e], blk_x<T, kLds>(xs, a.x, a.off_col[e], r0), sum);
     const T xi = canonical((bi - sum) / d);
     if constexpr (kLds) xs[i - r0] = xi;
     a.x[i] = xi;
@@ -639,7 +648,7 @@ k_block(KArgs<T> a, const int* __restrict__ seg_row0, const int* __restrict__ se
       T sum = T(0);
 #pragma unroll
       for (int q = 0; q < 4; ++q)
-        if (e0.j[q] >= 0) sum = __builtin_fma(e0.v[q], blk_x<T, kLds>(xs, a.x, e0.j[q], r0), sum);
+        if (e0.j[q] >= 0) sum = fma_t(e0.v[q], blk_x<T, kLds>(xs, a.x, e0.j[q], r0), sum);
       finish(e0.e + 4, e0.e1, e0.i, e0.d, e0.bi, sum);
     }
     // rows of this level beyond the first blockDim, not loaded ahead
