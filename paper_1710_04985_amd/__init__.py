@@ -41,12 +41,12 @@ def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
     return ctypes.c_void_p(t.data_ptr())
 
 
-def _need_cuda(t, name, dtype=None):
+def _need_cuda(t, name, dtype=None, dense=True):
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise TypeError("%s must be a CUDA (HIP) tensor" % name)
     if dtype is not None and t.dtype != dtype:
         raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
-    if not t.is_contiguous():
+    if dense and not t.is_contiguous():
         raise ValueError("%s must be contiguous" % name)
 
 
@@ -73,14 +73,25 @@ class _Base:
         return self._solve(lib.sptrsv_solve_transpose, b, out, stream)
 
     def solve_multi(self, B, out=None, transpose=False, stream=None):
-        """Column-major multi-RHS solve: B is (nrhs, n) contiguous, i.e. the
-        column-major n x nrhs matrix with ld = n (column r = B[r])."""
-        _need_cuda(B, "B", self.dtype)
+        """Column-major multi-RHS solve: B is (nrhs, n), column r = B[r], with
+        unit stride along a column and column stride ld = B.stride(0) >= n
+        (a row-slice of a wider buffer is accepted); out, if given, has the
+        same strides."""
+        _need_cuda(B, "B", self.dtype, dense=False)
         if B.dim() != 2 or B.shape[1] != self.n:
             raise ValueError("B must be (nrhs, n)")
-        X = torch.empty_like(B) if out is None else out
-        _need_cuda(X, "out", self.dtype)
-        check(lib.sptrsv_solve_multi(self._h, B.shape[0], self.n, _ptr(B), _ptr(X),
+        ld = B.stride(0) if B.shape[0] > 1 else self.n
+        if (self.n > 1 and B.stride(1) != 1) or ld < self.n:
+            raise ValueError("B must have unit stride along a column and column stride >= n")
+        if out is None:
+            X = torch.empty_strided(B.shape, (ld, 1), dtype=B.dtype, device=B.device)
+        else:
+            X = out
+            _need_cuda(X, "out", self.dtype, dense=False)
+            if X.shape != B.shape or (B.shape[0] > 1 and X.stride(0) != ld) or \
+                    (self.n > 1 and X.stride(1) != 1):
+                raise ValueError("out must have the shape and strides of B")
+        check(lib.sptrsv_solve_multi(self._h, B.shape[0], max(ld, 1), _ptr(B), _ptr(X),
                                      int(transpose), _stream(stream)))
         return X
 

@@ -247,6 +247,41 @@ def test_multi_rhs(sp, nrhs, opts):
         assert bits_equal(X2, X)
 
 
+@pytest.mark.parametrize("nrhs", [2, 5, 9])
+@pytest.mark.parametrize("assign", [0, 1, 2])
+def test_multi_rhs_strided(sp, nrhs, assign):
+    """Column stride ld > n (row-slices of a wider buffer): the same bits as
+    the contiguous solve, nothing written outside the columns; power-law rows
+    long enough for several entry batches; FP32 within tolerance."""
+    o = oracle.get()
+    T = W.powerlaw_lower(30000, 13, window=3000)
+    F = np.stack([W.uniform_vector(T.n, 300 + r) for r in range(nrhs)], 0)
+    h = sp.Handle(*dev_tri(T)).configure(algo=2, assign=assign, grid=40)
+    X = host(h.solve_multi(dev(F)))
+    h.status()
+    assert relerr(X.T, o.solve_multi(T.row_ptr, T.col_idx, T.vals, F.T)) <= TOL64
+    wide = torch.zeros(nrhs, T.n + 7, dtype=torch.float64, device="cuda")
+    wide[:, :T.n] = dev(F)
+    Xw = torch.zeros_like(wide)
+    h.solve_multi(wide[:, :T.n], out=Xw[:, :T.n])
+    h.status()
+    assert bits_equal(host(Xw[:, :T.n]), X)
+    assert not host(Xw[:, T.n:]).any()
+    # a strided result allocated by the binding
+    Xs = h.solve_multi(wide[:, :T.n])
+    assert Xs.stride() == (T.n + 7, 1)
+    assert bits_equal(host(Xs), X)
+    with pytest.raises(ValueError):
+        h.solve_multi(wide[:, :T.n], out=torch.empty(nrhs, T.n, dtype=torch.float64, device="cuda"))
+    v32 = T.vals.astype(np.float32)
+    F32 = F.astype(np.float32)
+    h32 = sp.Handle(*dev_tri(T, torch.float32)).configure(algo=2, assign=assign)
+    X32 = host(h32.solve_multi(dev(F32)))
+    h32.status()
+    ref = o.solve_multi(T.row_ptr, T.col_idx, v32.astype(np.float64), F32.T.astype(np.float64))
+    assert relerr(X32.T, ref) <= TOL32
+
+
 def test_batched(sp):
     o = oracle.get()
     tris = [W.ilu0_lower((s, s)) for s in (7, 33, 20, 64, 5, 41)]
