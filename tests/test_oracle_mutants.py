@@ -4,13 +4,21 @@ Each case copies oracle/sptrsv_oracle.c, replaces one fragment with a
 plausible mistake (a dropped term, a wrong sign or index, a transposed
 operand, a reversed sweep), compiles the copy on the CPU and runs every pin
 against it: at least one pin has to fail.  The real oracle is never touched.
+
+A mutant can index out of bounds and corrupt the memory of the process that
+runs it, so each mutant runs its pins in a child process of its own; a child
+that dies before reporting (a crash) has been caught as well.
 """
+import concurrent.futures as cf
+import json
 import os
+import subprocess
+import sys
+import tempfile
 
 import pytest
 
 import oracle
-from pins import ALL_PINS
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "sptrsv_oracle.c")
 
@@ -58,18 +66,55 @@ MUTANTS = [
 ]
 
 
-@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
-def test_mutant_is_caught(tmp_path, name, old, new):
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+TESTS = os.path.dirname(os.path.abspath(__file__))
+
+# run in a child: load the mutant library, run every pin, report the failures
+_CHILD = r"""
+import json, sys
+sys.path[:0] = [sys.argv[2], sys.argv[3]]
+import oracle
+from pins import ALL_PINS
+o = oracle.Oracle(oracle.load_library(sys.argv[1]))
+failed = []
+for pin in ALL_PINS:
+    try:
+        pin(o)
+    except (AssertionError, ValueError, IndexError):
+        failed.append(pin.__name__)
+print("PINS_FAILED " + json.dumps(failed), flush=True)
+"""
+
+
+def _run_mutant(workdir, name, old, new):
+    """(failed pin names or None if the child died first, child exit code)."""
     src = open(SRC).read()
-    assert src.count(old) == 1, "mutation anchor must be unique: %s" % name
-    mut = tmp_path / ("oracle_%s.c" % name)
-    mut.write_text(src.replace(old, new))
-    lib_path = oracle.compile_oracle(str(mut), str(tmp_path / ("lib_%s.so" % name)))
-    o = oracle.Oracle(oracle.load_library(lib_path))
-    failed = []
-    for pin in ALL_PINS:
-        try:
-            pin(o)
-        except (AssertionError, ValueError, IndexError) as e:   # a caught mistake
-            failed.append(pin.__name__)
-    assert failed, "no pin caught mutant %s" % name
+    if src.count(old) != 1:
+        return "anchor", None
+    mut = os.path.join(workdir, "oracle_%s.c" % name)
+    with open(mut, "w") as f:
+        f.write(src.replace(old, new))
+    lib_path = oracle.compile_oracle(mut, os.path.join(workdir, "lib_%s.so" % name))
+    r = subprocess.run([sys.executable, "-c", _CHILD, lib_path, ROOT, TESTS], capture_output=True,
+                       text=True, timeout=600, cwd=ROOT)
+    for line in r.stdout.splitlines():
+        if line.startswith("PINS_FAILED "):
+            return json.loads(line[len("PINS_FAILED "):]), r.returncode
+    return None, r.returncode
+
+
+@pytest.fixture(scope="module")
+def mutant_results():
+    with tempfile.TemporaryDirectory(prefix="oracle_mutants_") as d:
+        with cf.ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+            futs = {m[0]: ex.submit(_run_mutant, d, *m) for m in MUTANTS}
+            yield {k: f.result() for k, f in futs.items()}
+
+
+@pytest.mark.parametrize("name", [m[0] for m in MUTANTS])
+def test_mutant_is_caught(mutant_results, name):
+    failed, rc = mutant_results[name]
+    assert failed != "anchor", "mutation anchor must be unique: %s" % name
+    assert failed or failed is None, "no pin caught mutant %s" % name
+    if failed is None:   # died before reporting: the mistake is caught by the crash
+        assert rc != 0, "child of mutant %s ended without a report" % name
