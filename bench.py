@@ -243,7 +243,19 @@ def main():
         c1.record()
         c1.synchronize()
         cold.append(c0.elapsed_time(c1))
-    del flush
+    # measured device copy bandwidth (read + write bytes over time), the
+    # practical ceiling the HBM fraction is also given against
+    src, dst = flush[: 1 << 26], flush[1 << 26:]
+    for _ in range(3):
+        dst.copy_(src)
+    k0, k1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    k0.record()
+    for _ in range(10):
+        dst.copy_(src)
+    k1.record()
+    k1.synchronize()
+    copy_gbs = 2 * src.numel() * 8 * 10 / (k0.elapsed_time(k1) * 1e-3) / 1e9
+    del src, dst, flush
     ms_cold = float(np.median(cold))
 
     # critical-path bound: one producer-to-consumer hop per level
@@ -306,7 +318,9 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
                      "traffic": committed_traffic(kernel_name),
                      "kernel": kernel_name,
-                     "kernel_ms": round(kernel_ms, 5), "bytes_per_launch": lbL},
+                     "kernel_ms": round(kernel_ms, 5), "bytes_per_launch": lbL,
+                     "copy_gbs": round(copy_gbs, 1),
+                     "frac_of_copy": round(achieved / copy_gbs, 5)},
         "critical_path": {"nlev": nlev, "hop_ns_same_xcd": round(hop_same, 1),
                           "hop_ns_cross_xcd": round(hop_cross, 1),
                           "bound_ms_per_triangle": round(nlev * hop_same * 1e-6, 5),
