@@ -83,16 +83,19 @@ def committed_traffic(kernel):
 
 
 def cpu_info():
+    """(CPU model, logical CPUs visible, current clock in MHz or None)."""
     model = platform.processor()
+    mhz = None
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
-                if line.startswith("model name"):
+                if line.startswith("model name") and model == platform.processor():
                     model = line.split(":", 1)[1].strip()
-                    break
-    except OSError:
+                elif line.startswith("cpu MHz") and mhz is None:
+                    mhz = float(line.split(":", 1)[1])
+    except (OSError, ValueError):
         pass
-    return model, os.cpu_count()
+    return model, os.cpu_count(), mhz
 
 
 def cpu_baseline(TL, TU, bL, seconds):
@@ -328,11 +331,13 @@ def main():
     }
     if not args.no_cpu_baseline:
         t_cpu, reps = cpu_baseline(TL, TU, bL, args.cpu_seconds)
-        model, ncpu = cpu_info()
+        model, ncpu, mhz = cpu_info()
         out["cpu_baseline"] = {"value": round(step_bytes / t_cpu / 1e9, 4), "unit": "GB/s",
                                "cores": 1, "kind": "oracle",
                                "sample": "%d full L+U steps of the same workload (%.1f ms each) on %s, "
-                                         "%d host CPUs visible" % (reps, t_cpu * 1e3, model, ncpu)}
+                                         "%d host CPUs visible%s" % (
+                                             reps, t_cpu * 1e3, model, ncpu,
+                                             ", %.0f MHz" % mhz if mhz else "")}
     if args.copy_probe_mb:
         nbytes = args.copy_probe_mb << 20
         src = torch.empty(nbytes // 8, dtype=torch.float64, device=dev).fill_(1.0)
