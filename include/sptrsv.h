@@ -36,10 +36,15 @@
  *     push lists and their scratch; for T^T its analysis) with synchronous
  *     copies; later solves with that schedule perform no allocation, host
  *     synchronisation or memset, so they can be captured in a HIP graph.
- *     sptrsv_graph_capture prepares all of this itself.  Calls on one handle
- *     must be issued on one stream at a time: the handle's scratch (ticket,
- *     status, flags, epoch, the position-ordered solution, accumulators) is
- *     shared.
+ *     sptrsv_graph_capture prepares all of this itself.  The calls of one
+ *     handle that use its scratch (ticket, status, flags, epoch, the
+ *     position-ordered solution, accumulators, gathered values: solves,
+ *     value updates, tuning) are serialized across streams: the library
+ *     records an event after each, and a call issued on a different stream
+ *     than the previous one first makes its stream wait for that event.
+ *     Under graph capture nothing is recorded or waited for: the capturing
+ *     stream orders the graph, and the caller orders graph launches against
+ *     other work on the handle.
  *   - n = 0 is valid and every solve on it is a no-op.
  *   - Dependencies are taken from the pattern (Sec. 4.4): an explicitly
  *     stored zero off-diagonal still counts as a dependency.

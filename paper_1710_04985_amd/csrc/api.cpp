@@ -143,6 +143,10 @@ struct sptrsv_handle_s {
   double acc_ms = 0.0;
   int64_t acc_count = 0;
   hipStream_t last_stream = nullptr;
+  // cross-stream ordering of the work that uses the handle's buffers
+  hipEvent_t order_ev = nullptr;
+  hipStream_t order_stream = nullptr;
+  bool order_pending = false;
 };
 
 struct sptrsv_graph_s {
@@ -746,10 +750,47 @@ int solve_impl(sptrsv_handle_t h, PlanState& ps, const Config& c_in, const void*
   return kOk;
 }
 
+// Work on a handle's buffers (its position-ordered solution, flags,
+// counters, gathered values) issued on a different stream than the previous
+// such work first waits for that work: the library records an event after
+// each, so calls on several streams are serialized instead of racing.  Under
+// graph capture nothing is recorded or waited for (the capturing stream
+// orders the graph; the caller orders graph launches).
+int order_begin(sptrsv_handle_t h, hipStream_t s, bool* capturing) {
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cap) != hipSuccess) return kErrHip;
+  *capturing = cap != hipStreamCaptureStatusNone;
+  if (*capturing || !h->order_pending || h->order_stream == s) return kOk;
+  HIPCHK(hipStreamWaitEvent(s, h->order_ev, 0));
+  return kOk;
+}
+
+int order_end(sptrsv_handle_t h, hipStream_t s, bool capturing) {
+  if (capturing) return kOk;
+  if (!h->order_ev) HIPCHK(hipEventCreateWithFlags(&h->order_ev, hipEventDisableTiming));
+  HIPCHK(hipEventRecord(h->order_ev, s));
+  h->order_stream = s;
+  h->order_pending = true;
+  return kOk;
+}
+
+int solve_dispatch_ordered(sptrsv_handle_t h, bool transpose, const void* b, void* x, int nrhs,
+                           int ld, hipStream_t s);
+
 int solve_dispatch(sptrsv_handle_t h, bool transpose, const void* b, void* x, int nrhs, int ld,
                    hipStream_t s) {
   if (!h) return kErrInvalidArg;
   if (h->n > 0 && (!b || !x)) return kErrInvalidArg;
+  bool capturing = false;
+  int st = order_begin(h, s, &capturing);
+  if (st) return st;
+  st = solve_dispatch_ordered(h, transpose, b, x, nrhs, ld, s);
+  const int st2 = order_end(h, s, capturing);
+  return st ? st : st2;
+}
+
+int solve_dispatch_ordered(sptrsv_handle_t h, bool transpose, const void* b, void* x, int nrhs,
+                           int ld, hipStream_t s) {
   if (transpose) {
     const int st = build_transpose(h, s);
     if (st) return st;
@@ -868,6 +909,7 @@ void free_block(BlockState& b) {
 
 void destroy_handle(sptrsv_handle_t h) {
   if (!h) return;
+  if (h->order_ev) (void)hipEventDestroy(h->order_ev);
   free_plan(h->fwd);
   free_plan(h->trn);
   free_block(h->blk[0]);
@@ -1049,17 +1091,23 @@ int sptrsv_analyze_batched(int32_t count, const int32_t* n, const int32_t* nnz,
 int sptrsv_update_values(sptrsv_handle_t h, const void* vals, hipStream_t stream) {
   if (!h || (h->nnz > 0 && !vals)) return kErrInvalidArg;
   if (h->batched) return kErrInvalidArg;
-  int st = gather(h, h->fwd, vals, stream);
+  bool capturing = false;
+  int st = order_begin(h, stream, &capturing);
+  if (st) return st;
+  st = gather(h, h->fwd, vals, stream);
   if (!st && h->trn.built) st = gather(h, h->trn, h->fwd.vals_buf, stream);
   if (!st && h->blk[0].built) st = gather(h, h->blk[0].ps, h->fwd.vals_buf, stream);
   if (!st && h->blk[1].built) st = gather(h, h->blk[1].ps, h->trn.vals_buf, stream);
   if (!st) st = regather_push(h, stream);
   h->last_stream = stream;
-  return st;
+  const int st2 = order_end(h, stream, capturing);
+  return st ? st : st2;
 }
 
 int sptrsv_update_values_batched(sptrsv_handle_t h, const void* const* vals, hipStream_t stream) {
   if (!h || !vals || !h->batched) return kErrInvalidArg;
+  bool capturing = false;
+  if (const int st0 = order_begin(h, stream, &capturing)) return st0;
   int64_t eoff = 0;
   for (size_t s = 0; s < h->sys_n.size(); ++s) {
     if (h->sys_nnz[s] > 0) {
@@ -1076,7 +1124,8 @@ int sptrsv_update_values_batched(sptrsv_handle_t h, const void* const* vals, hip
   if (!st && h->blk[1].built) st = gather(h, h->blk[1].ps, h->trn.vals_buf, stream);
   if (!st) st = regather_push(h, stream);
   h->last_stream = stream;
-  return st;
+  const int st2 = order_end(h, stream, capturing);
+  return st ? st : st2;
 }
 
 int sptrsv_solve(sptrsv_handle_t h, const void* b, void* x, hipStream_t stream) {
@@ -1255,6 +1304,9 @@ int sptrsv_tune(sptrsv_handle_t h, const void* b, void* x, hipStream_t stream) {
     if (st0) return st0;
     cand.push_back({SPTRSV_ALGO_BLOCK, 0, 4, SPTRSV_SYNC_VALUE, 1, 0, SPTRSV_ASSIGN_TICKET});
   }
+  bool capturing = false;
+  if (const int so = order_begin(h, stream, &capturing)) return so;
+  if (capturing) return kErrNotSupported;
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
@@ -1302,6 +1354,7 @@ int sptrsv_tune(sptrsv_handle_t h, const void* b, void* x, hipStream_t stream) {
   if (st) return st;
   st = read_status(h, stream, true);
   if (st) return st;
+  if ((st = order_end(h, stream, false))) return st;
   h->tuned = true;
   h->tuned_cfg = best_c;
   std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1329,6 +1382,9 @@ int sptrsv_tune_multi(sptrsv_handle_t h, int32_t nrhs, int32_t ld, const void* B
   if (h->algo == SPTRSV_ALGO_AUTO || h->algo == SPTRSV_ALGO_LEVEL || h->algo == SPTRSV_ALGO_BLOCK ||
       cand.empty())
     cand.push_back({SPTRSV_ALGO_LEVEL, 0, 4, SPTRSV_SYNC_VALUE, 1, 0, SPTRSV_ASSIGN_TICKET});
+  bool capturing = false;
+  if (const int so = order_begin(h, stream, &capturing)) return so;
+  if (capturing) return kErrNotSupported;
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
@@ -1363,6 +1419,7 @@ int sptrsv_tune_multi(sptrsv_handle_t h, int32_t nrhs, int32_t ld, const void* B
   (void)hipEventDestroy(e1);
   if (st) return st;
   if ((st = read_status(h, stream, true))) return st;
+  if ((st = order_end(h, stream, false))) return st;
   h->tuned_multi[nrhs] = best_c;
   return kOk;
 }

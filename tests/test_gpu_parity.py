@@ -282,6 +282,37 @@ def test_multi_rhs_strided(sp, nrhs, assign):
     assert relerr(X32.T, ref) <= TOL32
 
 
+def test_two_streams_are_serialized(sp):
+    """Solves of one handle issued on two streams without any ordering by the
+    caller: the library makes each stream wait for the handle's previous
+    solve, so neither races on the shared scratch; with a value update in
+    between on a third stream."""
+    o = oracle.get()
+    T = W.laplacian_triangle((40, 40, 40))
+    bs = [W.uniform_vector(T.n, 60 + k) for k in range(4)]
+    h = sp.Handle(*dev_tri(T)).configure(algo=2, assign=2)
+    s1, s2, s3 = torch.cuda.Stream(), torch.cuda.Stream(), torch.cuda.Stream()
+    bd = [dev(b) for b in bs]
+    torch.cuda.synchronize()
+    outs = []
+    for k in range(8):
+        st = s1 if k % 2 == 0 else s2
+        with torch.cuda.stream(st):
+            outs.append(h.solve(bd[k % 4], stream=st))
+    v2 = dev(T.vals * 0.5)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s3):
+        h.update_values(v2, stream=s3)
+    with torch.cuda.stream(s1):
+        after = h.solve(bd[0], stream=s1)
+    torch.cuda.synchronize()
+    h.status()
+    for k in range(8):
+        ref = o.solve(T.row_ptr, T.col_idx, T.vals, bs[k % 4])
+        assert relerr(host(outs[k]), ref) <= TOL64, k
+    assert relerr(host(after), o.solve(T.row_ptr, T.col_idx, T.vals * 0.5, bs[0])) <= TOL64
+
+
 def test_batched(sp):
     o = oracle.get()
     tris = [W.ilu0_lower((s, s)) for s in (7, 33, 20, 64, 5, 41)]
