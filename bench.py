@@ -56,7 +56,7 @@ def parse():
                     help="also time the host and device setup routes (bench_setup.jsonl)")
     ap.add_argument("--table2", action="store_true",
                     help="also run the Table 2 grid sweep (bench_table2.jsonl)")
-    ap.add_argument("--out-dir", default="gpurun_out",
+    ap.add_argument("--out-dir", default="bench_results",
                     help="folder (relative to this file) for the extra JSON lines")
     return ap.parse_args()
 
@@ -118,7 +118,7 @@ def cpu_baseline(TL, TU, bL, seconds):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: this library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch

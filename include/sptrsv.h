@@ -74,7 +74,7 @@ typedef enum {
     SPTRSV_ERR_HIP = -8,            /* a HIP runtime call failed */
     SPTRSV_ERR_OOM = -9,            /* device or host allocation failed */
     SPTRSV_ERR_TIMEOUT = -10,       /* self-scheduled wait exceeded its spin limit */
-    SPTRSV_ERR_NOT_SUPPORTED = -11  /* valid request this build does not implement */
+    SPTRSV_ERR_NOT_SUPPORTED = -11  /* valid request the library does not implement */
 } sptrsv_status;
 
 typedef enum { SPTRSV_F64 = 0, SPTRSV_F32 = 1 } sptrsv_dtype;
