@@ -322,7 +322,9 @@ int sptrsv_get_status(sptrsv_handle_t h);
 
 /* Accumulated duration of the main solve kernels recorded while
  * SPTRSV_OPT_TIMING = 1 (milliseconds, HIP events on the solve stream) and
- * the number of launches timed; synchronises.  reset != 0 clears both. */
+ * the number of launches timed; synchronises.  reset != 0 clears both.
+ * The handle keeps at most 1024 pending event pairs: the next timed solve
+ * first folds them into the totals, waiting for the oldest to finish. */
 int sptrsv_kernel_time(sptrsv_handle_t h, double *ms, int64_t *count, int reset);
 
 const char *sptrsv_status_string(int status);

@@ -50,17 +50,23 @@ def _need_cuda(t, name, dtype=None, dense=True):
         raise ValueError("%s must be contiguous" % name)
 
 
+def _need_vec(t, name, dtype, numel):
+    """A contiguous CUDA tensor of `dtype` with exactly `numel` elements (the
+    kernels read or write that many: a shorter buffer would be overrun)."""
+    _need_cuda(t, name, dtype)
+    if t.numel() != numel:
+        raise ValueError("%s has %d elements, expected %d" % (name, t.numel(), numel))
+
+
 class _Base:
     _h = None
     n = 0
     dtype = torch.float64
 
     def _solve(self, fn, b, out, stream):
-        _need_cuda(b, "b", self.dtype)
-        if b.numel() != self.n:
-            raise ValueError("b has %d elements, expected %d" % (b.numel(), self.n))
+        _need_vec(b, "b", self.dtype, self.n)
         x = torch.empty_like(b) if out is None else out
-        _need_cuda(x, "out", self.dtype)
+        _need_vec(x, "out", self.dtype, self.n)
         check(fn(self._h, _ptr(b), _ptr(x), _stream(stream)))
         return x
 
@@ -113,7 +119,10 @@ class _Base:
         return self
 
     def tune(self, b, x=None, stream=None):
+        """Times the candidate schedules on b (x is scratch output, not b)."""
+        _need_vec(b, "b", self.dtype, self.n)
         x = torch.empty_like(b) if x is None else x
+        _need_vec(x, "x", self.dtype, self.n)
         check(lib.sptrsv_tune(self._h, _ptr(b), _ptr(x), _stream(stream)))
         return self.info()
 
@@ -124,6 +133,7 @@ class _Base:
         if B.dim() != 2 or B.shape[1] != self.n or B.shape[0] < 2:
             raise ValueError("B must be (nrhs >= 2, n)")
         X = torch.empty_like(B) if X is None else X
+        _need_vec(X, "X", self.dtype, B.numel())
         check(lib.sptrsv_tune_multi(self._h, B.shape[0], self.n, _ptr(B), _ptr(X), _stream(stream)))
 
     def info(self):
@@ -164,6 +174,8 @@ class _Base:
 
     def capture(self, b, x, transpose=False, stream=None):
         """HIP graph of one solve on fixed b/x (stream must not be the default)."""
+        _need_vec(b, "b", self.dtype, self.n)
+        _need_vec(x, "x", self.dtype, self.n)
         s = torch.cuda.current_stream() if stream is None else stream
         g = ctypes.c_void_p()
         check(lib.sptrsv_graph_capture(self._h, _ptr(b), _ptr(x), int(transpose),
@@ -225,6 +237,8 @@ class Handle(_Base):
             raise TypeError("vals must be float64 or float32")
         if setup not in SETUP:
             raise ValueError("setup must be one of %s" % sorted(SETUP))
+        if vals.numel() != col_idx.numel():
+            raise ValueError("vals has %d entries, col_idx %d" % (vals.numel(), col_idx.numel()))
         self.n = row_ptr.numel() - 1
         self.nnz = col_idx.numel()
         self.dtype = vals.dtype
@@ -247,15 +261,16 @@ class Handle(_Base):
         return {v: k for k, v in SETUP.items()}[route.value], ms.value
 
     def update_values(self, vals, stream=None):
-        _need_cuda(vals, "vals", self.dtype)
-        if vals.numel() != self.nnz:
-            raise ValueError("vals has %d entries, expected %d" % (vals.numel(), self.nnz))
+        _need_vec(vals, "vals", self.dtype, self.nnz)
         check(lib.sptrsv_update_values(self._h, _ptr(vals), _stream(stream)))
         self.vals = vals
 
     def grad_vals(self, grad_b, x, out=None, stream=None):
         """-grad_b[i] * x[j] for each stored entry (i, j), in CSR entry order."""
+        _need_vec(grad_b, "grad_b", self.dtype, self.n)
+        _need_vec(x, "x", self.dtype, self.n)
         gv = torch.empty(self.nnz, dtype=self.dtype, device=grad_b.device) if out is None else out
+        _need_vec(gv, "out", self.dtype, self.nnz)
         check(lib.sptrsv_grad_vals(self._h, _ptr(self.row_ptr), _ptr(self.col_idx), _ptr(grad_b),
                                    _ptr(x), _ptr(gv), _stream(stream)))
         return gv
@@ -270,10 +285,12 @@ class BatchedHandle(_Base):
         if not (count == len(col_idxs) == len(valss)) or count == 0:
             raise ValueError("need the same positive number of row_ptrs, col_idxs, vals")
         dt = valss[0].dtype
+        if dt not in _DT:
+            raise TypeError("vals must be float64 or float32")
         for i in range(count):
             _need_cuda(row_ptrs[i], "row_ptr", torch.int32)
             _need_cuda(col_idxs[i], "col_idx", torch.int32)
-            _need_cuda(valss[i], "vals", dt)
+            _need_vec(valss[i], "vals", dt, col_idxs[i].numel())
         self.count = count
         self.sizes = [r.numel() - 1 for r in row_ptrs]
         self.nnzs = [c.numel() for c in col_idxs]
@@ -292,6 +309,10 @@ class BatchedHandle(_Base):
         self._h = h
 
     def update_values(self, valss, stream=None):
+        if len(valss) != self.count:
+            raise ValueError("need %d value tensors, got %d" % (self.count, len(valss)))
+        for v, nz in zip(valss, self.nnzs):
+            _need_vec(v, "vals", self.dtype, nz)
         P = ctypes.c_void_p * self.count
         ptrs = P(*[v.data_ptr() for v in valss])
         check(lib.sptrsv_update_values_batched(self._h, ctypes.cast(ptrs, ctypes.c_void_p),
@@ -299,7 +320,10 @@ class BatchedHandle(_Base):
         self._keep = (self._keep[0], self._keep[1], list(valss))
 
     def grad_vals(self, grad_b, x, out=None, stream=None):
+        _need_vec(grad_b, "grad_b", self.dtype, self.n)
+        _need_vec(x, "x", self.dtype, self.n)
         gv = torch.empty(self.nnz, dtype=self.dtype, device=grad_b.device) if out is None else out
+        _need_vec(gv, "out", self.dtype, self.nnz)
         check(lib.sptrsv_grad_vals(self._h, None, None, _ptr(grad_b), _ptr(x), _ptr(gv),
                                    _stream(stream)))
         return gv

@@ -218,6 +218,15 @@ const WaveLists* get_wave_lists(ChunkEntry& ch, int W, int regions, int* err) {
   return &(ch.waves[key] = wl);
 }
 
+void free_push(PushState& p) {
+  for (auto& kv : p.chunks) free_entry(kv.second);
+  dfree(p.d.ptr);
+  dfree(p.d.dst);
+  dfree(p.d.src);
+  dfree(p.d.val);
+  p = PushState();
+}
+
 void free_plan(PlanState& ps) {
   free_chunks(ps);
   dfree(ps.d.off_ptr);
@@ -227,11 +236,7 @@ void free_plan(PlanState& ps) {
   dfree(ps.d.diag_src);
   dfree(ps.d.pos_row);
   dfree(ps.vals_buf);
-  dfree(ps.push.d.ptr);
-  dfree(ps.push.d.dst);
-  dfree(ps.push.d.src);
-  dfree(ps.push.d.val);
-  ps.push = PushState();
+  free_push(ps.push);
   ps.d = DevPlan();
   ps.vals_buf = nullptr;
   ps.built = false;
@@ -344,12 +349,13 @@ int build_transpose(sptrsv_handle_t h, hipStream_t s) {
   for (auto& v : sT) v = loc[v];
   build_plan(n, rT.data(), cT.data(), sT.data(), !h->upper, h->unit, h->trn.h);
   int st = upload_plan(h->trn, h->vb, s);
-  if (st) return st;
-  st = gather(h, h->trn, h->fwd.vals_buf, s);
-  if (st) return st;
-  HIPCHK(hipStreamSynchronize(s));
-  return kOk;
+  if (!st) st = gather(h, h->trn, h->fwd.vals_buf, s);
+  if (!st && hipStreamSynchronize(s) != hipSuccess) st = kErrHip;
+  if (st) free_plan(h->trn);   // a later call starts over instead of using half a plan
+  return st;
 }
+
+void free_block(BlockState& b);
 
 // Builds the block-ordered plan of direction `dir` (0: T, 1: T^T): one
 // segment per system of a batched handle, else one; values are gathered from
@@ -366,12 +372,15 @@ int build_block(sptrsv_handle_t h, int dir, hipStream_t s) {
     seg_row0.push_back(h->n);
   build_block_plan(base.h, seg_row0, b.ps.h, b.info);
   int st = upload_plan(b.ps, h->vb, s);
-  if (st) return st;
-  if ((st = upload_ints(&b.seg_row0, b.info.seg_row0, s))) return st;
-  if ((st = upload_ints(&b.seg_base, b.info.seg_base, s))) return st;
-  if ((st = upload_ints(&b.lev_pos, b.info.lev_pos, s))) return st;
-  if ((st = gather(h, b.ps, base.vals_buf, s))) return st;
-  HIPCHK(hipStreamSynchronize(s));
+  if (!st) st = upload_ints(&b.seg_row0, b.info.seg_row0, s);
+  if (!st) st = upload_ints(&b.seg_base, b.info.seg_base, s);
+  if (!st) st = upload_ints(&b.lev_pos, b.info.lev_pos, s);
+  if (!st) st = gather(h, b.ps, base.vals_buf, s);
+  if (!st && hipStreamSynchronize(s) != hipSuccess) st = kErrHip;
+  if (st) {
+    free_block(b);   // nothing half-built stays behind
+    return st;
+  }
   b.built = true;
   return kOk;
 }
@@ -514,11 +523,28 @@ int persistent_grid(sptrsv_handle_t h, int kind, int grid, int nchunks) {
   return std::max(1, std::min(g, need));
 }
 
+// Adds the recorded kernel times to the handle's totals and frees the event
+// pairs for reuse (waits for the recorded stops).
+int fold_timing(sptrsv_handle_t h) {
+  for (size_t i = 0; i < h->ev_used; ++i) {
+    HIPCHK(hipEventSynchronize(h->ev_pool[i].second));
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, h->ev_pool[i].first, h->ev_pool[i].second));
+    h->acc_ms += t;
+    h->acc_count++;
+  }
+  h->ev_used = 0;
+  return kOk;
+}
+
+constexpr size_t kMaxTimedSolves = 1024;   // event pairs kept before they are folded
+
 void timing_begin(sptrsv_handle_t h, hipStream_t s, hipEvent_t* stop) {
   *stop = nullptr;
   if (!h->timing) return;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+  if (h->ev_used == kMaxTimedSolves && fold_timing(h) != kOk) return;
   if (h->ev_used == h->ev_pool.size()) {
     hipEvent_t a, b;
     if (hipEventCreate(&a) != hipSuccess) return;
@@ -575,17 +601,22 @@ int build_push_state(sptrsv_handle_t h, PlanState& ps, hipStream_t s) {
   d.val = dalloc<char>(dst.size() * h->vb, &err);
   if (!h->col_acc) h->col_acc = dalloc<char>(static_cast<size_t>(h->n) * h->vb, &err);
   if (!h->col_cnt) h->col_cnt = dalloc<int>(static_cast<size_t>(h->n), &err);
-  if (err) return err;
-  HIPCHK(hipMemcpy(d.ptr, ps.push.h_ptr.data(), ps.push.h_ptr.size() * sizeof(int),
-                   hipMemcpyHostToDevice));
-  if (!dst.empty()) {
-    HIPCHK(hipMemcpy(d.dst, dst.data(), dst.size() * sizeof(int), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(d.src, src.data(), src.size() * sizeof(int), hipMemcpyHostToDevice));
+  if (!err &&
+      (hipMemcpy(d.ptr, ps.push.h_ptr.data(), ps.push.h_ptr.size() * sizeof(int),
+                 hipMemcpyHostToDevice) != hipSuccess ||
+       (!dst.empty() &&
+        (hipMemcpy(d.dst, dst.data(), dst.size() * sizeof(int), hipMemcpyHostToDevice) !=
+             hipSuccess ||
+         hipMemcpy(d.src, src.data(), src.size() * sizeof(int), hipMemcpyHostToDevice) !=
+             hipSuccess)) ||
+       (h->dtype == SPTRSV_F64 ? launch_push_gather<double>(ps.d, d, s)
+                               : launch_push_gather<float>(ps.d, d, s)) != hipSuccess ||
+       hipStreamSynchronize(s) != hipSuccess))
+    err = kErrHip;
+  if (err) {
+    free_push(ps.push);   // a later call starts over
+    return err;
   }
-  const hipError_t e = h->dtype == SPTRSV_F64 ? launch_push_gather<double>(ps.d, d, s)
-                                               : launch_push_gather<float>(ps.d, d, s);
-  if (e != hipSuccess) return kErrHip;
-  HIPCHK(hipStreamSynchronize(s));
   ps.push.built = true;
   return kOk;
 }
@@ -1106,19 +1137,21 @@ int sptrsv_update_values(sptrsv_handle_t h, const void* vals, hipStream_t stream
 
 int sptrsv_update_values_batched(sptrsv_handle_t h, const void* const* vals, hipStream_t stream) {
   if (!h || !vals || !h->batched) return kErrInvalidArg;
+  for (size_t s = 0; s < h->sys_n.size(); ++s)
+    if (h->sys_nnz[s] > 0 && !vals[s]) return kErrInvalidArg;
   bool capturing = false;
   if (const int st0 = order_begin(h, stream, &capturing)) return st0;
+  int st = kOk;
   int64_t eoff = 0;
-  for (size_t s = 0; s < h->sys_n.size(); ++s) {
-    if (h->sys_nnz[s] > 0) {
-      if (!vals[s]) return kErrInvalidArg;
-      HIPCHK(hipMemcpyAsync(static_cast<char*>(h->vals_cat) + eoff * h->vb, vals[s],
-                            static_cast<size_t>(h->sys_nnz[s]) * h->vb, hipMemcpyDeviceToDevice,
-                            stream));
-    }
+  for (size_t s = 0; s < h->sys_n.size() && !st; ++s) {
+    if (h->sys_nnz[s] > 0 &&
+        hipMemcpyAsync(static_cast<char*>(h->vals_cat) + eoff * h->vb, vals[s],
+                       static_cast<size_t>(h->sys_nnz[s]) * h->vb, hipMemcpyDeviceToDevice,
+                       stream) != hipSuccess)
+      st = kErrHip;
     eoff += h->sys_nnz[s];
   }
-  int st = gather(h, h->fwd, h->vals_cat, stream);
+  if (!st) st = gather(h, h->fwd, h->vals_cat, stream);
   if (!st && h->trn.built) st = gather(h, h->trn, h->fwd.vals_buf, stream);
   if (!st && h->blk[0].built) st = gather(h, h->blk[0].ps, h->fwd.vals_buf, stream);
   if (!st && h->blk[1].built) st = gather(h, h->blk[1].ps, h->trn.vals_buf, stream);
@@ -1309,7 +1342,10 @@ int sptrsv_tune(sptrsv_handle_t h, const void* b, void* x, hipStream_t stream) {
   if (capturing) return kErrNotSupported;
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
-  HIPCHK(hipEventCreate(&e1));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return kErrHip;
+  }
   const int saved_timing = h->timing;
   h->timing = 0;
   float best = 1e30f;
@@ -1351,10 +1387,9 @@ int sptrsv_tune(sptrsv_handle_t h, const void* b, void* x, hipStream_t stream) {
   h->timing = saved_timing;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  if (st) return st;
-  st = read_status(h, stream, true);
-  if (st) return st;
-  if ((st = order_end(h, stream, false))) return st;
+  if (!st) st = read_status(h, stream, true);
+  const int so = order_end(h, stream, false);   // the trials used the handle's buffers
+  if (st || (st = so)) return st;
   h->tuned = true;
   h->tuned_cfg = best_c;
   std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1387,7 +1422,10 @@ int sptrsv_tune_multi(sptrsv_handle_t h, int32_t nrhs, int32_t ld, const void* B
   if (capturing) return kErrNotSupported;
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
-  HIPCHK(hipEventCreate(&e1));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return kErrHip;
+  }
   const int saved_timing = h->timing;
   h->timing = 0;
   float best = 1e30f;
@@ -1417,9 +1455,9 @@ int sptrsv_tune_multi(sptrsv_handle_t h, int32_t nrhs, int32_t ld, const void* B
   h->timing = saved_timing;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  if (st) return st;
-  if ((st = read_status(h, stream, true))) return st;
-  if ((st = order_end(h, stream, false))) return st;
+  if (!st) st = read_status(h, stream, true);
+  const int so = order_end(h, stream, false);
+  if (st || (st = so)) return st;
   h->tuned_multi[nrhs] = best_c;
   return kOk;
 }
@@ -1509,14 +1547,7 @@ int sptrsv_get_status(sptrsv_handle_t h) {
 
 int sptrsv_kernel_time(sptrsv_handle_t h, double* ms, int64_t* count, int reset) {
   if (!h) return kErrInvalidArg;
-  for (size_t i = 0; i < h->ev_used; ++i) {
-    HIPCHK(hipEventSynchronize(h->ev_pool[i].second));
-    float t = 0.f;
-    HIPCHK(hipEventElapsedTime(&t, h->ev_pool[i].first, h->ev_pool[i].second));
-    h->acc_ms += t;
-    h->acc_count++;
-  }
-  h->ev_used = 0;
+  if (const int st = fold_timing(h)) return st;
   if (ms) *ms = h->acc_ms;
   if (count) *count = h->acc_count;
   if (reset) {

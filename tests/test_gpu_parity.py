@@ -405,6 +405,42 @@ def test_validation_errors(sp):
     assert e.value.status == -6
 
 
+def test_binding_rejects_short_buffers(sp):
+    """Buffers of the wrong length or type are refused before any launch (a
+    kernel would otherwise read or write past their end)."""
+    T = W.laplacian_triangle((6, 5))
+    n = T.n
+    with pytest.raises(ValueError):
+        sp.Handle(dev(T.row_ptr), dev(T.col_idx), dev(T.vals[:-1]))
+    h = sp.Handle(dev(T.row_ptr), dev(T.col_idx), dev(T.vals))
+    b = dev(np.ones(n))
+    for bad in (torch.empty(n - 1, dtype=torch.float64, device=DEV),
+                torch.empty(n, dtype=torch.float32, device=DEV)):
+        with pytest.raises((ValueError, TypeError)):
+            h.solve(b, out=bad)
+        with pytest.raises((ValueError, TypeError)):
+            h.solve_t(bad)
+        with pytest.raises((ValueError, TypeError)):
+            h.tune(b, bad)
+        with pytest.raises((ValueError, TypeError)):
+            h.capture(b, bad)
+        with pytest.raises((ValueError, TypeError)):
+            h.grad_vals(b, bad)
+    with pytest.raises(ValueError):
+        h.update_values(dev(T.vals[:-2]))
+    with pytest.raises(ValueError):
+        h.grad_vals(b, b, out=torch.empty(T.nnz - 1, dtype=torch.float64, device=DEV))
+    bh = sp.BatchedHandle([dev(T.row_ptr)] * 2, [dev(T.col_idx)] * 2, [dev(T.vals)] * 2)
+    with pytest.raises(ValueError):
+        bh.update_values([dev(T.vals)])
+    with pytest.raises(ValueError):
+        bh.update_values([dev(T.vals), dev(T.vals[:-1])])
+    # the handle still solves correctly after the refused calls
+    x = host(h.solve(b))
+    ref = oracle.get().solve(T.row_ptr, T.col_idx, T.vals, np.ones(n))
+    assert relerr(x, ref) <= TOL64
+
+
 def test_empty_and_single(sp):
     h = sp.Handle(dev(np.zeros(1, np.int32)), dev(np.zeros(0, np.int32)), dev(np.zeros(0)))
     x = h.solve(dev(np.zeros(0)))
