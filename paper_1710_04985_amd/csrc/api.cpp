@@ -51,7 +51,7 @@ struct PlanState {
   HostPlan h;
   DevPlan d;
   PushState push;
-  void* vals_buf = nullptr;       // [noff + n] values: off-diagonals then diagonal
+  void* vals_buf = nullptr;       // [noff + 2n] values: off-diagonals, diagonal, 1/diagonal
   // (group, epl, rows_fixed, rows_per_lane)
   std::map<std::tuple<int, int, int, int>, ChunkEntry> chunks;
 };
@@ -266,10 +266,11 @@ int upload_plan(PlanState& ps, size_t vb, hipStream_t s) {
   if ((st = upload_ints(&d.diag_src, h.diag_src, s))) return st;
   if ((st = upload_ints(&d.pos_row, h.pos_row, s))) return st;
   int err = kOk;
-  ps.vals_buf = dalloc<char>((static_cast<size_t>(h.noff) + h.n) * vb, &err);
+  ps.vals_buf = dalloc<char>((static_cast<size_t>(h.noff) + 2 * static_cast<size_t>(h.n)) * vb, &err);
   if (!ps.vals_buf) return err;
   d.off_val = ps.vals_buf;
   d.diag = static_cast<char*>(ps.vals_buf) + static_cast<size_t>(h.noff) * vb;
+  d.dinv = static_cast<char*>(d.diag) + static_cast<size_t>(h.n) * vb;
   ps.built = true;
   return kOk;
 }
@@ -911,10 +912,12 @@ int analyze_on_device(sptrsv_handle_t h, const int* row_ptr, const int* col_idx,
   h->dev_jlev = da.jlev;
   h->host_plan = false;
   int err = kOk;
-  h->fwd.vals_buf = dalloc<char>((static_cast<size_t>(da.noff) + h->n) * h->vb, &err);
+  h->fwd.vals_buf =
+      dalloc<char>((static_cast<size_t>(da.noff) + 2 * static_cast<size_t>(h->n)) * h->vb, &err);
   if (!h->fwd.vals_buf) return err;
   d.off_val = h->fwd.vals_buf;
   d.diag = static_cast<char*>(h->fwd.vals_buf) + static_cast<size_t>(da.noff) * h->vb;
+  d.dinv = static_cast<char*>(d.diag) + static_cast<size_t>(h->n) * h->vb;
   h->fwd.built = true;
   // the handle's own copy of the pattern, for what is built later
   h->rp_dev = dalloc<int>(static_cast<size_t>(h->n) + 1, &err);

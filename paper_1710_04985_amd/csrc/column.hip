@@ -2,8 +2,8 @@
 // Sec. 3.2 for the sweep, Sec. 4.1 LEVC, Sec. 4.2 SLFC).
 //
 // Position k holds acc[k] = b_i minus every update pushed so far (i the row
-// solved at k).  Once all in-degree(k) updates have arrived, x_i = acc[k] /
-// d_i; the column then adds -T(j,i) x_i to acc of each dependent position
+// solved at k).  Once all in-degree(k) updates have arrived, x_i = acc[k] *
+// (1 / d_i); the column then adds -T(j,i) x_i to acc of each dependent position
 // and, in the self-scheduled form, counts one arrival there.  The updates
 // land in an order fixed by timing, so results match the row-wise solves to
 // rounding, not bit for bit.
@@ -38,7 +38,7 @@ __device__ __attribute__((noinline)) void wait_count(const int* p, int target, i
 
 template <typename T> struct CArgs {
   const int* off_ptr;    // in-degree of position k = off_ptr[k+1] - off_ptr[k]
-  const T* diag;
+  const T* dinv;   // 1 / diagonal, by position
   const int* pos_row;
   const int* push_ptr;
   const int* push_dst;
@@ -128,7 +128,7 @@ __device__ __forceinline__ void column_chunk(const CArgs<T>& a, int st, int meta
   } else {
     v = a.acc[k];
   }
-  const T xk = v / a.diag[k];
+  const T xk = v * a.dinv[k];
   if (g == 0) a.x[a.pos_row[k]] = xk;
   push_column<T, kSelf>(a, a.push_ptr[k] + g, a.push_ptr[k + 1], G, xk);
 }
@@ -164,7 +164,7 @@ k_column_self(CArgs<T> a, const int* __restrict__ cstart, const int* __restrict_
 template <typename T> CArgs<T> make_cargs(const ColumnArgs& s) {
   CArgs<T> a;
   a.off_ptr = s.plan->off_ptr;
-  a.diag = static_cast<const T*>(s.plan->diag);
+  a.dinv = static_cast<const T*>(s.plan->dinv);
   a.pos_row = s.plan->pos_row;
   a.push_ptr = s.push->ptr;
   a.push_dst = s.push->dst;

@@ -19,7 +19,8 @@ struct DevPlan {
   int* diag_src = nullptr;  // [n]
   int* pos_row = nullptr;   // [n]
   void* off_val = nullptr;  // [noff] T
-  void* diag = nullptr;     // [n] T
+  void* diag = nullptr;     // [n] T, the diagonal (source of other plans' values)
+  void* dinv = nullptr;     // [n] T, 1 / diagonal (what the solves multiply by)
 };
 
 // One chunk table on the device.

@@ -73,12 +73,12 @@ def test_column_solve_fp32(sp, algo):
 
 @pytest.mark.parametrize("algo", [LEVC, SLFC])
 def test_column_exact_cases(sp, algo):
-    """Diagonal: no updates, x = b/d; chain I - S with integer b: every
+    """Diagonal: no updates, x = b * (1/d); chain I - S with integer b: every
     partial sum is an integer below 2^53, so the order cannot matter."""
     d = W.uniform_vector(5000, 1, 0.5, 3.0)
     b = W.uniform_vector(5000, 2)
     h = sp.Handle(*dev_tri(W.diagonal_matrix(d))).configure(algo=algo)
-    assert np.array_equal(host(h.solve(dev(b))), b / d)
+    assert np.array_equal(host(h.solve(dev(b))), b * (1.0 / d))
     n = 100000 if algo == SLFC else 5000
     rng = np.random.Generator(np.random.PCG64(4))
     bi = rng.integers(-1000, 1000, n).astype(np.float64)

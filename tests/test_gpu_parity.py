@@ -176,13 +176,16 @@ def test_in_place(sp, opts):
 @pytest.mark.parametrize("opts", [dict(algo=1), dict(algo=2, sync=0), dict(algo=2, sync=1),
                                   dict(algo=2, sync=0, assign=1), dict(algo=3)])
 def test_exact_cases(sp, opts):
-    """Diagonal: x = b/d; chain I - S (nlev = n): prefix sums of
-    integers; bidiagonal (2, -1) with b = e_0: x_i = 2^-(i+1).  Bit-exact."""
+    """Diagonal: x = b * (1/d), the kernels' rounding (within 1.5 ulp of
+    b/d); chain I - S (nlev = n): prefix sums of integers; bidiagonal (2, -1)
+    with b = e_0: x_i = 2^-(i+1).  Bit-exact."""
     d = W.uniform_vector(5000, 1, 0.5, 3.0)
     D = W.diagonal_matrix(d)
     b = W.uniform_vector(5000, 2)
     h = sp.Handle(*dev_tri(D)).configure(**opts)
-    assert np.array_equal(host(h.solve(dev(b))), b / d)
+    x = host(h.solve(dev(b)))
+    assert np.array_equal(x, b * (1.0 / d))
+    assert np.all(np.abs(x - b / d) <= 1.5 * np.spacing(np.abs(b / d)))
     n = 200000 if opts["algo"] == 2 else 20000      # level-scheduled: one launch per row
     rng = np.random.Generator(np.random.PCG64(4))
     bi = rng.integers(-1000, 1000, n).astype(np.float64)
