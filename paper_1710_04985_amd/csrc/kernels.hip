@@ -151,7 +151,9 @@ __device__ __forceinline__ void wait_values(const T* xr, int xs, const int (&j)[
       for (int q = 0; q < N; ++q) pa[q] = load_agent(p[q]);
       take(pb);
       if (!pend) return;
-      if ((s & 15) == 1 && (load_status(status) & kStatusTimeout)) break;
+      // the status word only every 32 passes, and not in the first: waiting
+      // for its load also waits for every poll in flight
+      if ((s & 63) == 63 && (load_status(status) & kStatusTimeout)) break;
     }
   } else {
     for (int s = 1; s <= spin_limit; ++s) {
