@@ -162,3 +162,21 @@ def test_device_analysis_full_size_lap3d128(sp, upper):
     level, ilev, jlev, dep = h.export_analysis()
     assert np.array_equal(level, lv) and np.array_equal(ilev, il)
     assert np.array_equal(jlev, jl) and np.array_equal(dep, dc)
+
+
+def test_device_analysis_full_size_powerlaw(sp):
+    """The random power-law triangle (10^6 rows, rows of up to ~2000
+    dependencies): its long rows take the level sweep's whole-wavefront
+    reads.  Levels, level sets and counts bit-exact; the solve matches the
+    host route's bit for bit."""
+    print("device setup power-law 1e6", flush=True)
+    T, xs, b = W.c3_powerlaw()
+    h = _handle(sp, T, "device")
+    assert h.setup_info()[0] == "device"
+    lv, nlev, il, jl, dc = oracle.get().analyze(T.row_ptr, T.col_idx, T.upper)
+    assert h.info()["nlev"] == nlev
+    level, ilev, jlev, dep = h.export_analysis()
+    assert np.array_equal(level, lv) and np.array_equal(ilev, il)
+    assert np.array_equal(jlev, jl) and np.array_equal(dep, dc)
+    hh = _handle(sp, T, "host")
+    assert bits_equal(h.solve(dev(b)), hh.solve(dev(b)))
