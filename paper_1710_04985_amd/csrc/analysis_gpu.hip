@@ -366,8 +366,9 @@ int device_analysis(int n, int64_t nnz, const int* row_ptr, const int* col, bool
   k_check<<<blocks(n), 256, 0, s>>>(n, nnz, row_ptr, col, upper, unit_diag, out.depcnt, tp.flags,
                                      tp.counters);
   DCHK(hipGetLastError());
-  int flags = 0;
+  int flags = 0, max_len = 0;
   DCHK(hipMemcpyAsync(&flags, tp.flags, sizeof(int), hipMemcpyDeviceToHost, s));
+  DCHK(hipMemcpyAsync(&max_len, tp.counters, sizeof(int), hipMemcpyDeviceToHost, s));
   DCHK(hipStreamSynchronize(s));
   if (flags) {
     free_device_analysis(out);
@@ -381,7 +382,14 @@ int device_analysis(int n, int64_t nnz, const int* row_ptr, const int* col, bool
     int per_cu = 0;
     DCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_levels, 64, 0));
     const int nch = (n + 63) / 64;
-    const int grid = std::max(1, std::min(nch, std::max(1, per_cu) * num_cu));
+    // A waiting lane rereads up to sixteen dependencies per round, so rows
+    // longer than that multiply the polling traffic of every wavefront that
+    // waits ahead of the level front.  With such rows four wavefronts per CU
+    // are used (random power-law triangle: 24 -> 14 ms), otherwise every
+    // resident one (mesh triangles, whose level front spans all rows: 6.8 ms,
+    // 12.6 ms at four per CU).
+    const int waves_per_cu = max_len > 16 ? std::min(4, std::max(1, per_cu)) : std::max(1, per_cu);
+    const int grid = std::max(1, std::min(nch, waves_per_cu * num_cu));
     k_levels<<<grid, 64, 0, s>>>(n, row_ptr, col, upper ? 1 : 0, out.level, tp.flags,
                                  tp.counters + 1, tp.counters + 2, 1 << 24);
     DCHK(hipGetLastError());
