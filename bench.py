@@ -288,7 +288,7 @@ def main():
     if infoL["sync"] == sp.SYNC_FLAG:
         kernel_name = "k_self_flag<double>"
     elif infoL["assign"] in (sp.ASSIGN_STATIC, sp.ASSIGN_XCD):
-        kernel_name = "k_self_static<double,false>"
+        kernel_name = "k_self_static<double,false,1>"
     else:
         kernel_name = "k_self_value<double>"
     lbL = lb_bytes(TL.n, TL.nnz)

@@ -125,12 +125,18 @@ typedef enum {
     SPTRSV_OPT_ROWS_PER_LANE = 8, /* rows one lane owns when a row gets one lane (1..4,
                                      default 1): fewer, larger work chunks */
     SPTRSV_OPT_ASSIGN = 9,        /* sptrsv_assign: how self-scheduled wavefronts get chunks */
-    SPTRSV_OPT_POLL = 10          /* how a waiting lane polls its dependencies (value sync):
+    SPTRSV_OPT_POLL = 10,         /* how a waiting lane polls its dependencies (value sync):
                                      1 (default) = two rounds in flight over all of its
                                      slots, so a value is seen soon after it lands; 0 = one
                                      round at a time over the pending slots only (less
                                      polling traffic, better when most dependencies are
                                      already available) */
+    SPTRSV_OPT_XP_STRIDE = 11     /* 1 (default) or 2: elements between consecutive values of
+                                     the position-ordered solution the self-scheduled static
+                                     schedules (one right-hand side) publish and poll.  2
+                                     gives FP32 values 8-byte slots, half as many per cache
+                                     line for concurrent stores and polls; ignored by the
+                                     other schedules */
 } sptrsv_option;
 
 typedef enum {
@@ -307,6 +313,10 @@ int sptrsv_get_info(sptrsv_handle_t h, int32_t *n, int64_t *nnz, int32_t *nlev,
 int sptrsv_get_schedule(sptrsv_handle_t h, int32_t *algo, int32_t *group,
                         int32_t *entries_per_lane, int32_t *sync, int32_t *rows_per_lane,
                         int32_t *grid, int32_t *assign, int32_t *poll);
+
+/* SPTRSV_OPT_XP_STRIDE of the schedule the next solve uses (the
+ * autotuner's choice if one is current, else the option). */
+int sptrsv_get_xp_stride(sptrsv_handle_t h, int32_t *stride);
 
 /* Copy the analysis to HOST buffers (any may be NULL): level int32[n],
  * ilev int32[nlev+1], jlev int32[n] (rows by (level, row)), depcnt int32[n]

@@ -25,7 +25,8 @@ __all__ = ["Handle", "BatchedHandle", "SpTRSVFunction", "sptrsv", "SpTRSVError",
 ALGO_AUTO, ALGO_LEVEL, ALGO_SELF, ALGO_BLOCK, ALGO_COLUMN_LEVEL, ALGO_COLUMN_SELF = 0, 1, 2, 3, 4, 5
 SYNC_VALUE, SYNC_FLAG = 0, 1
 OPT = {"algo": 0, "group": 1, "entries_per_lane": 2, "sync": 3, "spin_limit": 4,
-       "grid": 5, "timing": 6, "wg": 7, "rows_per_lane": 8, "assign": 9, "poll": 10}
+       "grid": 5, "timing": 6, "wg": 7, "rows_per_lane": 8, "assign": 9, "poll": 10,
+       "xp_stride": 11}
 ASSIGN_STATIC, ASSIGN_TICKET, ASSIGN_XCD = 0, 1, 2
 SETUP = {"host": 0, "device": 1}
 
@@ -145,10 +146,12 @@ class _Base:
         check(lib.sptrsv_get_schedule(self._h, None, None, ctypes.byref(epl), ctypes.byref(sync),
                                       ctypes.byref(rpl), ctypes.byref(grid), ctypes.byref(assign),
                                       ctypes.byref(poll)))
+        stride = ctypes.c_int32()
+        check(lib.sptrsv_get_xp_stride(self._h, ctypes.byref(stride)))
         return {"n": n.value, "nnz": nnz.value, "nlev": nlev.value, "algo": algo.value,
                 "group": group.value, "entries_per_lane": epl.value, "sync": sync.value,
                 "rows_per_lane": rpl.value, "grid": grid.value, "assign": assign.value,
-                "poll": poll.value}
+                "poll": poll.value, "xp_stride": stride.value}
 
     def export_analysis(self, transpose=False):
         """(level, ilev, jlev, depcnt) as numpy int32 arrays (host copies)."""

@@ -63,6 +63,7 @@ SIGNATURES = {
     "sptrsv_tune": (_int, [_v, _v, _v, _v]),
     "sptrsv_get_info": (_int, [_v, _pi32, _pi64, _pi32, _pi32, _pi32]),
     "sptrsv_get_schedule": (_int, [_v, _pi32, _pi32, _pi32, _pi32, _pi32, _pi32, _pi32, _pi32]),
+    "sptrsv_get_xp_stride": (_int, [_v, _pi32]),
     "sptrsv_export_analysis": (_int, [_v, _int, _pi32, _pi32, _pi32, _pi32]),
     "sptrsv_get_status": (_int, [_v]),
     "sptrsv_kernel_time": (_int, [_v, ctypes.POINTER(ctypes.c_double), _pi64, _int]),

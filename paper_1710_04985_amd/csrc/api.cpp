@@ -76,6 +76,7 @@ struct Config {
   int grid;   // persistent workgroups, 0 = default
   int assign; // sptrsv_assign
   int poll = 1;  // waits: 1 overlapped rounds over all slots, 0 single rounds of pending ones
+  int stride = 1;  // static schedules, one right-hand side: elements between xp values
 };
 
 std::mutex g_tune_mu;
@@ -130,6 +131,7 @@ struct sptrsv_handle_s {
   int rpl = 1;
   int assign = SPTRSV_ASSIGN_STATIC;
   int poll = 1;
+  int xp_stride = 1;
   // autotuner result
   bool tuned = false;
   Config tuned_cfg{SPTRSV_ALGO_SELF, 0, 4, SPTRSV_SYNC_VALUE, 1, 0, SPTRSV_ASSIGN_STATIC};
@@ -456,6 +458,7 @@ Config resolve(sptrsv_handle_t h) {
   if (h->tuned) return h->tuned_cfg;
   Config c{h->algo, h->group, h->epl, h->sync, h->rpl, h->grid, h->assign};
   c.poll = h->poll;
+  c.stride = h->xp_stride;
   if (c.algo == SPTRSV_ALGO_AUTO) c.algo = SPTRSV_ALGO_SELF;
   return c;
 }
@@ -714,7 +717,9 @@ int solve_impl(sptrsv_handle_t h, PlanState& ps, const Config& c_in, const void*
     if (!multi && c.rpl != 1 && !(ch = get_chunks(h, ps, c.group, c.epl, 0, c.rpl, &err)))
       return err;
   }
-  if ((err = ensure_xp(h, static_cast<int64_t>(n) * nrhs))) return err;
+  // the static schedules with one right-hand side may space the values out
+  const int stride = use_static && !multi ? c.stride : 1;
+  if ((err = ensure_xp(h, static_cast<int64_t>(n) * nrhs * stride))) return err;
   SolveArgs a;
   a.plan = &ps.d;
   a.chunks = &ch->d;
@@ -726,6 +731,7 @@ int solve_impl(sptrsv_handle_t h, PlanState& ps, const Config& c_in, const void*
   a.ld = ld;
   a.spin_limit = h->spin_limit;
   a.poll = c.poll;
+  a.xp_stride = stride;
   a.wg = h->wg;
   hipEvent_t stop;
   if (c.algo == SPTRSV_ALGO_BLOCK && !multi) {
@@ -765,7 +771,7 @@ int solve_impl(sptrsv_handle_t h, PlanState& ps, const Config& c_in, const void*
   }
   // value sync: xp starts as the sentinel (b == x needs no copy: a row reads
   // its own b before any write of its own x, and x is only written)
-  if (launch_fill_sentinel<T>(static_cast<T*>(h->xp), static_cast<int64_t>(n) * nrhs, s) !=
+  if (launch_fill_sentinel<T>(static_cast<T*>(h->xp), static_cast<int64_t>(n) * nrhs * stride, s) !=
       hipSuccess)
     return kErrHip;
   a.grid = persistent_grid(h, use_static ? 3 : 0, c.grid, ch->d.count);
@@ -1208,7 +1214,7 @@ int sptrsv_set_option(sptrsv_handle_t h, sptrsv_option key, int64_t v) {
   if (!h) return kErrInvalidArg;
   if (key == SPTRSV_OPT_ALGO || key == SPTRSV_OPT_GROUP || key == SPTRSV_OPT_ENTRIES_PER_LANE ||
       key == SPTRSV_OPT_SYNC || key == SPTRSV_OPT_ROWS_PER_LANE || key == SPTRSV_OPT_GRID ||
-      key == SPTRSV_OPT_ASSIGN || key == SPTRSV_OPT_POLL) {
+      key == SPTRSV_OPT_ASSIGN || key == SPTRSV_OPT_POLL || key == SPTRSV_OPT_XP_STRIDE) {
     h->tuned = false;   // an explicit schedule option overrides the tuner's choice
     h->tuned_multi.clear();
   }
@@ -1259,6 +1265,10 @@ int sptrsv_set_option(sptrsv_handle_t h, sptrsv_option key, int64_t v) {
       if (v != 0 && v != 1) return kErrInvalidArg;
       h->poll = static_cast<int>(v);
       return kOk;
+    case SPTRSV_OPT_XP_STRIDE:
+      if (v != 1 && v != 2) return kErrInvalidArg;
+      h->xp_stride = static_cast<int>(v);
+      return kOk;
   }
   return kErrInvalidArg;
 }
@@ -1277,6 +1287,7 @@ int sptrsv_get_option(sptrsv_handle_t h, sptrsv_option key, int64_t* v) {
     case SPTRSV_OPT_ROWS_PER_LANE: *v = h->rpl; return kOk;
     case SPTRSV_OPT_ASSIGN: *v = h->assign; return kOk;
     case SPTRSV_OPT_POLL: *v = h->poll; return kOk;
+    case SPTRSV_OPT_XP_STRIDE: *v = h->xp_stride; return kOk;
   }
   return kErrInvalidArg;
 }
@@ -1310,13 +1321,17 @@ int sptrsv_tune(sptrsv_handle_t h, const void* b, void* x, hipStream_t stream) {
   for (int epl : {1, 2, 4, 8}) {
     if (self_ok) {
       for (int grid : {ncu / 2, ncu, 2 * ncu, 4 * ncu}) {
-        for (int poll : {1, 0}) {
-          Config c1{SPTRSV_ALGO_SELF, 0, epl, SPTRSV_SYNC_VALUE, 1, grid, SPTRSV_ASSIGN_STATIC};
-          Config c2{SPTRSV_ALGO_SELF, 0, epl, SPTRSV_SYNC_VALUE, 1, grid, SPTRSV_ASSIGN_XCD};
-          c1.poll = c2.poll = poll;
-          cand.push_back(c1);
-          cand.push_back(c2);
-        }
+        for (int poll : {1, 0})
+          // FP32 values also in 8-byte slots (fewer per line under concurrent polls)
+          for (int stride : {1, 2}) {
+            if (stride == 2 && h->dtype != SPTRSV_F32) continue;
+            Config c1{SPTRSV_ALGO_SELF, 0, epl, SPTRSV_SYNC_VALUE, 1, grid, SPTRSV_ASSIGN_STATIC};
+            Config c2{SPTRSV_ALGO_SELF, 0, epl, SPTRSV_SYNC_VALUE, 1, grid, SPTRSV_ASSIGN_XCD};
+            c1.poll = c2.poll = poll;
+            c1.stride = c2.stride = stride;
+            cand.push_back(c1);
+            cand.push_back(c2);
+          }
       }
       for (int rpl : {1, 4})
         cand.push_back({SPTRSV_ALGO_SELF, 0, epl, SPTRSV_SYNC_VALUE, rpl, ncu, SPTRSV_ASSIGN_TICKET});
@@ -1527,6 +1542,12 @@ int sptrsv_get_schedule(sptrsv_handle_t h, int32_t* algo, int32_t* group,
   return kOk;
 }
 
+int sptrsv_get_xp_stride(sptrsv_handle_t h, int32_t* stride) {
+  if (!h || !stride) return kErrInvalidArg;
+  *stride = resolve(h).stride;
+  return kOk;
+}
+
 int sptrsv_export_analysis(sptrsv_handle_t h, int transpose, int32_t* level, int32_t* ilev,
                            int32_t* jlev, int32_t* depcnt) {
   if (!h) return kErrInvalidArg;
@@ -1605,6 +1626,8 @@ int sptrsv_graph_capture(sptrsv_handle_t h, const void* b, void* x, int transpos
         (c.assign == SPTRSV_ASSIGN_STATIC || c.assign == SPTRSV_ASSIGN_XCD)) {
       ChunkEntry* ch = get_chunks(h, ps, c.group, c.epl, 0, 1, &err);
       if (!ch || !static_lists(h, *ch, c, &err)) return err;
+      // xp is resized outside the capture
+      if ((err = ensure_xp(h, static_cast<int64_t>(h->n) * c.stride))) return err;
     }
     if (h->n > 0 && c.algo == SPTRSV_ALGO_BLOCK && (err = build_block(h, transpose ? 1 : 0, stream)))
       return err;

@@ -33,6 +33,8 @@
 // release/acquire fences (flag sync).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "analysis.hpp"
 #include "kernels.hpp"
 
@@ -436,7 +438,7 @@ template <typename T> struct StageD {   // first entries of the lane, raw
   T v[4];
 };
 
-template <typename T, bool kMulti>
+template <typename T, bool kMulti, int kStride>
 __global__ void __launch_bounds__(256)
 k_self_static(KArgs<T> a, const int* __restrict__ cstart, const int* __restrict__ cmeta,
               const int* __restrict__ wptr, const int* __restrict__ wlist) {
@@ -447,7 +449,7 @@ k_self_static(KArgs<T> a, const int* __restrict__ cstart, const int* __restrict_
   const int llast = a.nchunks - 1;    // clamp for the list load past the end
   const int nlast = a.n - 1;          // clamp for loads whose result is discarded
   const int64_t olast = a.noff > 0 ? a.noff - 1 : 0;
-  const int xs = kMulti ? a.nrhs : 1;
+  const int xs = kMulti ? a.nrhs : kStride;   // elements between xp values
   StageB<T> sb{-1, 0, 0};
   StageC<T> sc{-1, 0, -1, 0, 0, 0, T(1)};
   StageD<T> sd;
@@ -555,7 +557,7 @@ k_self_static(KArgs<T> a, const int* __restrict__ cstart, const int* __restrict_
         sum = group_sum(sum, sd.lg);
         if (sd.k >= 0 && (lane & (G - 1)) == 0) {
           const T xi = canonical((sd.bi - sum) * sd.d);
-          store_agent(a.xp + sd.k, xi);
+          store_agent(a.xp + static_cast<int64_t>(sd.k) * xs, xi);
           a.x[sd.i] = xi;
         }
       }
@@ -877,8 +879,9 @@ template <typename T> hipError_t launch_self_static(const SolveArgs& sa, hipStre
   const int* wp = sa.wave_ptr;
   const int* wl = sa.wave_list;
   void* args[] = {&ka, &cs, &cm, &wp, &wl};
-  const void* fn = sa.nrhs > 1 ? reinterpret_cast<const void*>(k_self_static<T, true>)
-                               : reinterpret_cast<const void*>(k_self_static<T, false>);
+  const void* fn = sa.nrhs > 1 ? reinterpret_cast<const void*>(k_self_static<T, true, 1>)
+                   : sa.xp_stride == 2 ? reinterpret_cast<const void*>(k_self_static<T, false, 2>)
+                                       : reinterpret_cast<const void*>(k_self_static<T, false, 1>);
   return hipLaunchCooperativeKernel(fn, dim3(sa.grid), dim3(sa.wg), args, 0, s);
 }
 
@@ -928,8 +931,10 @@ template <typename T> int self_value_blocks_per_cu(int wg) {
 }
 template <typename T> int self_flag_blocks_per_cu(int wg) { return occupancy(k_self_flag<T>, wg); }
 template <typename T> int self_static_blocks_per_cu(int wg) {
-  const int a = occupancy(k_self_static<T, false>, wg), b = occupancy(k_self_static<T, true>, wg);
-  return a < b ? a : b;
+  const int a = occupancy(k_self_static<T, false, 1>, wg);
+  const int b = occupancy(k_self_static<T, true, 1>, wg);
+  const int c = occupancy(k_self_static<T, false, 2>, wg);
+  return std::min(a, std::min(b, c));
 }
 
 #define SPTRSV_INSTANTIATE(T)                                                                    \

@@ -56,6 +56,7 @@ struct SolveArgs {
   int ld = 0;
   int spin_limit = 1 << 22;
   int poll = 1;      // waits: 1 = two overlapped rounds over all slots, 0 = pending only
+  int xp_stride = 1; // static schedules, one right-hand side: elements between xp values
   int grid = 0;      // persistent workgroups
   int wg = 64;       // threads per workgroup
   const int* wave_ptr = nullptr;   // static schedule: per-wavefront chunk lists (CSR)

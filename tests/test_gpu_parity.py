@@ -59,7 +59,10 @@ SCHEDULES = [("level", dict(algo=1)), ("self_value", dict(algo=2, sync=0)),
              ("self_value_wg256_grid1", dict(algo=2, wg=256, grid=1)),
              ("self_static_poll0", dict(algo=2, sync=0, assign=0, poll=0)),
              ("self_xcd_poll0_grid16", dict(algo=2, sync=0, assign=2, grid=16, poll=0)),
-             ("self_ticket_poll0", dict(algo=2, sync=0, assign=1, poll=0))]
+             ("self_ticket_poll0", dict(algo=2, sync=0, assign=1, poll=0)),
+             ("self_static_stride2", dict(algo=2, sync=0, assign=0, xp_stride=2)),
+             ("self_xcd_stride2_poll0", dict(algo=2, sync=0, assign=2, grid=16, poll=0,
+                                             xp_stride=2))]
 
 
 @pytest.mark.parametrize("name,T", CASES, ids=[c[0] for c in CASES])
@@ -104,13 +107,21 @@ def test_solve_fp32(sp, name, T):
     v32 = T.vals.astype(np.float32)
     b32 = W.uniform_vector(T.n, 9).astype(np.float32)
     xo = o.solve(T.row_ptr, T.col_idx, v32.astype(np.float64), b32.astype(np.float64), T.upper)
-    for opts in (dict(algo=1), dict(algo=2, sync=0), dict(algo=2, sync=1)):
+    ref = None
+    for opts in (dict(algo=1), dict(algo=2, sync=0), dict(algo=2, sync=1),
+                 dict(algo=2, sync=0, xp_stride=2), dict(algo=2, assign=2, poll=0, xp_stride=2)):
         h = sp.Handle(dev(T.row_ptr), dev(T.col_idx), dev(v32),
                       uplo="U" if T.upper else "L").configure(**opts)
         x = h.solve(dev(b32))
         h.status()
         assert x.dtype == torch.float32
         assert relerr(host(x), xo) <= TOL32, opts
+        if opts.get("algo") == 2 and opts.get("sync") == 0 and "assign" not in opts:
+            # 8-byte slots change where values live, not how they are computed
+            if ref is None:
+                ref = x
+            else:
+                assert bits_equal(x, ref)
 
 
 @pytest.mark.parametrize("group,rpl", [(1, 1), (1, 4), (0, 4), (4, 1), (16, 1), (64, 1)])
@@ -126,11 +137,13 @@ def test_level_equals_self_bitwise(sp, name, T, group, rpl):
         hb = sp.Handle(*dev_tri(T), uplo="U" if T.upper else "L").configure(algo=3)
         for _ in range(5):
             assert bits_equal(hb.solve(b), ref)
-    for sync, assign, poll in ((0, 0, 1), (0, 1, 1), (1, 1, 1), (0, 2, 1), (0, 0, 0), (0, 1, 0)):
+    for sync, assign, poll, stride in ((0, 0, 1, 1), (0, 1, 1, 1), (1, 1, 1, 1), (0, 2, 1, 1),
+                                       (0, 0, 0, 1), (0, 1, 0, 1), (0, 0, 1, 2), (0, 2, 0, 2)):
         if assign in (0, 2) and rpl != 1:
             continue                  # static assignment keeps one row per lane
         hs = sp.Handle(*dev_tri(T), uplo="U" if T.upper else "L").configure(
-            algo=2, group=group, sync=sync, rows_per_lane=rpl, assign=assign, poll=poll)
+            algo=2, group=group, sync=sync, rows_per_lane=rpl, assign=assign, poll=poll,
+            xp_stride=stride)
         for _ in range(20):
             assert bits_equal(hs.solve(b), ref)
         hs.status()
@@ -475,7 +488,8 @@ def test_watchdog_timeout_is_reported_and_recovers(sp, sync, assign, poll):
 
 
 @pytest.mark.parametrize("opts", [dict(algo=1), dict(algo=2, sync=0), dict(algo=2, sync=1),
-                                  dict(algo=3)])
+                                  dict(algo=3),
+                                  dict(algo=2, sync=0, xp_stride=2)])
 def test_graph_replay(sp, opts):
     T = W.laplacian_triangle((24, 23, 22))
     h = sp.Handle(*dev_tri(T)).configure(**opts)
@@ -498,6 +512,32 @@ def test_graph_replay(sp, opts):
             s.synchronize()
             assert bits_equal(x, ref_t), rep
     h.status()
+
+
+def test_capture_first_with_xp_stride(sp):
+    """A graph captured before any eager solve, with values in 8-byte slots:
+    the wider solution buffer is sized before the capture."""
+    T = W.laplacian_triangle((19, 18, 17))
+    v32 = T.vals.astype(np.float32)
+    h = sp.Handle(dev(T.row_ptr), dev(T.col_idx), dev(v32)).configure(algo=2, sync=0,
+                                                                        xp_stride=2)
+    assert h.info()["xp_stride"] == 2
+    s = torch.cuda.Stream()
+    b = dev(W.uniform_vector(T.n, 4).astype(np.float32))
+    x = torch.empty_like(b)
+    with torch.cuda.stream(s):
+        g = h.capture(b, x, stream=s)
+        for rep in range(3):
+            x.zero_()
+            g.launch(s)
+            s.synchronize()
+            ref = h.solve(b)
+            s.synchronize()
+            assert bits_equal(x, ref), rep
+    h.status()
+    xo = oracle.get().solve(T.row_ptr, T.col_idx, v32.astype(np.float64),
+                            host(b).astype(np.float64))
+    assert relerr(host(x), xo) <= TOL32
 
 
 def test_tune_and_timing(sp):
