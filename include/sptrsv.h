@@ -134,9 +134,10 @@ typedef enum {
     SPTRSV_OPT_XP_STRIDE = 11     /* 1 (default) or 2: elements between consecutive values of
                                      the position-ordered solution the self-scheduled static
                                      schedules (one right-hand side) publish and poll.  2
-                                     gives FP32 values 8-byte slots, half as many per cache
-                                     line for concurrent stores and polls; ignored by the
-                                     other schedules */
+                                     gives each value a slot twice its size, half as many
+                                     values per cache line for concurrent stores and polls
+                                     (faster where dependencies are scattered, slower where
+                                     polls coalesce); ignored by the other schedules */
 } sptrsv_option;
 
 typedef enum {

@@ -1322,9 +1322,9 @@ int sptrsv_tune(sptrsv_handle_t h, const void* b, void* x, hipStream_t stream) {
     if (self_ok) {
       for (int grid : {ncu / 2, ncu, 2 * ncu, 4 * ncu}) {
         for (int poll : {1, 0})
-          // FP32 values also in 8-byte slots (fewer per line under concurrent polls)
+          // values also in slots twice their size (fewer per cache line under
+          // concurrent stores and polls)
           for (int stride : {1, 2}) {
-            if (stride == 2 && h->dtype != SPTRSV_F32) continue;
             Config c1{SPTRSV_ALGO_SELF, 0, epl, SPTRSV_SYNC_VALUE, 1, grid, SPTRSV_ASSIGN_STATIC};
             Config c2{SPTRSV_ALGO_SELF, 0, epl, SPTRSV_SYNC_VALUE, 1, grid, SPTRSV_ASSIGN_XCD};
             c1.poll = c2.poll = poll;
