@@ -131,13 +131,14 @@ typedef enum {
                                      round at a time over the pending slots only (less
                                      polling traffic, better when most dependencies are
                                      already available) */
-    SPTRSV_OPT_XP_STRIDE = 11     /* 1 (default) or 2: elements between consecutive values of
-                                     the position-ordered solution the self-scheduled static
-                                     schedules (one right-hand side) publish and poll.  2
-                                     gives each value a slot twice its size, half as many
-                                     values per cache line for concurrent stores and polls
-                                     (faster where dependencies are scattered, slower where
-                                     polls coalesce); ignored by the other schedules */
+    SPTRSV_OPT_XP_STRIDE = 11     /* 1 (default), 2, 4, 8 or 16: elements between consecutive
+                                     values of the position-ordered solution the
+                                     self-scheduled static schedules (one right-hand side)
+                                     publish and poll.  Wider slots put fewer values on a
+                                     cache line under concurrent stores and polls: faster
+                                     where dependencies are scattered, slower where polls
+                                     coalesce.  The autotuner tries packed values and 32- and
+                                     64-byte slots.  Ignored by the other schedules */
 } sptrsv_option;
 
 typedef enum {

@@ -1266,7 +1266,7 @@ int sptrsv_set_option(sptrsv_handle_t h, sptrsv_option key, int64_t v) {
       h->poll = static_cast<int>(v);
       return kOk;
     case SPTRSV_OPT_XP_STRIDE:
-      if (v != 1 && v != 2) return kErrInvalidArg;
+      if (v != 1 && v != 2 && v != 4 && v != 8 && v != 16) return kErrInvalidArg;
       h->xp_stride = static_cast<int>(v);
       return kOk;
   }
@@ -1322,9 +1322,10 @@ int sptrsv_tune(sptrsv_handle_t h, const void* b, void* x, hipStream_t stream) {
     if (self_ok) {
       for (int grid : {ncu / 2, ncu, 2 * ncu, 4 * ncu}) {
         for (int poll : {1, 0})
-          // values also in slots twice their size (fewer per cache line under
-          // concurrent stores and polls)
-          for (int stride : {1, 2}) {
+          // values packed, or one per 32- or 64-byte slot (fewer per cache line
+          // under concurrent stores and polls)
+          for (int slot : {0, 32, 64}) {
+            const int stride = slot == 0 ? 1 : slot / static_cast<int>(h->vb);
             Config c1{SPTRSV_ALGO_SELF, 0, epl, SPTRSV_SYNC_VALUE, 1, grid, SPTRSV_ASSIGN_STATIC};
             Config c2{SPTRSV_ALGO_SELF, 0, epl, SPTRSV_SYNC_VALUE, 1, grid, SPTRSV_ASSIGN_XCD};
             c1.poll = c2.poll = poll;

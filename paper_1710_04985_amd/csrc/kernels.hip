@@ -880,6 +880,9 @@ template <typename T> hipError_t launch_self_static(const SolveArgs& sa, hipStre
   const int* wl = sa.wave_list;
   void* args[] = {&ka, &cs, &cm, &wp, &wl};
   const void* fn = sa.nrhs > 1 ? reinterpret_cast<const void*>(k_self_static<T, true, 1>)
+                   : sa.xp_stride == 16 ? reinterpret_cast<const void*>(k_self_static<T, false, 16>)
+                   : sa.xp_stride == 8 ? reinterpret_cast<const void*>(k_self_static<T, false, 8>)
+                   : sa.xp_stride == 4 ? reinterpret_cast<const void*>(k_self_static<T, false, 4>)
                    : sa.xp_stride == 2 ? reinterpret_cast<const void*>(k_self_static<T, false, 2>)
                                        : reinterpret_cast<const void*>(k_self_static<T, false, 1>);
   return hipLaunchCooperativeKernel(fn, dim3(sa.grid), dim3(sa.wg), args, 0, s);
@@ -934,7 +937,10 @@ template <typename T> int self_static_blocks_per_cu(int wg) {
   const int a = occupancy(k_self_static<T, false, 1>, wg);
   const int b = occupancy(k_self_static<T, true, 1>, wg);
   const int c = occupancy(k_self_static<T, false, 2>, wg);
-  return std::min(a, std::min(b, c));
+  const int d = occupancy(k_self_static<T, false, 4>, wg);
+  const int e = occupancy(k_self_static<T, false, 8>, wg);
+  const int f = occupancy(k_self_static<T, false, 16>, wg);
+  return std::min(std::min(std::min(a, b), std::min(c, d)), std::min(e, f));
 }
 
 #define SPTRSV_INSTANTIATE(T)                                                                    \

@@ -62,7 +62,9 @@ SCHEDULES = [("level", dict(algo=1)), ("self_value", dict(algo=2, sync=0)),
              ("self_ticket_poll0", dict(algo=2, sync=0, assign=1, poll=0)),
              ("self_static_stride2", dict(algo=2, sync=0, assign=0, xp_stride=2)),
              ("self_xcd_stride2_poll0", dict(algo=2, sync=0, assign=2, grid=16, poll=0,
-                                             xp_stride=2))]
+                                             xp_stride=2)),
+             ("self_static_stride8", dict(algo=2, sync=0, assign=0, xp_stride=8)),
+             ("self_xcd_stride16", dict(algo=2, sync=0, assign=2, grid=16, xp_stride=16))]
 
 
 @pytest.mark.parametrize("name,T", CASES, ids=[c[0] for c in CASES])
@@ -109,7 +111,8 @@ def test_solve_fp32(sp, name, T):
     xo = o.solve(T.row_ptr, T.col_idx, v32.astype(np.float64), b32.astype(np.float64), T.upper)
     ref = None
     for opts in (dict(algo=1), dict(algo=2, sync=0), dict(algo=2, sync=1),
-                 dict(algo=2, sync=0, xp_stride=2), dict(algo=2, assign=2, poll=0, xp_stride=2)):
+                 dict(algo=2, sync=0, xp_stride=2), dict(algo=2, assign=2, poll=0, xp_stride=2),
+                 dict(algo=2, sync=0, xp_stride=16)):
         h = sp.Handle(dev(T.row_ptr), dev(T.col_idx), dev(v32),
                       uplo="U" if T.upper else "L").configure(**opts)
         x = h.solve(dev(b32))
@@ -138,7 +141,8 @@ def test_level_equals_self_bitwise(sp, name, T, group, rpl):
         for _ in range(5):
             assert bits_equal(hb.solve(b), ref)
     for sync, assign, poll, stride in ((0, 0, 1, 1), (0, 1, 1, 1), (1, 1, 1, 1), (0, 2, 1, 1),
-                                       (0, 0, 0, 1), (0, 1, 0, 1), (0, 0, 1, 2), (0, 2, 0, 2)):
+                                       (0, 0, 0, 1), (0, 1, 0, 1), (0, 0, 1, 2), (0, 2, 0, 2),
+                                       (0, 0, 1, 4), (0, 2, 1, 8), (0, 0, 0, 16)):
         if assign in (0, 2) and rpl != 1:
             continue                  # static assignment keeps one row per lane
         hs = sp.Handle(*dev_tri(T), uplo="U" if T.upper else "L").configure(
@@ -444,6 +448,9 @@ def test_binding_rejects_short_buffers(sp):
             h.grad_vals(b, bad)
     with pytest.raises(ValueError):
         h.update_values(dev(T.vals[:-2]))
+    for bad_stride in (0, 3, 32):
+        with pytest.raises(sp.SpTRSVError):
+            h.set_option("xp_stride", bad_stride)
     with pytest.raises(ValueError):
         h.grad_vals(b, b, out=torch.empty(T.nnz - 1, dtype=torch.float64, device=DEV))
     bh = sp.BatchedHandle([dev(T.row_ptr)] * 2, [dev(T.col_idx)] * 2, [dev(T.vals)] * 2)
