@@ -567,3 +567,41 @@ def test_probe_hop(sp):
     for same in (True, False):
         ns = sp.probe_hop(same_xcd=same, iters=200)
         assert 10.0 < ns < 1e5, (same, ns)
+
+
+def test_mixed_solve_sequence(sp):
+    """A mixed sequence on one handle (slot widths of the position-ordered
+    solution, several right-hand sides, level scheduling, tickets,
+    transposes) gives every solve bit for bit what a fresh handle gives: no
+    state left by one solve leaks into the next."""
+    T = W.laplacian_triangle((21, 17, 13))
+    b = dev(W.uniform_vector(T.n, 12))
+    F = dev(np.stack([W.uniform_vector(T.n, 20 + r) for r in range(3)]))
+
+    def fresh(**opts):
+        return sp.Handle(*dev_tri(T)).configure(**opts)
+
+    want = {}
+    for key, opts in (("s1", dict(algo=2, sync=0, assign=0)),
+                      ("s4", dict(algo=2, sync=0, assign=2, xp_stride=4)),
+                      ("lv", dict(algo=1)),
+                      ("tk", dict(algo=2, sync=0, assign=1))):
+        want[key] = fresh(**opts).solve(b)
+        want[key + "t"] = fresh(**opts).solve_t(b)
+    want["multi"] = fresh(algo=2, sync=0, assign=0).solve_multi(F)
+    h = sp.Handle(*dev_tri(T))
+    seq = ["s1", "s1", "s4", "lv", "s1", "multi", "s4", "tk", "s1t", "s4t", "multi", "lvt",
+           "s1", "tkt", "s4"]
+    opts_of = {"s1": dict(algo=2, sync=0, assign=0, xp_stride=1),
+               "s4": dict(algo=2, sync=0, assign=2, xp_stride=4),
+               "lv": dict(algo=1), "tk": dict(algo=2, sync=0, assign=1, xp_stride=1)}
+    for it, key in enumerate(seq):
+        if key == "multi":
+            h.configure(algo=2, sync=0, assign=0, xp_stride=1)
+            assert bits_equal(h.solve_multi(F), want["multi"]), it
+            continue
+        base = key.rstrip("t")
+        h.configure(**opts_of[base])
+        got = h.solve_t(b) if key.endswith("t") else h.solve(b)
+        assert bits_equal(got, want[key]), (it, key)
+    h.status()
