@@ -61,9 +61,11 @@ def parse():
     return ap.parse_args()
 
 
-def committed_traffic(kernel):
+def committed_traffic(kernel, schedule):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, or None if it covers another kernel or kernels.hip changed since."""
+    summary, or None unless that summary covers this kernel under this
+    schedule (lanes rule, grid, assignment, polling, slot width) with the
+    current kernels.hip."""
     import hashlib
     root = os.path.dirname(os.path.abspath(__file__))
     path = os.path.join(root, "profiles", "k_self_static_lap3d128_hbm_counters.md")
@@ -79,7 +81,12 @@ def committed_traffic(kernel):
         return None
     if not rec or rec.get("kernels_hip_sha256_16") != h or rec.get("kernel") != kernel:
         return None
+    if rec.get("schedule") != schedule:
+        return None
     return rec["bytes_per_launch"]
+
+
+SCHED_KEYS = ("entries_per_lane", "grid", "assign", "poll", "xp_stride")
 
 
 def cpu_info():
@@ -285,12 +292,13 @@ def main():
     kernel_ms = (kmsL + kmsU) / max(1, kcL + kcU)
 
     infoL = hL.info()
+    schedule = {k: infoL[k] for k in SCHED_KEYS}
     if infoL["sync"] == sp.SYNC_FLAG:
         kernel_name = "k_self_flag<double>"
     elif infoL["assign"] in (sp.ASSIGN_STATIC, sp.ASSIGN_XCD):
-        kernel_name = "k_self_static<double,false,1>"
+        kernel_name = "k_self_static<double,false,%d>" % infoL["xp_stride"]
     else:
-        kernel_name = "k_self_value<double>"
+        kernel_name = "k_self_value<double,false>"
     lbL = lb_bytes(TL.n, TL.nnz)
     lbU = lb_bytes(TU.n, TU.nnz)
     step_bytes = lbL + lbU
@@ -327,8 +335,8 @@ def main():
         "bytes_per_step": step_bytes,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-                     "traffic": committed_traffic(kernel_name),
-                     "kernel": kernel_name,
+                     "traffic": committed_traffic(kernel_name, schedule),
+                     "kernel": kernel_name, "schedule": schedule,
                      "kernel_ms": round(kernel_ms, 5), "bytes_per_launch": lbL,
                      "copy_gbs": round(copy_gbs, 1),
                      "frac_of_copy": round(achieved / copy_gbs, 5)},
@@ -367,6 +375,10 @@ def main():
     if args.table2:
         import bench_suite
         bench_suite.table2(sp, torch, out_path=os.path.join(out_dir, "bench_table2.jsonl"))
+    # release every handle while the runtime is fully up (not at interpreter exit)
+    for h in (hL, hU, lvL, lvU):
+        h.close()
+    torch.cuda.synchronize()
     print(json.dumps(out), flush=True)
 
 

@@ -74,7 +74,9 @@ typedef enum {
     SPTRSV_ERR_HIP = -8,            /* a HIP runtime call failed */
     SPTRSV_ERR_OOM = -9,            /* device or host allocation failed */
     SPTRSV_ERR_TIMEOUT = -10,       /* self-scheduled wait exceeded its spin limit */
-    SPTRSV_ERR_NOT_SUPPORTED = -11  /* valid request the library does not implement */
+    SPTRSV_ERR_NOT_SUPPORTED = -11, /* valid request the library does not implement */
+    SPTRSV_ERR_BUSY = -12           /* sptrsv_destroy: graphs captured from the handle are
+                                       still alive (destroy them first) */
 } sptrsv_status;
 
 typedef enum { SPTRSV_F64 = 0, SPTRSV_F32 = 1 } sptrsv_dtype;
@@ -341,12 +343,19 @@ int sptrsv_kernel_time(sptrsv_handle_t h, double *ms, int64_t *count, int reset)
 
 const char *sptrsv_status_string(int status);
 
+/* Frees the handle and everything it owns, after the work it issued has
+ * finished.  Returns SPTRSV_ERR_BUSY, and frees nothing, while graphs
+ * captured from the handle are alive: their kernels use its buffers. */
 int sptrsv_destroy(sptrsv_handle_t h);
 
 /* ---------------------------------------------------------------------- */
 /* HIP graph of one solve (or transposed solve) on fixed b/x pointers:
  * captured once on `stream`, replayed by sptrsv_graph_launch.  The handle's
- * options are frozen into the graph. */
+ * options are frozen into the graph.  The graph uses the handle's buffers:
+ * the handle cannot be destroyed while it lives (SPTRSV_ERR_BUSY), and a
+ * position-ordered solution buffer that later calls replace (several
+ * right-hand sides, wider slots) stays allocated until the graph is
+ * destroyed.  b and x must stay allocated while the graph may be launched. */
 int sptrsv_graph_capture(sptrsv_handle_t h, const void *b, void *x, int transpose,
                          hipStream_t stream, sptrsv_graph_t *out);
 int sptrsv_graph_launch(sptrsv_graph_t g, hipStream_t stream);

@@ -12,6 +12,8 @@ from __future__ import annotations
 
 import ctypes
 import os
+import sys
+import weakref
 
 import numpy as np
 import torch
@@ -61,8 +63,10 @@ def _need_vec(t, name, dtype, numel):
 
 class _Base:
     _h = None
+    _graphs = None
     n = 0
     dtype = torch.float64
+    _value_gen = 0      # bumped by every update_values (the adjoint checks it)
 
     def _solve(self, fn, b, out, stream):
         _need_vec(b, "b", self.dtype, self.n)
@@ -183,14 +187,25 @@ class _Base:
         g = ctypes.c_void_p()
         check(lib.sptrsv_graph_capture(self._h, _ptr(b), _ptr(x), int(transpose),
                                        ctypes.c_void_p(s.cuda_stream), ctypes.byref(g)))
-        return Graph(g)
+        graph = Graph(g, self, b, x)
+        if self._graphs is None:
+            self._graphs = weakref.WeakSet()
+        self._graphs.add(graph)
+        return graph
 
     def close(self):
+        """Destroys the handle (and first every graph captured from it)."""
         if self._h:
-            lib.sptrsv_destroy(self._h)
+            for g in list(self._graphs or ()):
+                g.close()
+            check(lib.sptrsv_destroy(self._h))
             self._h = None
 
     def __del__(self):
+        # no HIP calls while the interpreter shuts down (the runtime, or a
+        # profiler wrapped around it, may already be tearing down)
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -198,18 +213,27 @@ class _Base:
 
 
 class Graph:
-    def __init__(self, g):
+    """A captured solve.  Holds its handle and its b/x tensors, so neither
+    can be freed (or their memory reused) while the graph can be launched."""
+
+    def __init__(self, g, owner, b, x):
         self._g = g
+        self._keep = (owner, b, x)
 
     def launch(self, stream=None):
+        if not self._g:
+            raise RuntimeError("graph is closed")
         check(lib.sptrsv_graph_launch(self._g, _stream(stream)))
 
     def close(self):
         if self._g:
             lib.sptrsv_graph_destroy(self._g)
             self._g = None
+            self._keep = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -267,6 +291,7 @@ class Handle(_Base):
         _need_vec(vals, "vals", self.dtype, self.nnz)
         check(lib.sptrsv_update_values(self._h, _ptr(vals), _stream(stream)))
         self.vals = vals
+        self._value_gen += 1
 
     def grad_vals(self, grad_b, x, out=None, stream=None):
         """-grad_b[i] * x[j] for each stored entry (i, j), in CSR entry order."""
@@ -321,6 +346,7 @@ class BatchedHandle(_Base):
         check(lib.sptrsv_update_values_batched(self._h, ctypes.cast(ptrs, ctypes.c_void_p),
                                                _stream(stream)))
         self._keep = (self._keep[0], self._keep[1], list(valss))
+        self._value_gen += 1
 
     def grad_vals(self, grad_b, x, out=None, stream=None):
         _need_vec(grad_b, "grad_b", self.dtype, self.n)
@@ -340,7 +366,11 @@ class SpTRSVFunction(torch.autograd.Function):
     tensor identity or version counters cannot tell (in-place writes through
     .data do not bump the version).
     Backward (the adjoint): grad_b = T^{-T} grad_x by the transposed solve,
-    grad_vals[k] = -grad_b[i] * x[j] for each stored entry k = (i, j)."""
+    grad_vals[k] = -grad_b[i] * x[j] for each stored entry k = (i, j).  If
+    the handle was given other values between this forward and its backward
+    (another forward on the same handle), backward gathers this forward's
+    values again first, so the transposed solve uses the matrix that
+    produced x."""
 
     @staticmethod
     def forward(ctx, vals, b, handle, values_current=False):
@@ -348,13 +378,16 @@ class SpTRSVFunction(torch.autograd.Function):
             handle.update_values(vals.detach().contiguous())
         x = handle.solve(b.contiguous())
         ctx.handle = handle
-        ctx.save_for_backward(x)
+        ctx.value_gen = handle._value_gen
+        ctx.save_for_backward(x, vals)
         return x
 
     @staticmethod
     def backward(ctx, gx):
-        (x,) = ctx.saved_tensors
+        x, vals = ctx.saved_tensors
         h = ctx.handle
+        if h._value_gen != ctx.value_gen:
+            h.update_values(vals.detach().contiguous())
         gb = h.solve_t(gx.contiguous())
         gv = h.grad_vals(gb, x) if ctx.needs_input_grad[0] else None
         return gv, (gb if ctx.needs_input_grad[1] else None), None, None

@@ -22,6 +22,8 @@ enum : int {
   kErrOom = -9,
   kErrTimeout = -10,
   kErrNotSupported = -11,
+  kErrBusy = -12,
+  kErrTooLarge = -13,
 };
 
 // Checks the problem statement of Sec. 3, eq. (1) on the pattern: row_ptr

@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <tuple>
 #include <utility>
@@ -17,6 +18,7 @@
 
 #include "analysis.hpp"
 #include "analysis_gpu.hpp"
+#include "api_internal.hpp"
 #include "column.hpp"
 #include "probe.hpp"
 #include "kernels.hpp"
@@ -82,6 +84,29 @@ struct Config {
 std::mutex g_tune_mu;
 std::map<uint64_t, Config> g_tune_cache;
 
+// Where a solve keeps its position-ordered solution.  By default in the
+// handle's own buffer (grown on demand); sptrsv_solve_noalloc passes a
+// caller-side buffer of fixed capacity instead and forbids every allocation
+// (work tables not built yet -> SPTRSV_ERR_NOT_SUPPORTED).
+struct SolveExt {
+  void* xp = nullptr;          // external buffer, or null for the handle's own
+  int64_t xp_bytes = 0;        // its capacity
+  bool no_alloc = false;
+};
+
+// Device buffer shared by a handle and the graphs captured with it: a buffer
+// the handle replaces (a larger position-ordered solution) stays allocated
+// until the last graph that baked its address into a kernel is destroyed.
+struct DevBuffer {
+  void* p = nullptr;
+  DevBuffer() = default;
+  DevBuffer(const DevBuffer&) = delete;
+  DevBuffer& operator=(const DevBuffer&) = delete;
+  ~DevBuffer() {
+    if (p) (void)hipFree(p);   // hipFree waits for the device before freeing
+  }
+};
+
 }  // namespace
 
 struct sptrsv_handle_s {
@@ -111,8 +136,10 @@ struct sptrsv_handle_s {
   double setup_ms = 0.0;           // wall time of the analysis call
   BlockState blk[2];               // block-ordered plans of T and T^T
   DevScratch scratch;
-  void* xp = nullptr;             // position-ordered solution(s) of the solve kernels
+  std::shared_ptr<DevBuffer> xp_buf;   // position-ordered solution(s) of the solve kernels
+  void* xp = nullptr;             // xp_buf->p
   int64_t xp_elems = 0;
+  int live_graphs = 0;            // graphs captured from this handle, not yet destroyed
   // batched handles keep the concatenated pattern and values on the device
   bool batched = false;
   std::vector<int> sys_n, sys_nnz;
@@ -154,6 +181,8 @@ struct sptrsv_handle_s {
 struct sptrsv_graph_s {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  sptrsv_handle_t owner = nullptr;
+  std::shared_ptr<DevBuffer> xp_keep;   // the position-ordered buffer the graph's kernels use
 };
 
 #define HIPCHK(expr)                          \
@@ -195,10 +224,15 @@ void free_chunks(PlanState& ps) {
 
 // Per-wavefront chunk lists of a static schedule over W wavefronts (built on
 // first use and kept; synchronous upload).
-const WaveLists* get_wave_lists(ChunkEntry& ch, int W, int regions, int* err) {
+const WaveLists* get_wave_lists(ChunkEntry& ch, int W, int regions, int* err,
+                                bool no_alloc = false) {
   const auto key = std::make_pair(W, regions);
   auto it = ch.waves.find(key);
   if (it != ch.waves.end()) return &it->second;
+  if (no_alloc) {
+    *err = kErrNotSupported;
+    return nullptr;
+  }
   ChunkTable t;
   t.start = ch.h_start;
   t.meta = ch.h_meta;
@@ -393,11 +427,15 @@ int build_block(sptrsv_handle_t h, int dir, hipStream_t s) {
 bool upload_chunks(const ChunkTable& t, ChunkEntry& e, int* err);
 
 ChunkEntry* get_chunks(sptrsv_handle_t h, PlanState& ps, int group, int epl, int rows_fixed,
-                       int rpl, int* err) {
+                       int rpl, int* err, bool no_alloc = false) {
   (void)h;
   auto key = std::make_tuple(group, epl, rows_fixed, rpl);
   auto it = ps.chunks.find(key);
   if (it != ps.chunks.end()) return &it->second;
+  if (no_alloc) {
+    *err = kErrNotSupported;
+    return nullptr;
+  }
   ChunkTable t;
   build_chunks(ps.h, group, epl, rows_fixed, rpl, t);
   ChunkEntry e;
@@ -407,10 +445,14 @@ ChunkEntry* get_chunks(sptrsv_handle_t h, PlanState& ps, int group, int epl, int
 
 // Chunks over the push lists of a plan: rows of one level get lanes by the
 // length of their push list.
-ChunkEntry* get_push_chunks(PlanState& ps, int group, int epl, int* err) {
+ChunkEntry* get_push_chunks(PlanState& ps, int group, int epl, int* err, bool no_alloc = false) {
   auto key = std::make_pair(group, epl);
   auto it = ps.push.chunks.find(key);
   if (it != ps.push.chunks.end()) return &it->second;
+  if (no_alloc) {
+    *err = kErrNotSupported;
+    return nullptr;
+  }
   HostPlan view;
   view.n = ps.h.n;
   view.nlev = ps.h.nlev;
@@ -480,18 +522,18 @@ uint64_t tune_key(sptrsv_handle_t h) {
          (static_cast<uint64_t>(h->algo) << 56);
 }
 
-// Grows the position-ordered solution buffer to `elems` values (blocking:
-// frees the previous buffer once the device is idle).
+// Grows the position-ordered solution buffer to `elems` values.  Work the
+// handle issued earlier may still use the old buffer: it is waited for
+// through the handle's ordering event (not the whole device), and a graph
+// captured with the old buffer keeps it alive (see DevBuffer).
 int ensure_xp(sptrsv_handle_t h, int64_t elems) {
   if (h->xp_elems >= elems) return kOk;
-  if (h->xp) {
-    HIPCHK(hipDeviceSynchronize());
-    dfree(h->xp);
-  }
-  h->xp = nullptr;
-  h->xp_elems = 0;
-  if (hipMalloc(&h->xp, static_cast<size_t>(elems > 0 ? elems : 1) * h->vb) != hipSuccess)
+  if (h->xp_buf && h->order_ev && h->order_pending) HIPCHK(hipEventSynchronize(h->order_ev));
+  auto nb = std::make_shared<DevBuffer>();
+  if (hipMalloc(&nb->p, static_cast<size_t>(elems > 0 ? elems : 1) * h->vb) != hipSuccess)
     return kErrOom;
+  h->xp_buf = std::move(nb);   // frees the old buffer unless a graph holds it
+  h->xp = h->xp_buf->p;
   h->xp_elems = elems;
   return kOk;
 }
@@ -543,9 +585,9 @@ int fold_timing(sptrsv_handle_t h) {
 
 constexpr size_t kMaxTimedSolves = 1024;   // event pairs kept before they are folded
 
-void timing_begin(sptrsv_handle_t h, hipStream_t s, hipEvent_t* stop) {
+void timing_begin(sptrsv_handle_t h, hipStream_t s, hipEvent_t* stop, bool no_alloc = false) {
   *stop = nullptr;
-  if (!h->timing) return;
+  if (!h->timing || no_alloc) return;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
   if (h->ev_used == kMaxTimedSolves && fold_timing(h) != kOk) return;
@@ -640,15 +682,15 @@ int regather_push(sptrsv_handle_t h, hipStream_t s) {
 // (one cooperative launch, chunk c on wavefront c mod W, or by XCD region).
 template <typename T>
 int solve_column(sptrsv_handle_t h, PlanState& ps, const Config& c, const void* b, void* x,
-                 hipStream_t s) {
+                 hipStream_t s, const SolveExt& ext) {
   if (!ps.push.built) {
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cap) != hipSuccess) return kErrHip;
-    if (cap != hipStreamCaptureStatusNone) return kErrNotSupported;
+    if (cap != hipStreamCaptureStatusNone || ext.no_alloc) return kErrNotSupported;
     if (const int st = build_push_state(h, ps, s)) return st;
   }
   int err = kOk;
-  ChunkEntry* ch = get_push_chunks(ps, c.group, c.epl, &err);
+  ChunkEntry* ch = get_push_chunks(ps, c.group, c.epl, &err, ext.no_alloc);
   if (!ch) return err;
   ColumnArgs a;
   a.plan = &ps.d;
@@ -664,7 +706,7 @@ int solve_column(sptrsv_handle_t h, PlanState& ps, const Config& c, const void* 
   if (launch_column_init<T>(a, s) != hipSuccess) return kErrHip;
   hipEvent_t stop;
   if (c.algo == SPTRSV_ALGO_COLUMN_LEVEL) {
-    timing_begin(h, s, &stop);
+    timing_begin(h, s, &stop, ext.no_alloc);
     for (int m = 0; m < ps.h.nlev; ++m)
       if (launch_column_level<T>(a, ch->level_chunk[m], ch->level_chunk[m + 1], s) != hipSuccess)
         return kErrHip;
@@ -674,11 +716,11 @@ int solve_column(sptrsv_handle_t h, PlanState& ps, const Config& c, const void* 
   a.grid = persistent_grid(h, 4, c.grid, ch->d.count);
   const int W = a.grid * (h->wg / 64);
   const int regions = (c.assign == SPTRSV_ASSIGN_XCD && W % 8 == 0) ? 8 : 1;
-  const WaveLists* wl = get_wave_lists(*ch, W, regions, &err);
+  const WaveLists* wl = get_wave_lists(*ch, W, regions, &err, ext.no_alloc);
   if (!wl) return err;
   a.wave_ptr = wl->ptr;
   a.wave_list = wl->list;
-  timing_begin(h, s, &stop);
+  timing_begin(h, s, &stop, ext.no_alloc);
   if (launch_column_self<T>(a, s) != hipSuccess) return kErrHip;
   timing_end(s, stop);
   return kOk;
@@ -686,12 +728,12 @@ int solve_column(sptrsv_handle_t h, PlanState& ps, const Config& c, const void* 
 
 template <typename T>
 int solve_impl(sptrsv_handle_t h, PlanState& ps, const Config& c_in, const void* b, void* x,
-               int nrhs, int ld, hipStream_t s) {
+               int nrhs, int ld, hipStream_t s, const SolveExt& ext = SolveExt()) {
   const int n = h->n;
   h->last_stream = s;
   if (n == 0 || nrhs == 0) return kOk;
   const bool multi = nrhs > 1;
-  if (is_column(c_in.algo) && !multi) return solve_column<T>(h, ps, c_in, b, x, s);
+  if (is_column(c_in.algo) && !multi) return solve_column<T>(h, ps, c_in, b, x, s, ext);
   // several right-hand sides under a column-wise schedule: row-wise, self-scheduled
   Config c = c_in;
   if (is_column(c.algo)) {
@@ -707,26 +749,36 @@ int solve_impl(sptrsv_handle_t h, PlanState& ps, const Config& c_in, const void*
   const bool capturing = cap != hipStreamCaptureStatusNone;
   bool use_static = c.algo == SPTRSV_ALGO_SELF && (multi || c.sync == SPTRSV_SYNC_VALUE) &&
                     (c.assign == SPTRSV_ASSIGN_STATIC || c.assign == SPTRSV_ASSIGN_XCD);
-  ChunkEntry* ch = multi ? get_chunks(h, ps, 0, 0, 64 / kl, 1, &err)
-                         : get_chunks(h, ps, c.group, c.epl, 0, use_static ? 1 : c.rpl, &err);
+  ChunkEntry* ch = multi ? get_chunks(h, ps, 0, 0, 64 / kl, 1, &err, ext.no_alloc)
+                         : get_chunks(h, ps, c.group, c.epl, 0, use_static ? 1 : c.rpl, &err,
+                                      ext.no_alloc);
   if (!ch) return err;
-  // under capture the per-wavefront lists cannot be uploaded: the static
-  // form is captured only when they exist (sptrsv_graph_capture builds them)
-  if (use_static && capturing && !static_lists_ready(h, *ch, c)) {
+  // under capture (or without allocation) the per-wavefront lists cannot be
+  // uploaded: the static form is used only when they exist
+  // (sptrsv_graph_capture and the analysis build them), else the ticket form
+  if (use_static && (capturing || ext.no_alloc) && !static_lists_ready(h, *ch, c)) {
     use_static = false;
-    if (!multi && c.rpl != 1 && !(ch = get_chunks(h, ps, c.group, c.epl, 0, c.rpl, &err)))
+    if (!multi && c.rpl != 1 &&
+        !(ch = get_chunks(h, ps, c.group, c.epl, 0, c.rpl, &err, ext.no_alloc)))
       return err;
   }
   // the static schedules with one right-hand side may space the values out
   const int stride = use_static && !multi ? c.stride : 1;
-  if ((err = ensure_xp(h, static_cast<int64_t>(n) * nrhs * stride))) return err;
+  const int64_t xp_need = static_cast<int64_t>(n) * nrhs * stride;
+  void* xp = ext.xp;
+  if (xp) {
+    if (xp_need * static_cast<int64_t>(h->vb) > ext.xp_bytes) return kErrInvalidArg;
+  } else {
+    if ((err = ensure_xp(h, xp_need))) return err;
+    xp = h->xp;
+  }
   SolveArgs a;
   a.plan = &ps.d;
   a.chunks = &ch->d;
   a.scratch = h->scratch;
   a.b = b;
   a.x = x;
-  a.xp = h->xp;
+  a.xp = xp;
   a.nrhs = nrhs;
   a.ld = ld;
   a.spin_limit = h->spin_limit;
@@ -737,14 +789,14 @@ int solve_impl(sptrsv_handle_t h, PlanState& ps, const Config& c_in, const void*
   if (c.algo == SPTRSV_ALGO_BLOCK && !multi) {
     const int dir = (&ps == &h->trn) ? 1 : 0;
     BlockState& bs = h->blk[dir];
-    if (!bs.built) return kErrInvalidArg;   // built by solve_dispatch / capture
+    if (!bs.built) return ext.no_alloc ? kErrNotSupported : kErrInvalidArg;
     a.plan = &bs.ps.d;
     int threads = 64;
     while (threads < bs.info.max_level && threads < 1024) threads <<= 1;
     const size_t lds_bytes = static_cast<size_t>(bs.info.max_rows) * sizeof(T);
     const int lds_rows = lds_bytes <= static_cast<size_t>(h->lds_limit) ? bs.info.max_rows : 0;
     const int nseg = static_cast<int>(bs.info.seg_row0.size()) - 1;
-    timing_begin(h, s, &stop);
+    timing_begin(h, s, &stop, ext.no_alloc);
     if (launch_block<T>(a, bs.seg_row0, bs.seg_base, bs.lev_pos, nseg, threads, lds_rows, s) !=
         hipSuccess)
       return kErrHip;
@@ -752,7 +804,7 @@ int solve_impl(sptrsv_handle_t h, PlanState& ps, const Config& c_in, const void*
     return kOk;
   }
   if (c.algo == SPTRSV_ALGO_LEVEL || c.algo == SPTRSV_ALGO_BLOCK) {
-    timing_begin(h, s, &stop);
+    timing_begin(h, s, &stop, ext.no_alloc);
     for (int m = 0; m < ps.h.nlev; ++m) {
       const int cb = ch->level_chunk[m], ce = ch->level_chunk[m + 1];
       const hipError_t e = launch_level<T>(a, cb, ce, s);
@@ -764,15 +816,14 @@ int solve_impl(sptrsv_handle_t h, PlanState& ps, const Config& c_in, const void*
   if (c.algo != SPTRSV_ALGO_SELF) return kErrNotSupported;
   if (c.sync == SPTRSV_SYNC_FLAG && !multi) {
     a.grid = persistent_grid(h, 1, c.grid, ch->d.count);
-    timing_begin(h, s, &stop);
+    timing_begin(h, s, &stop, ext.no_alloc);
     if (launch_self_flag<T>(a, s) != hipSuccess) return kErrHip;
     timing_end(s, stop);
     return kOk;
   }
   // value sync: xp starts as the sentinel (b == x needs no copy: a row reads
   // its own b before any write of its own x, and x is only written)
-  if (launch_fill_sentinel<T>(static_cast<T*>(h->xp), static_cast<int64_t>(n) * nrhs * stride, s) !=
-      hipSuccess)
+  if (launch_fill_sentinel<T>(static_cast<T*>(xp), xp_need, s) != hipSuccess)
     return kErrHip;
   a.grid = persistent_grid(h, use_static ? 3 : 0, c.grid, ch->d.count);
   if (use_static) {
@@ -781,7 +832,7 @@ int solve_impl(sptrsv_handle_t h, PlanState& ps, const Config& c_in, const void*
     a.wave_ptr = wl->ptr;
     a.wave_list = wl->list;
   }
-  timing_begin(h, s, &stop);
+  timing_begin(h, s, &stop, ext.no_alloc);
   const hipError_t e = use_static ? launch_self_static<T>(a, s) : launch_self_value<T>(a, s);
   if (e != hipSuccess) return kErrHip;
   timing_end(s, stop);
@@ -813,34 +864,71 @@ int order_end(sptrsv_handle_t h, hipStream_t s, bool capturing) {
 }
 
 int solve_dispatch_ordered(sptrsv_handle_t h, bool transpose, const void* b, void* x, int nrhs,
-                           int ld, hipStream_t s);
+                           int ld, hipStream_t s, const SolveExt& ext);
 
 int solve_dispatch(sptrsv_handle_t h, bool transpose, const void* b, void* x, int nrhs, int ld,
-                   hipStream_t s) {
+                   hipStream_t s, const SolveExt& ext = SolveExt()) {
   if (!h) return kErrInvalidArg;
   if (h->n > 0 && (!b || !x)) return kErrInvalidArg;
   bool capturing = false;
   int st = order_begin(h, s, &capturing);
   if (st) return st;
-  st = solve_dispatch_ordered(h, transpose, b, x, nrhs, ld, s);
+  st = solve_dispatch_ordered(h, transpose, b, x, nrhs, ld, s, ext);
   const int st2 = order_end(h, s, capturing);
   return st ? st : st2;
 }
 
 int solve_dispatch_ordered(sptrsv_handle_t h, bool transpose, const void* b, void* x, int nrhs,
-                           int ld, hipStream_t s) {
-  if (transpose) {
+                           int ld, hipStream_t s, const SolveExt& ext) {
+  if (transpose && !h->trn.built) {
+    if (ext.no_alloc) return kErrNotSupported;
     const int st = build_transpose(h, s);
     if (st) return st;
   }
   PlanState& ps = transpose ? h->trn : h->fwd;
   const Config c = nrhs > 1 ? resolve_multi(h, nrhs) : resolve(h);
-  if (c.algo == SPTRSV_ALGO_BLOCK && nrhs == 1) {
+  if (c.algo == SPTRSV_ALGO_BLOCK && nrhs == 1 && !h->blk[transpose ? 1 : 0].built) {
+    if (ext.no_alloc) return kErrNotSupported;
     const int st = build_block(h, transpose ? 1 : 0, s);
     if (st) return st;
   }
-  if (h->dtype == SPTRSV_F64) return solve_impl<double>(h, ps, c, b, x, nrhs, ld, s);
-  return solve_impl<float>(h, ps, c, b, x, nrhs, ld, s);
+  if (h->dtype == SPTRSV_F64) return solve_impl<double>(h, ps, c, b, x, nrhs, ld, s, ext);
+  return solve_impl<float>(h, ps, c, b, x, nrhs, ld, s, ext);
+}
+
+// Builds everything solves with schedule c (one right-hand side) on T or
+// T^T need, with synchronous uploads: the chunk table, the occupancy
+// figures, the static schedule's per-wavefront lists and position-ordered
+// buffer, the block plan, the push lists.  Run before a graph capture and at
+// the end of the analysis (for the default schedule), so that later solves
+// with c allocate nothing.
+int prepare_schedule(sptrsv_handle_t h, bool transpose, const Config& c, hipStream_t s) {
+  if (h->n == 0) return kOk;
+  if (transpose)
+    if (const int st = build_transpose(h, s)) return st;
+  int err = kOk;
+  PlanState& ps = transpose ? h->trn : h->fwd;
+  if (!get_chunks(h, ps, c.group, c.epl, 0, c.rpl, &err)) return err;
+  for (int kind : {0, 1, 3, 4}) (void)blocks_per_cu(h, kind);
+  if (c.algo == SPTRSV_ALGO_SELF && c.sync == SPTRSV_SYNC_VALUE &&
+      (c.assign == SPTRSV_ASSIGN_STATIC || c.assign == SPTRSV_ASSIGN_XCD)) {
+    ChunkEntry* ch = get_chunks(h, ps, c.group, c.epl, 0, 1, &err);
+    if (!ch || !static_lists(h, *ch, c, &err)) return err;
+    if ((err = ensure_xp(h, static_cast<int64_t>(h->n) * c.stride))) return err;
+  }
+  if (c.algo == SPTRSV_ALGO_BLOCK && (err = build_block(h, transpose ? 1 : 0, s))) return err;
+  if (is_column(c.algo)) {
+    if ((err = build_push_state(h, ps, s))) return err;
+    ChunkEntry* ch = get_push_chunks(ps, c.group, c.epl, &err);
+    if (!ch) return err;
+    if (c.algo == SPTRSV_ALGO_COLUMN_SELF) {
+      const int grid = persistent_grid(h, 4, c.grid, ch->d.count);
+      const int W = grid * (h->wg / 64);
+      if (!get_wave_lists(*ch, W, (c.assign == SPTRSV_ASSIGN_XCD && W % 8 == 0) ? 8 : 1, &err))
+        return err;
+    }
+  }
+  return kOk;
 }
 
 int init_handle_common(sptrsv_handle_t h, hipStream_t s) {
@@ -861,6 +949,7 @@ int init_handle_common(sptrsv_handle_t h, hipStream_t s) {
   h->scratch.flags = dalloc<unsigned>(h->n, &err);
   if (err) return err;
   if ((err = ensure_xp(h, h->n))) return err;
+  HIPCHK(hipEventCreateWithFlags(&h->order_ev, hipEventDisableTiming));
   HIPCHK(launch_init_scratch(h->scratch, h->n, s));
   return kOk;
 }
@@ -958,7 +1047,8 @@ void destroy_handle(sptrsv_handle_t h) {
   dfree(h->scratch.status);
   dfree(h->scratch.epoch);
   dfree(h->scratch.flags);
-  dfree(h->xp);
+  h->xp_buf.reset();
+  h->xp = nullptr;
   dfree(h->rp_cat);
   dfree(h->col_cat);
   dfree(h->vals_cat);
@@ -977,6 +1067,22 @@ void destroy_handle(sptrsv_handle_t h) {
 }
 
 }  // namespace
+
+namespace sptrsv {
+
+int solve_external_scratch(sptrsv_handle_t h, const void* b, void* x, void* xp, int64_t xp_bytes,
+                           hipStream_t s) {
+  if (!h || !xp || xp_bytes <= 0) return kErrInvalidArg;
+  SolveExt ext;
+  ext.xp = xp;
+  ext.xp_bytes = xp_bytes;
+  ext.no_alloc = true;
+  return solve_dispatch(h, false, b, x, 1, h->n, s, ext);
+}
+
+int handle_device(sptrsv_handle_t h) { return h ? h->device : -1; }
+
+}  // namespace sptrsv
 
 extern "C" {
 
@@ -1028,6 +1134,8 @@ int sptrsv_analyze_ex(int32_t n, int32_t nnz, const int32_t* row_ptr, const int3
     st = analyze_from_host(h, vals, stream);
     h->setup = SPTRSV_SETUP_HOST;
   }
+  // the default schedule's work tables, so that the first solve allocates nothing
+  if (!st) st = prepare_schedule(h, false, resolve(h), stream);
   if (st) {
     destroy_handle(h);
     return st;
@@ -1119,6 +1227,7 @@ int sptrsv_analyze_batched(int32_t count, const int32_t* n, const int32_t* nnz,
   int st = analyze_from_host(h, h->vals_cat, stream);
   if (!st) st = upload_ints(&h->rp_cat, h->rp_h, stream);
   if (!st) st = upload_ints(&h->col_cat, h->col_h, stream);
+  if (!st) st = prepare_schedule(h, false, resolve(h), stream);
   if (!st && hipStreamSynchronize(stream) != hipSuccess) st = kErrHip;
   if (st) {
     destroy_handle(h);
@@ -1596,13 +1705,16 @@ const char* sptrsv_status_string(int status) {
     case SPTRSV_ERR_OOM: return "out of memory";
     case SPTRSV_ERR_TIMEOUT: return "self-scheduled wait timed out";
     case SPTRSV_ERR_NOT_SUPPORTED: return "not supported";
+    case SPTRSV_ERR_BUSY: return "handle still has live graphs";
   }
   return "unknown status";
 }
 
 int sptrsv_destroy(sptrsv_handle_t h) {
   if (!h) return kErrInvalidArg;
-  (void)hipDeviceSynchronize();
+  if (h->live_graphs > 0) return kErrBusy;   // their kernels use the handle's buffers
+  // the handle's own work first (hipFree also waits for the device)
+  if (h->order_ev && h->order_pending) (void)hipEventSynchronize(h->order_ev);
   destroy_handle(h);
   return kOk;
 }
@@ -1615,35 +1727,9 @@ int sptrsv_graph_capture(sptrsv_handle_t h, const void* b, void* x, int transpos
     const int st = build_transpose(h, stream);
     if (st) return st;
   }
-  // make sure the chunk table, the occupancy figures and the static schedule's
-  // per-wavefront lists exist before capture (their uploads are synchronous)
-  {
-    const Config c = resolve(h);
-    int err = kOk;
-    PlanState& ps = transpose ? h->trn : h->fwd;
-    if (h->n > 0 && !get_chunks(h, ps, c.group, c.epl, 0, c.rpl, &err)) return err;
-    for (int kind : {0, 1, 3, 4}) (void)blocks_per_cu(h, kind);
-    if (h->n > 0 && c.algo == SPTRSV_ALGO_SELF && c.sync == SPTRSV_SYNC_VALUE &&
-        (c.assign == SPTRSV_ASSIGN_STATIC || c.assign == SPTRSV_ASSIGN_XCD)) {
-      ChunkEntry* ch = get_chunks(h, ps, c.group, c.epl, 0, 1, &err);
-      if (!ch || !static_lists(h, *ch, c, &err)) return err;
-      // xp is resized outside the capture
-      if ((err = ensure_xp(h, static_cast<int64_t>(h->n) * c.stride))) return err;
-    }
-    if (h->n > 0 && c.algo == SPTRSV_ALGO_BLOCK && (err = build_block(h, transpose ? 1 : 0, stream)))
-      return err;
-    if (h->n > 0 && is_column(c.algo)) {
-      if ((err = build_push_state(h, ps, stream))) return err;
-      ChunkEntry* ch = get_push_chunks(ps, c.group, c.epl, &err);
-      if (!ch) return err;
-      if (c.algo == SPTRSV_ALGO_COLUMN_SELF) {
-        const int grid = persistent_grid(h, 4, c.grid, ch->d.count);
-        const int W = grid * (h->wg / 64);
-        if (!get_wave_lists(*ch, W, (c.assign == SPTRSV_ASSIGN_XCD && W % 8 == 0) ? 8 : 1, &err))
-          return err;
-      }
-    }
-  }
+  // the work tables, occupancy figures and buffers exist before the capture
+  // (their uploads are synchronous)
+  if (const int st = prepare_schedule(h, transpose != 0, resolve(h), stream)) return st;
   auto* g = new (std::nothrow) sptrsv_graph_s;
   if (!g) return kErrOom;
   if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
@@ -1662,6 +1748,9 @@ int sptrsv_graph_capture(sptrsv_handle_t h, const void* b, void* x, int transpos
     delete g;
     return kErrHip;
   }
+  g->owner = h;
+  g->xp_keep = h->xp_buf;
+  h->live_graphs++;
   *out = g;
   return kOk;
 }
@@ -1675,7 +1764,8 @@ int sptrsv_graph_destroy(sptrsv_graph_t g) {
   if (!g) return kErrInvalidArg;
   if (g->exec) (void)hipGraphExecDestroy(g->exec);
   if (g->graph) (void)hipGraphDestroy(g->graph);
-  delete g;
+  if (g->owner) g->owner->live_graphs--;
+  delete g;   // releases the graph's hold on its position-ordered buffer
   return kOk;
 }
 

@@ -101,3 +101,34 @@ def test_batched_grad(sp):
         assert relerr(gv[eoff:eoff + t.nnz], gvo) <= 1e-12
         off += t.n
         eoff += t.nnz
+
+
+def test_chained_calls_share_one_handle(sp):
+    """y = T2^{-1} (T1^{-1} b) with T1, T2 two value sets on ONE handle: the
+    first call's backward runs after the second forward re-gathered other
+    values, so it must gather its own again.  Dense reference gradients."""
+    T = W.ilu0_lower((5, 5, 4))
+    v1 = T.vals * W.uniform_vector(T.nnz, 21, 0.8, 1.2)
+    v2 = T.vals * W.uniform_vector(T.nnz, 22, 0.7, 1.3)
+    rp, ci, _ = dev_tri(T)
+    h = sp.Handle(rp, ci, dev(v1))
+    a1 = dev(v1).requires_grad_(True)
+    a2 = dev(v2).requires_grad_(True)
+    b_np = W.uniform_vector(T.n, 23)
+    w_np = W.uniform_vector(T.n, 24)
+    b = dev(b_np).requires_grad_(True)
+    y = sp.sptrsv(a2, sp.sptrsv(a1, b, h), h)
+    (y * dev(w_np)).sum().backward()
+    rows = np.repeat(np.arange(T.n), np.diff(T.row_ptr))
+    M1 = np.zeros((T.n, T.n))
+    M2 = np.zeros((T.n, T.n))
+    M1[rows, T.col_idx] = v1
+    M2[rows, T.col_idx] = v2
+    z = np.linalg.solve(M1, b_np)
+    yd = np.linalg.solve(M2, z)
+    g2 = np.linalg.solve(M2.T, w_np)            # d loss / d z
+    g1 = np.linalg.solve(M1.T, g2)              # d loss / d b
+    assert relerr(host(y), yd) <= 1e-12
+    assert relerr(host(b.grad), g1) <= 1e-10
+    assert relerr(host(a2.grad), -g2[rows] * yd[T.col_idx]) <= 1e-10
+    assert relerr(host(a1.grad), -g1[rows] * z[T.col_idx]) <= 1e-10
