@@ -75,8 +75,10 @@ typedef enum {
     SPTRSV_ERR_OOM = -9,            /* device or host allocation failed */
     SPTRSV_ERR_TIMEOUT = -10,       /* self-scheduled wait exceeded its spin limit */
     SPTRSV_ERR_NOT_SUPPORTED = -11, /* valid request the library does not implement */
-    SPTRSV_ERR_BUSY = -12           /* sptrsv_destroy: graphs captured from the handle are
+    SPTRSV_ERR_BUSY = -12,          /* sptrsv_destroy: graphs captured from the handle are
                                        still alive (destroy them first) */
+    SPTRSV_ERR_TOO_LARGE = -13      /* sptrsv_solve_noalloc: the schedule needs more than
+                                       SPTRSV_NOALLOC_SCRATCH_BYTES of scratch */
 } sptrsv_status;
 
 typedef enum { SPTRSV_F64 = 0, SPTRSV_F32 = 1 } sptrsv_dtype;
@@ -241,6 +243,26 @@ int sptrsv_update_values_batched(sptrsv_handle_t h, const void *const *vals, hip
  * b, x: device vectors of n elements of the handle's dtype.  b == x (in
  * place) is allowed; partial overlap is not.  Asynchronous. */
 int sptrsv_solve(sptrsv_handle_t h, const void *b, void *x, hipStream_t stream);
+
+/* sptrsv_solve for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same schedule, kernels and result (bit for bit) as sptrsv_solve, but the
+ * position-ordered solution the kernels publish and poll lives in a
+ * library-owned static device array of SPTRSV_NOALLOC_SCRATCH_BYTES (64
+ * MiB) per GPU, held until the process ends, instead of the handle's
+ * buffer, and the call allocates nothing (no hipMalloc, hipFree, event or
+ * library allocation).  Needs n * slot stride * value bytes <= 64 MiB
+ * (FP64 packed: up to 8,388,608 rows), else SPTRSV_ERR_TOO_LARGE.  The work
+ * tables of the handle's current schedule must already exist: the analysis
+ * builds those of the default schedule and sptrsv_tune those of its choice
+ * (as does any earlier sptrsv_solve or graph capture with that schedule);
+ * otherwise SPTRSV_ERR_NOT_SUPPORTED, as for column-wise schedules not yet
+ * prepared.  The current device must be the handle's (else INVALID_ARG).
+ * All calls on one GPU share the array, which keeps the last call's
+ * contents (each solve reinitialises what it reads): calls that overlap in
+ * time on one GPU race; order them on one stream.  Asynchronous. */
+#define SPTRSV_NOALLOC_SCRATCH_BYTES (64u << 20)
+int sptrsv_solve_noalloc(sptrsv_handle_t h, const void *b, void *x, hipStream_t stream);
 
 /* Solve T^T x = b.  Uses the analysis of T^T (the column-wise view of
  * Sec. 3.2: rows of T^T are the columns of T, levels from the reversed

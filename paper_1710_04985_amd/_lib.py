@@ -16,7 +16,7 @@ STATUS = {
     -3: "SPTRSV_ERR_BAD_COLIDX", -4: "SPTRSV_ERR_NOT_TRIANGULAR", -5: "SPTRSV_ERR_DUPLICATE",
     -6: "SPTRSV_ERR_MISSING_DIAG", -7: "SPTRSV_ERR_ZERO_PIVOT", -8: "SPTRSV_ERR_HIP",
     -9: "SPTRSV_ERR_OOM", -10: "SPTRSV_ERR_TIMEOUT", -11: "SPTRSV_ERR_NOT_SUPPORTED",
-    -12: "SPTRSV_ERR_BUSY",
+    -12: "SPTRSV_ERR_BUSY", -13: "SPTRSV_ERR_TOO_LARGE",
 }
 
 
@@ -56,6 +56,7 @@ SIGNATURES = {
     "sptrsv_update_values_batched": (_int, [_v, _v, _v]),
     "sptrsv_solve": (_int, [_v, _v, _v, _v]),
     "sptrsv_solve_transpose": (_int, [_v, _v, _v, _v]),
+    "sptrsv_solve_noalloc": (_int, [_v, _v, _v, _v]),
     "sptrsv_prepare_transpose": (_int, [_v, _v]),
     "sptrsv_solve_multi": (_int, [_v, _i32, _i32, _v, _v, _int, _v]),
     "sptrsv_grad_vals": (_int, [_v, _v, _v, _v, _v, _v, _v]),

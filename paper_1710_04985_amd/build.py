@@ -25,7 +25,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-I", INCLUDE, "-I", CSRC]
 
-SOURCES = ["analysis.cpp", "analysis_gpu.hip", "api.cpp", "column.hip", "kernels.hip", "probe.hip"]
+SOURCES = ["analysis.cpp", "analysis_gpu.hip", "api.cpp", "column.hip", "kernels.hip", "noalloc.hip",
+           "probe.hip"]
 
 
 def _compile(src: str) -> str:

@@ -767,7 +767,7 @@ int solve_impl(sptrsv_handle_t h, PlanState& ps, const Config& c_in, const void*
   const int64_t xp_need = static_cast<int64_t>(n) * nrhs * stride;
   void* xp = ext.xp;
   if (xp) {
-    if (xp_need * static_cast<int64_t>(h->vb) > ext.xp_bytes) return kErrInvalidArg;
+    if (xp_need * static_cast<int64_t>(h->vb) > ext.xp_bytes) return kErrTooLarge;
   } else {
     if ((err = ensure_xp(h, xp_need))) return err;
     xp = h->xp;
@@ -1706,6 +1706,7 @@ const char* sptrsv_status_string(int status) {
     case SPTRSV_ERR_TIMEOUT: return "self-scheduled wait timed out";
     case SPTRSV_ERR_NOT_SUPPORTED: return "not supported";
     case SPTRSV_ERR_BUSY: return "handle still has live graphs";
+    case SPTRSV_ERR_TOO_LARGE: return "request exceeds the fixed scratch capacity";
   }
   return "unknown status";
 }

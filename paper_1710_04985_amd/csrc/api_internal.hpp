@@ -11,7 +11,7 @@ namespace sptrsv {
 // buffer xp (xp_bytes of device memory on the handle's device) instead of the
 // handle's own, and no allocation of any kind: work tables that the current
 // schedule needs and that do not exist yet give kErrNotSupported, a schedule
-// that needs more than xp_bytes is refused.  Serialized with the
+// that needs more than xp_bytes gives kErrTooLarge.  Serialized with the
 // handle's other calls like sptrsv_solve.
 int solve_external_scratch(sptrsv_handle_t h, const void* b, void* x, void* xp, int64_t xp_bytes,
                            hipStream_t s);
