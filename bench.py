@@ -15,8 +15,13 @@ in HBM before the timed region.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 
-Prints one JSON line.  --suite also writes per-configuration lines for the
-other workloads to bench_suite.jsonl in the output folder (--out-dir).
+Prints one JSON line.  Its "per_config" object holds the other workloads
+(2-D 64x64 lower, the random power-law triangle in FP64 and FP32, the batch
+of 256 ILU(0) factors, 16 right-hand sides, the forward solve plus adjoint),
+each under the same protocol with its full-size oracle error, roofline
+fraction, critical-path bound and setup break-even (Sec. 5.3, Table 7).
+--suite also writes per-configuration lines (with the block schedule and
+graph replays) to bench_suite.jsonl in the output folder (--out-dir).
 """
 from __future__ import annotations
 
@@ -51,6 +56,8 @@ def parse():
     ap.add_argument("--assign", type=int, default=None, help="fixed chunk assignment (with --no-tune)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
+    ap.add_argument("--no-per-config", action="store_true",
+                    help="skip the other workloads (C1, C3, C4a, C4b, C5) in the JSON line")
     ap.add_argument("--suite", action="store_true")
     ap.add_argument("--setup", action="store_true",
                     help="also time the host and device setup routes (bench_setup.jsonl)")
@@ -345,6 +352,22 @@ def main():
                           "bound_ms_per_triangle": round(nlev * hop_same * 1e-6, 5),
                           "kernel_over_bound": round(kernel_ms / (nlev * hop_same * 1e-6), 3)},
     }
+    # setup amortisation (Sec. 5.3, Table 7) on the lower triangle: solves
+    # after which the self-scheduled solver with the device analysis has cost
+    # less in total than the level-scheduled one with the host analysis, and
+    # than itself with the host analysis (same plan, same solve time)
+    import bench_suite
+    out["setup"] = {
+        "self_device_route_ms": round(analysis_ms, 2), "level_host_route_ms": round(analysis_ms_host, 2),
+        "n_s_self_device_vs_level_host": bench_suite.break_even(
+            analysis_ms, ms_self / 2, analysis_ms_host, ms_level / 2),
+        "n_s_device_vs_host_route": bench_suite.break_even(
+            analysis_ms, ms_self / 2, analysis_ms_host, ms_self / 2)}
+    if not args.no_per_config:
+        for h in (hL, hU, lvL, lvU):
+            h.close()
+        torch.cuda.synchronize()
+        out["per_config"] = bench_suite.per_config(sp, torch, args.steps, args.warmup, hop_same)
     if not args.no_cpu_baseline:
         t_cpu, reps = cpu_baseline(TL, TU, bL, args.cpu_seconds)
         model, ncpu, mhz = cpu_info()

@@ -335,3 +335,245 @@ def setup_routes(sp, torch, out_path, reps=3):
         with open(out_path, "a") as f:
             f.write(json.dumps(res) + "\n")
     return rows
+
+
+# ------------------------------------------------------------------------
+# Per-configuration records of the default bench line: every workload other
+# than the headline one, under the headline's protocol (the paper's Sec. 5:
+# mean of back-to-back solves, warm, inputs resident in HBM), with the
+# roofline fraction, the critical-path bound, the full-size oracle error and
+# the setup amortisation of Table 7.
+
+def break_even(setup_a, solve_a, setup_b, solve_b):
+    """Smallest n_s >= 0 with setup_a + n_s*solve_a < setup_b + n_s*solve_b
+    (the paper's Sec. 5.3 criterion for Table 7); None if never."""
+    if setup_a < setup_b and solve_a <= solve_b:
+        return 0
+    if solve_a >= solve_b:
+        return None
+    return int(np.floor((setup_a - setup_b) / (solve_b - solve_a))) + 1
+
+
+def _kernel_ms(torch, h, fn, steps):
+    """Mean duration of the library's main solve kernel (HIP events the
+    library records on the solve stream around it)."""
+    h.set_option("timing", 1)
+    h.kernel_time(reset=True)
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    ms, cnt = h.kernel_time(reset=True)
+    h.set_option("timing", 0)
+    return ms / max(cnt, 1)
+
+
+def _schedule(info):
+    keys = ("algo", "entries_per_lane", "sync", "rows_per_lane", "grid", "assign", "poll",
+            "xp_stride")
+    return {k: info[k] for k in keys}
+
+
+def _finish(res, lb, hop_ns, hops, setup_self_ms=None, setup_level_host_ms=None,
+            setup_host_ms=None):
+    res["lb_bytes"] = lb
+    res["gbs_self"] = round(lb / (res["self_ms"] * 1e-3) / 1e9, 3)
+    res["gbs_level"] = round(lb / (res["level_ms"] * 1e-3) / 1e9, 3)
+    res["frac_hbm_self"] = round(res["gbs_self"] / 8000.0, 5)
+    if res.get("self_kernel_ms"):
+        res["frac_hbm_self_kernel"] = round(lb / (res["self_kernel_ms"] * 1e-3) / 1e9 / 8000.0, 5)
+    res["speedup_self_vs_level"] = round(res["level_ms"] / res["self_ms"], 3)
+    bound = hops * hop_ns * 1e-6
+    res["critical_path"] = {"hops": hops, "hop_ns": round(hop_ns, 1),
+                            "bound_ms": round(bound, 5),
+                            "self_over_bound": round(res["self_ms"] / bound, 3)}
+    if setup_self_ms is not None:
+        res["setup"] = {"self_device_route_ms": round(setup_self_ms, 2)}
+        if setup_level_host_ms is not None:
+            res["setup"]["level_host_route_ms"] = round(setup_level_host_ms, 2)
+            res["setup"]["n_s_self_device_vs_level_host"] = break_even(
+                setup_self_ms, res["self_ms"], setup_level_host_ms, res["level_ms"])
+        if setup_host_ms is not None:
+            res["setup"]["self_host_route_ms"] = round(setup_host_ms, 2)
+            res["setup"]["n_s_device_vs_host_route"] = break_even(
+                setup_self_ms, res["self_ms"], setup_host_ms, res["self_ms"])
+    errs = [v for k, v in res.items() if k.startswith("rel_err")]
+    tol = res.pop("_tol")
+    res["parity"] = "ok" if errs and max(errs) <= tol else "FAIL"
+    return res
+
+
+def _timed_handle(torch, make):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h = make()
+    torch.cuda.synchronize()
+    return h, (time.perf_counter() - t0) * 1e3
+
+
+def pc_single(sp, torch, T, b, steps, warmup, hop_ns, dtype=None, tol=1e-12, block=False):
+    """One triangle, one right-hand side: self (tuned) vs level (tuned)."""
+    dtype = dtype or torch.float64
+    o = oracle.get()
+    vals64 = T.vals if dtype == torch.float64 else T.vals.astype(np.float32).astype(np.float64)
+    b64 = b if dtype == torch.float64 else b.astype(np.float32).astype(np.float64)
+    xo = o.solve(T.row_ptr, T.col_idx, vals64, b64, T.upper)
+    d = _tri(torch, T, dtype)
+    bd = torch.from_numpy(b).to(DEV).to(dtype)
+    x = torch.empty_like(bd)
+    uplo = "U" if T.upper else "L"
+    res = {"n": T.n, "nnz": T.nnz, "dtype": "f64" if dtype == torch.float64 else "f32",
+           "_tol": tol}
+    hs, setup_dev = _timed_handle(torch, lambda: sp.Handle(*d, uplo=uplo, setup="device"))
+    hh, setup_host = _timed_handle(torch, lambda: sp.Handle(*d, uplo=uplo, setup="host"))
+    hh.close()
+    hl = sp.Handle(*d, uplo=uplo).configure(algo=sp.ALGO_LEVEL)
+    res["nlev"] = hs.info()["nlev"]
+    hs.set_option("algo", sp.ALGO_SELF)
+    t0 = time.perf_counter()
+    hs.tune(bd, x)
+    res["tune_ms"] = round((time.perf_counter() - t0) * 1e3, 1)
+    hl.tune(bd, x)
+    res["schedule_self"] = _schedule(hs.info())
+    hands = [("self", hs), ("level", hl)]
+    if block:
+        hands.append(("block", sp.Handle(*d, uplo=uplo).configure(algo=sp.ALGO_BLOCK)))
+    for tag, h in hands:
+        h.solve(bd, out=x)
+        h.status()
+        res["rel_err_" + tag] = float("%.3e" % _relerr(x.cpu().numpy(), xo))
+        res[tag + "_ms"] = round(_time(torch, lambda: h.solve(bd, out=x), steps, warmup), 5)
+    res["self_kernel_ms"] = round(_kernel_ms(torch, hs, lambda: hs.solve(bd, out=x), steps), 5)
+    for _, h in hands:
+        h.close()
+    vb = 8 if dtype == torch.float64 else 4
+    return _finish(res, lb_bytes(T.n, T.nnz, vb), hop_ns, res["nlev"], setup_dev, setup_host,
+                   setup_host)
+
+
+def pc_batched(sp, torch, steps, warmup, hop_ns):
+    o = oracle.get()
+    tris, xs, bs = W.c4a_batch()
+    devs = [_tri(torch, t) for t in tris]
+    bd = torch.from_numpy(np.concatenate(bs)).to(DEV)
+    x = torch.empty_like(bd)
+    n = sum(t.n for t in tris)
+    nnz = sum(t.nnz for t in tris)
+    res = {"n": n, "nnz": nnz, "systems": len(tris), "dtype": "f64", "_tol": 1e-12}
+    parts = ([dv[0] for dv in devs], [dv[1] for dv in devs], [dv[2] for dv in devs])
+    hs, setup_ms = _timed_handle(torch, lambda: sp.BatchedHandle(*parts))
+    hl = sp.BatchedHandle(*parts).configure(algo=sp.ALGO_LEVEL)
+    hb = sp.BatchedHandle(*parts).configure(algo=sp.ALGO_BLOCK)
+    res["nlev"] = hs.info()["nlev"]
+    hs.set_option("algo", sp.ALGO_SELF)
+    hs.tune(bd, x)
+    hl.tune(bd, x)
+    res["schedule_self"] = _schedule(hs.info())
+    xo = np.concatenate([o.solve(t.row_ptr, t.col_idx, t.vals, b) for t, b in zip(tris, bs)])
+    for tag, h in (("self", hs), ("level", hl), ("block", hb)):
+        h.solve(bd, out=x)
+        h.status()
+        res["rel_err_" + tag] = float("%.3e" % _relerr(x.cpu().numpy(), xo))
+        res[tag + "_ms"] = round(_time(torch, lambda: h.solve(bd, out=x), steps, warmup), 5)
+    res["self_kernel_ms"] = round(_kernel_ms(torch, hs, lambda: hs.solve(bd, out=x), steps), 5)
+    # the whole batch from one HIP graph, replayed
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        g = hs.capture(bd, x, stream=s)
+        g.launch(s)
+        s.synchronize()
+        res["rel_err_graph_self"] = float("%.3e" % _relerr(x.cpu().numpy(), xo))
+        res["graph_self_ms"] = round(_time(torch, lambda: g.launch(s), steps, warmup), 5)
+        g.close()
+    for h in (hs, hl, hb):
+        h.close()
+    return _finish(res, lb_bytes(n, nnz), hop_ns, res["nlev"], setup_ms)
+
+
+def pc_multi(sp, torch, steps, warmup, hop_ns, nrhs=16):
+    o = oracle.get()
+    T, X, B = W.c4b_multi(nrhs=nrhs)
+    d = _tri(torch, T)
+    Bd = torch.from_numpy(np.ascontiguousarray(B.T)).to(DEV)        # (nrhs, n): column-major
+    Xd = torch.empty_like(Bd)
+    res = {"n": T.n, "nnz": T.nnz, "nrhs": nrhs, "dtype": "f64", "_tol": 1e-12}
+    hs, setup_ms = _timed_handle(torch, lambda: sp.Handle(*d, setup="device"))
+    hs.set_option("algo", sp.ALGO_SELF)
+    hl = sp.Handle(*d).configure(algo=sp.ALGO_LEVEL)
+    res["nlev"] = hs.info()["nlev"]
+    Xo = o.solve_multi(T.row_ptr, T.col_idx, T.vals, B)
+    hs.tune_multi(Bd)
+    for tag, h in (("self", hs), ("level", hl)):
+        h.solve_multi(Bd, out=Xd)
+        h.status()
+        res["rel_err_" + tag] = float("%.3e" % _relerr(Xd.cpu().numpy().T, Xo))
+        res[tag + "_ms"] = round(_time(torch, lambda: h.solve_multi(Bd, out=Xd), steps, warmup), 5)
+    res["self_kernel_ms"] = round(
+        _kernel_ms(torch, hs, lambda: hs.solve_multi(Bd, out=Xd), steps), 5)
+    res["rhs_solves_per_s_self"] = round(nrhs * 1e3 / res["self_ms"], 2)
+    for h in (hs, hl):
+        h.close()
+    return _finish(res, lb_bytes(T.n, T.nnz, 8, nrhs), hop_ns, res["nlev"], setup_ms)
+
+
+def pc_adjoint(sp, torch, steps, warmup, hop_ns, side=96):
+    """Forward solve plus adjoint (transposed solve and gradient on the
+    pattern) through torch.autograd, self vs level."""
+    o = oracle.get()
+    T, b, w = W.c5_ilu3d(side=side)
+    d = _tri(torch, T)
+    res = {"n": T.n, "nnz": T.nnz, "dtype": "f64", "_tol": 1e-12}
+    xo, gbo, gvo = o.adjoint(T.row_ptr, T.col_idx, T.vals, b, w)
+    wd = torch.from_numpy(w).to(DEV)
+    bd0 = torch.from_numpy(b).to(DEV)
+    setup_ms = None
+    for tag, algo in (("self", sp.ALGO_SELF), ("level", sp.ALGO_LEVEL)):
+        def make():
+            h = sp.Handle(*d, setup="device").configure(algo=algo)
+            h.prepare_transpose()
+            return h
+        h, ms = _timed_handle(torch, make)
+        if tag == "self":
+            setup_ms = ms
+        res["nlev"] = h.info()["nlev"]
+        vals = d[2].clone().requires_grad_(True)
+        bd = bd0.clone().requires_grad_(True)
+
+        def step():
+            vals.grad = None
+            bd.grad = None
+            x = sp.sptrsv(vals, bd, h)
+            x.backward(wd)
+            return x
+
+        x = step()
+        h.status()
+        err = max(_relerr(x.detach().cpu().numpy(), xo), _relerr(bd.grad.cpu().numpy(), gbo),
+                  _relerr(vals.grad.cpu().numpy(), gvo))
+        res["rel_err_" + tag] = float("%.3e" % err)
+        res[tag + "_ms"] = round(_time(torch, step, steps, warmup), 5)
+        h.close()
+    lb_solve = lb_bytes(T.n, T.nnz)
+    gather = T.nnz * 8 * 2 + T.nnz * 4
+    grad = (T.n + 1) * 4 + T.nnz * 4 + T.n * 8 * 2 + T.nnz * 8
+    return _finish(res, 2 * lb_solve + gather + grad, hop_ns, 2 * res["nlev"], setup_ms)
+
+
+def per_config(sp, torch, steps, warmup, hop_ns):
+    """{config name: record} for C1, C3 (FP64, FP32), C4a, C4b and C5."""
+    out = {}
+    T, _, b = W.c1_lap2d_64()
+    _log("per-config: c1")
+    out["c1_lap2d_64_lower"] = pc_single(sp, torch, T, b, steps, warmup, hop_ns, block=True)
+    T, _, b = W.c3_powerlaw()
+    _log("per-config: c3 f64")
+    out["c3_powerlaw_1M_f64"] = pc_single(sp, torch, T, b, steps, warmup, hop_ns)
+    _log("per-config: c3 f32")
+    out["c3_powerlaw_1M_f32"] = pc_single(sp, torch, T, b, steps, warmup, hop_ns,
+                                          dtype=torch.float32, tol=1e-5)
+    _log("per-config: c4a")
+    out["c4a_batched_256_ilu0_2d"] = pc_batched(sp, torch, steps, warmup, hop_ns)
+    _log("per-config: c4b")
+    out["c4b_lap3d_128_lower_16rhs"] = pc_multi(sp, torch, steps, warmup, hop_ns)
+    _log("per-config: c5")
+    out["c5_ilu0_3d_96_fwd_adjoint"] = pc_adjoint(sp, torch, steps, warmup, hop_ns)
+    return out
