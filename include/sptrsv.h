@@ -135,7 +135,7 @@ typedef enum {
                                      round at a time over the pending slots only (less
                                      polling traffic, better when most dependencies are
                                      already available) */
-    SPTRSV_OPT_XP_STRIDE = 11     /* 1 (default), 2, 4, 8 or 16: elements between consecutive
+    SPTRSV_OPT_XP_STRIDE = 11,    /* 1 (default), 2, 4, 8 or 16: elements between consecutive
                                      values of the position-ordered solution the
                                      self-scheduled static schedules (one right-hand side)
                                      publish and poll.  Wider slots put fewer values on a
@@ -143,6 +143,12 @@ typedef enum {
                                      where dependencies are scattered, slower where polls
                                      coalesce.  The autotuner tries packed values and 32- and
                                      64-byte slots.  Ignored by the other schedules */
+    SPTRSV_OPT_MULTI_ROWS = 12    /* several right-hand sides, static schedules: rows each
+                                     group of a row's lanes owns in a chunk (1, 2 or 4; 0 =
+                                     default: 4 when a row takes 8 or more lanes, 2 at 4
+                                     lanes, else 1).  A wavefront issues the gathers of all
+                                     its rows before it waits on any, so larger values mean
+                                     fewer waits per level.  Results do not depend on it */
 } sptrsv_option;
 
 typedef enum {

@@ -28,7 +28,7 @@ ALGO_AUTO, ALGO_LEVEL, ALGO_SELF, ALGO_BLOCK, ALGO_COLUMN_LEVEL, ALGO_COLUMN_SEL
 SYNC_VALUE, SYNC_FLAG = 0, 1
 OPT = {"algo": 0, "group": 1, "entries_per_lane": 2, "sync": 3, "spin_limit": 4,
        "grid": 5, "timing": 6, "wg": 7, "rows_per_lane": 8, "assign": 9, "poll": 10,
-       "xp_stride": 11}
+       "xp_stride": 11, "multi_rows": 12}
 ASSIGN_STATIC, ASSIGN_TICKET, ASSIGN_XCD = 0, 1, 2
 SETUP = {"host": 0, "device": 1}
 
@@ -201,10 +201,11 @@ class _Base:
             check(lib.sptrsv_destroy(self._h))
             self._h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # no HIP calls while the interpreter shuts down (the runtime, or a
-        # profiler wrapped around it, may already be tearing down)
-        if sys.is_finalizing():
+        # profiler wrapped around it, may already be tearing down; module
+        # globals such as `sys` may already be gone)
+        if _finalizing():
             return
         try:
             self.close()
@@ -231,8 +232,8 @@ class Graph:
             self._g = None
             self._keep = None
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
             return
         try:
             self.close()

@@ -231,7 +231,10 @@ void build_chunks(const HostPlan& p, int group, int entries_per_lane, int rows_f
       int lg;
       if (rows_fixed > 0 || group > 0) lg = fixed_lg;
       else lg = lanes_for(p.off_ptr[k + 1] - p.off_ptr[k]);
-      const int cap = (lg == 0 && rows_fixed <= 0) ? 64 * rows_per_lane : 64 >> lg;
+      // rows_fixed: rows_per_lane rows in each of the 64 >> lg lane groups
+      const int cap = rows_fixed > 0 ? (64 >> lg) * rows_per_lane
+                      : lg == 0      ? 64 * rows_per_lane
+                                     : 64 >> lg;
       int cnt = 1;
       while (cnt < cap && k + cnt < end) {
         if (rows_fixed <= 0 && group <= 0) {

@@ -99,9 +99,11 @@ struct ChunkTable {
 
 // group > 0: every row gets G = group lanes (a power of two <= 64).
 // group == 0: G = smallest power of two with ceil(len / G) <= entries_per_lane.
-// rows_fixed > 0 overrides both: count <= rows_fixed and G = 64 / rows_fixed
-// (multi-RHS kernels, where lanes split right-hand sides, not entries).
-// rows_per_lane (1..kMaxRowsPerLane) caps the rows a G = 1 lane owns.
+// rows_fixed > 0 overrides both: G = 64 / rows_fixed lanes per row and
+// count <= rows_fixed * rows_per_lane (multi-RHS kernels, where the lanes of
+// a row split right-hand sides, not entries, and each lane group may own
+// rows_per_lane rows).  Otherwise rows_per_lane (1..kMaxRowsPerLane) caps the
+// rows a G = 1 lane owns.
 void build_chunks(const HostPlan& plan, int group, int entries_per_lane, int rows_fixed,
                   int rows_per_lane, ChunkTable& out);
 

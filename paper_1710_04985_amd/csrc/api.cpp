@@ -79,6 +79,8 @@ struct Config {
   int assign; // sptrsv_assign
   int poll = 1;  // waits: 1 overlapped rounds over all slots, 0 single rounds of pending ones
   int stride = 1;  // static schedules, one right-hand side: elements between xp values
+  int mrows = 0;   // static schedule, several right-hand sides: rows per lane group
+                   // (1, 2, 4; 0 = by the number of right-hand sides)
 };
 
 std::mutex g_tune_mu;
@@ -140,6 +142,8 @@ struct sptrsv_handle_s {
   void* xp = nullptr;             // xp_buf->p
   int64_t xp_elems = 0;
   int live_graphs = 0;            // graphs captured from this handle, not yet destroyed
+  void* bp = nullptr;             // several right-hand sides in position order
+  int64_t bp_elems = 0;
   // batched handles keep the concatenated pattern and values on the device
   bool batched = false;
   std::vector<int> sys_n, sys_nnz;
@@ -159,6 +163,7 @@ struct sptrsv_handle_s {
   int assign = SPTRSV_ASSIGN_STATIC;
   int poll = 1;
   int xp_stride = 1;
+  int mrows = 0;
   // autotuner result
   bool tuned = false;
   Config tuned_cfg{SPTRSV_ALGO_SELF, 0, 4, SPTRSV_SYNC_VALUE, 1, 0, SPTRSV_ASSIGN_STATIC};
@@ -271,6 +276,7 @@ void free_plan(PlanState& ps) {
   dfree(ps.d.off_src);
   dfree(ps.d.diag_src);
   dfree(ps.d.pos_row);
+  dfree(ps.d.row_pos);
   dfree(ps.vals_buf);
   free_push(ps.push);
   ps.d = DevPlan();
@@ -501,6 +507,7 @@ Config resolve(sptrsv_handle_t h) {
   Config c{h->algo, h->group, h->epl, h->sync, h->rpl, h->grid, h->assign};
   c.poll = h->poll;
   c.stride = h->xp_stride;
+  c.mrows = h->mrows;
   if (c.algo == SPTRSV_ALGO_AUTO) c.algo = SPTRSV_ALGO_SELF;
   return c;
 }
@@ -538,9 +545,31 @@ int ensure_xp(sptrsv_handle_t h, int64_t elems) {
   return kOk;
 }
 
+// Several right-hand sides: the position-ordered copy of B (grown like the
+// solution buffer) and the plan's inverse permutation (built once).
+int ensure_multi(sptrsv_handle_t h, PlanState& ps, int64_t elems, hipStream_t s) {
+  if (h->bp_elems < elems) {
+    if (h->bp && h->order_ev && h->order_pending) HIPCHK(hipEventSynchronize(h->order_ev));
+    dfree(h->bp);
+    h->bp = nullptr;
+    h->bp_elems = 0;
+    if (hipMalloc(&h->bp, static_cast<size_t>(elems > 0 ? elems : 1) * h->vb) != hipSuccess)
+      return kErrOom;
+    h->bp_elems = elems;
+  }
+  if (!ps.d.row_pos) {
+    int err = kOk;
+    ps.d.row_pos = dalloc<int>(static_cast<size_t>(h->n), &err);
+    if (!ps.d.row_pos) return err;
+    HIPCHK(launch_row_pos(h->n, ps.d.pos_row, ps.d.row_pos, s));
+  }
+  return kOk;
+}
+
 // Resident workgroups per CU of persistent kernel `kind` (0 value sync, 1 flag
-// sync, 3 static value sync, 4 column-wise); queried once per (kind, wg) and
-// cached, so that solves under graph capture make no occupancy query.
+// sync, 3 static value sync, 4 column-wise, 5 + log2(rows per lane group):
+// static value sync with several right-hand sides); queried once per (kind,
+// wg) and cached, so that solves under graph capture make no occupancy query.
 int blocks_per_cu(sptrsv_handle_t h, int kind) {
   const auto key = std::make_pair(kind, h->wg);
   auto it = h->occupancy.find(key);
@@ -550,6 +579,7 @@ int blocks_per_cu(sptrsv_handle_t h, int kind) {
   if (kind == 0) per_cu = dbl ? self_value_blocks_per_cu<double>(h->wg) : self_value_blocks_per_cu<float>(h->wg);
   else if (kind == 1) per_cu = dbl ? self_flag_blocks_per_cu<double>(h->wg) : self_flag_blocks_per_cu<float>(h->wg);
   else if (kind == 3) per_cu = dbl ? self_static_blocks_per_cu<double>(h->wg) : self_static_blocks_per_cu<float>(h->wg);
+  else if (kind >= 5) per_cu = dbl ? self_multi_blocks_per_cu<double>(h->wg, 1 << (kind - 5)) : self_multi_blocks_per_cu<float>(h->wg, 1 << (kind - 5));
   else per_cu = dbl ? column_self_blocks_per_cu<double>(h->wg) : column_self_blocks_per_cu<float>(h->wg);
   h->occupancy[key] = per_cu;
   return per_cu;
@@ -609,20 +639,27 @@ void timing_end(hipStream_t s, hipEvent_t stop) {
   if (stop) (void)hipEventRecord(stop, s);
 }
 
+// Occupancy kind of the static schedule: 3 with one right-hand side (mrows
+// 0), 5, 6, 7 for the multi-RHS kernel with 1, 2, 4 rows per lane group.
+int multi_kind(int mrows) { return mrows <= 0 ? 3 : mrows >= 4 ? 7 : mrows == 2 ? 6 : 5; }
+
 // Wave-list key of the static schedule: (wavefronts, regions).
-std::pair<int, int> static_key(sptrsv_handle_t h, const ChunkEntry& ch, const Config& c) {
-  const int grid = persistent_grid(h, 3, c.grid, ch.d.count);
+std::pair<int, int> static_key(sptrsv_handle_t h, const ChunkEntry& ch, const Config& c,
+                               int mrows = 0) {
+  const int grid = persistent_grid(h, multi_kind(mrows), c.grid, ch.d.count);
   const int W = grid * (h->wg / 64);
   const int regions = (c.assign == SPTRSV_ASSIGN_XCD && W % 8 == 0) ? 8 : 1;
   return {W, regions};
 }
 
-bool static_lists_ready(sptrsv_handle_t h, const ChunkEntry& ch, const Config& c) {
-  return ch.waves.count(static_key(h, ch, c)) != 0;
+bool static_lists_ready(sptrsv_handle_t h, const ChunkEntry& ch, const Config& c,
+                        int mrows = 0) {
+  return ch.waves.count(static_key(h, ch, c, mrows)) != 0;
 }
 
-const WaveLists* static_lists(sptrsv_handle_t h, ChunkEntry& ch, const Config& c, int* err) {
-  const auto key = static_key(h, ch, c);
+const WaveLists* static_lists(sptrsv_handle_t h, ChunkEntry& ch, const Config& c, int* err,
+                              int mrows = 0) {
+  const auto key = static_key(h, ch, c, mrows);
   return get_wave_lists(ch, key.first, key.second, err);
 }
 
@@ -676,6 +713,14 @@ int regather_push(sptrsv_handle_t h, hipStream_t s) {
     if (e != hipSuccess) return kErrHip;
   }
   return kOk;
+}
+
+// Rows per lane group of the static multi-RHS kernel: the configured value,
+// else 4 when a row takes 8 or more lanes (chunks of 32 or fewer rows), 2 at
+// 4 lanes, 1 below (chunks already 32 or 64 rows).
+int multi_rows(const Config& c, int lanes_per_row) {
+  if (c.mrows == 1 || c.mrows == 2 || c.mrows == 4) return c.mrows;
+  return lanes_per_row >= 8 ? 4 : lanes_per_row == 4 ? 2 : 1;
 }
 
 // Column-wise solve, one right-hand side: LEVC (a launch per level) or SLFC
@@ -749,17 +794,21 @@ int solve_impl(sptrsv_handle_t h, PlanState& ps, const Config& c_in, const void*
   const bool capturing = cap != hipStreamCaptureStatusNone;
   bool use_static = c.algo == SPTRSV_ALGO_SELF && (multi || c.sync == SPTRSV_SYNC_VALUE) &&
                     (c.assign == SPTRSV_ASSIGN_STATIC || c.assign == SPTRSV_ASSIGN_XCD);
-  ChunkEntry* ch = multi ? get_chunks(h, ps, 0, 0, 64 / kl, 1, &err, ext.no_alloc)
+  // several right-hand sides, static: each lane group owns mrows rows
+  const int mrows = multi && use_static ? multi_rows(c, kl) : 1;
+  ChunkEntry* ch = multi ? get_chunks(h, ps, 0, 0, 64 / kl, mrows, &err, ext.no_alloc)
                          : get_chunks(h, ps, c.group, c.epl, 0, use_static ? 1 : c.rpl, &err,
                                       ext.no_alloc);
   if (!ch) return err;
   // under capture (or without allocation) the per-wavefront lists cannot be
   // uploaded: the static form is used only when they exist
   // (sptrsv_graph_capture and the analysis build them), else the ticket form
-  if (use_static && (capturing || ext.no_alloc) && !static_lists_ready(h, *ch, c)) {
+  if (use_static && (capturing || ext.no_alloc) &&
+      !static_lists_ready(h, *ch, c, multi ? mrows : 0)) {
     use_static = false;
-    if (!multi && c.rpl != 1 &&
-        !(ch = get_chunks(h, ps, c.group, c.epl, 0, c.rpl, &err, ext.no_alloc)))
+    if (multi ? mrows != 1 && !(ch = get_chunks(h, ps, 0, 0, 64 / kl, 1, &err, ext.no_alloc))
+              : c.rpl != 1 &&
+                    !(ch = get_chunks(h, ps, c.group, c.epl, 0, c.rpl, &err, ext.no_alloc)))
       return err;
   }
   // the static schedules with one right-hand side may space the values out
@@ -772,6 +821,10 @@ int solve_impl(sptrsv_handle_t h, PlanState& ps, const Config& c_in, const void*
     if ((err = ensure_xp(h, xp_need))) return err;
     xp = h->xp;
   }
+  if (multi) {
+    if (ext.no_alloc) return kErrNotSupported;
+    if ((err = ensure_multi(h, ps, xp_need, s))) return err;
+  }
   SolveArgs a;
   a.plan = &ps.d;
   a.chunks = &ch->d;
@@ -779,11 +832,13 @@ int solve_impl(sptrsv_handle_t h, PlanState& ps, const Config& c_in, const void*
   a.b = b;
   a.x = x;
   a.xp = xp;
+  a.bp = multi ? h->bp : nullptr;
   a.nrhs = nrhs;
   a.ld = ld;
   a.spin_limit = h->spin_limit;
   a.poll = c.poll;
   a.xp_stride = stride;
+  a.mrows = use_static ? mrows : 1;
   a.wg = h->wg;
   hipEvent_t stop;
   if (c.algo == SPTRSV_ALGO_BLOCK && !multi) {
@@ -803,7 +858,20 @@ int solve_impl(sptrsv_handle_t h, PlanState& ps, const Config& c_in, const void*
     timing_end(s, stop);
     return kOk;
   }
-  if (c.algo == SPTRSV_ALGO_LEVEL || c.algo == SPTRSV_ALGO_BLOCK) {
+  // several right-hand sides: B into position order (and xp filled with the
+  // readiness sentinel for the value-synchronised solves), X out afterwards
+  const bool level = c.algo == SPTRSV_ALGO_LEVEL || c.algo == SPTRSV_ALGO_BLOCK;
+  if (multi && launch_multi_in<T>(n, nrhs, ld, static_cast<const T*>(b), ps.d.row_pos,
+                                  static_cast<T*>(h->bp), static_cast<T*>(xp), !level,
+                                  s) != hipSuccess)
+    return kErrHip;
+  auto multi_out = [&]() {
+    return !multi || launch_multi_out<T>(n, nrhs, ld, static_cast<const T*>(xp), ps.d.row_pos,
+                                         static_cast<T*>(x), s) == hipSuccess
+               ? kOk
+               : kErrHip;
+  };
+  if (level) {
     timing_begin(h, s, &stop, ext.no_alloc);
     for (int m = 0; m < ps.h.nlev; ++m) {
       const int cb = ch->level_chunk[m], ce = ch->level_chunk[m + 1];
@@ -811,7 +879,7 @@ int solve_impl(sptrsv_handle_t h, PlanState& ps, const Config& c_in, const void*
       if (e != hipSuccess) return kErrHip;
     }
     timing_end(s, stop);
-    return kOk;
+    return multi_out();
   }
   if (c.algo != SPTRSV_ALGO_SELF) return kErrNotSupported;
   if (c.sync == SPTRSV_SYNC_FLAG && !multi) {
@@ -823,11 +891,12 @@ int solve_impl(sptrsv_handle_t h, PlanState& ps, const Config& c_in, const void*
   }
   // value sync: xp starts as the sentinel (b == x needs no copy: a row reads
   // its own b before any write of its own x, and x is only written)
-  if (launch_fill_sentinel<T>(static_cast<T*>(xp), xp_need, s) != hipSuccess)
+  if (!multi && launch_fill_sentinel<T>(static_cast<T*>(xp), xp_need, s) != hipSuccess)
     return kErrHip;
-  a.grid = persistent_grid(h, use_static ? 3 : 0, c.grid, ch->d.count);
+  a.grid = persistent_grid(h, use_static ? multi_kind(multi ? mrows : 0) : 0, c.grid,
+                           ch->d.count);
   if (use_static) {
-    const WaveLists* wl = static_lists(h, *ch, c, &err);
+    const WaveLists* wl = static_lists(h, *ch, c, &err, multi ? mrows : 0);
     if (!wl) return err;
     a.wave_ptr = wl->ptr;
     a.wave_list = wl->list;
@@ -836,7 +905,7 @@ int solve_impl(sptrsv_handle_t h, PlanState& ps, const Config& c_in, const void*
   const hipError_t e = use_static ? launch_self_static<T>(a, s) : launch_self_value<T>(a, s);
   if (e != hipSuccess) return kErrHip;
   timing_end(s, stop);
-  return kOk;
+  return multi_out();
 }
 
 // Work on a handle's buffers (its position-ordered solution, flags,
@@ -1049,6 +1118,7 @@ void destroy_handle(sptrsv_handle_t h) {
   dfree(h->scratch.flags);
   h->xp_buf.reset();
   h->xp = nullptr;
+  dfree(h->bp);
   dfree(h->rp_cat);
   dfree(h->col_cat);
   dfree(h->vals_cat);
@@ -1323,7 +1393,8 @@ int sptrsv_set_option(sptrsv_handle_t h, sptrsv_option key, int64_t v) {
   if (!h) return kErrInvalidArg;
   if (key == SPTRSV_OPT_ALGO || key == SPTRSV_OPT_GROUP || key == SPTRSV_OPT_ENTRIES_PER_LANE ||
       key == SPTRSV_OPT_SYNC || key == SPTRSV_OPT_ROWS_PER_LANE || key == SPTRSV_OPT_GRID ||
-      key == SPTRSV_OPT_ASSIGN || key == SPTRSV_OPT_POLL || key == SPTRSV_OPT_XP_STRIDE) {
+      key == SPTRSV_OPT_ASSIGN || key == SPTRSV_OPT_POLL || key == SPTRSV_OPT_XP_STRIDE ||
+      key == SPTRSV_OPT_MULTI_ROWS) {
     h->tuned = false;   // an explicit schedule option overrides the tuner's choice
     h->tuned_multi.clear();
   }
@@ -1378,6 +1449,10 @@ int sptrsv_set_option(sptrsv_handle_t h, sptrsv_option key, int64_t v) {
       if (v != 1 && v != 2 && v != 4 && v != 8 && v != 16) return kErrInvalidArg;
       h->xp_stride = static_cast<int>(v);
       return kOk;
+    case SPTRSV_OPT_MULTI_ROWS:
+      if (v != 0 && v != 1 && v != 2 && v != 4) return kErrInvalidArg;
+      h->mrows = static_cast<int>(v);
+      return kOk;
   }
   return kErrInvalidArg;
 }
@@ -1397,6 +1472,7 @@ int sptrsv_get_option(sptrsv_handle_t h, sptrsv_option key, int64_t* v) {
     case SPTRSV_OPT_ASSIGN: *v = h->assign; return kOk;
     case SPTRSV_OPT_POLL: *v = h->poll; return kOk;
     case SPTRSV_OPT_XP_STRIDE: *v = h->xp_stride; return kOk;
+    case SPTRSV_OPT_MULTI_ROWS: *v = h->mrows; return kOk;
   }
   return kErrInvalidArg;
 }
@@ -1535,13 +1611,15 @@ int sptrsv_tune_multi(sptrsv_handle_t h, int32_t nrhs, int32_t ld, const void* B
   const bool self_ok = h->algo == SPTRSV_ALGO_AUTO || h->algo == SPTRSV_ALGO_SELF ||
                        is_column(h->algo);
   if (self_ok)
-    for (int grid : {ncu, 2 * ncu, 4 * ncu, 8 * ncu})
+    for (int grid : {ncu / 2, ncu, 2 * ncu, 4 * ncu, 8 * ncu})
       for (int as : {SPTRSV_ASSIGN_STATIC, SPTRSV_ASSIGN_XCD})
-        for (int poll : {1, 0}) {
-          Config c{SPTRSV_ALGO_SELF, 0, 4, SPTRSV_SYNC_VALUE, 1, grid, as};
-          c.poll = poll;
-          cand.push_back(c);
-        }
+        for (int poll : {1, 0})
+          for (int mrows : {1, 2, 4}) {
+            Config c{SPTRSV_ALGO_SELF, 0, 4, SPTRSV_SYNC_VALUE, 1, grid, as};
+            c.poll = poll;
+            c.mrows = mrows;
+            cand.push_back(c);
+          }
   if (h->algo == SPTRSV_ALGO_AUTO || h->algo == SPTRSV_ALGO_LEVEL || h->algo == SPTRSV_ALGO_BLOCK ||
       cand.empty())
     cand.push_back({SPTRSV_ALGO_LEVEL, 0, 4, SPTRSV_SYNC_VALUE, 1, 0, SPTRSV_ASSIGN_TICKET});

@@ -189,6 +189,7 @@ template <typename T> struct KArgs {
   const T* b;
   T* x;
   T* xp;
+  const T* bp;            // several right-hand sides: bp[k * nrhs + q], position order
   int ld;
   int nrhs;
   int* ticket;
@@ -347,10 +348,12 @@ __device__ __forceinline__ void solve_chunk(const KArgs<T>& a, int start, int me
   }
 }
 
-// Several right-hand sides: the 2^lg lanes of a row take columns q0 = lane %
-// 2^lg (+ multiples of 2^lg); each lane walks all entries of its row in order
-// for its column, so every column is solved as the one-lane-per-row single
-// solve.  The row's indices and values are fetched once for all columns.
+// Several right-hand sides, in position order (bp in, xp out; see
+// launch_multi_in / launch_multi_out): the 2^lg lanes of a row take columns
+// q0 = lane % 2^lg (+ multiples of 2^lg); each lane walks all entries of its
+// row in order for its column, so every column is solved as the
+// one-lane-per-row single solve.  The row's indices and values are fetched
+// once for all columns.
 template <typename T, bool kPoll>
 __device__ __forceinline__ void solve_chunk_multi(const KArgs<T>& a, int start, int meta,
                                                   int lane) {
@@ -358,16 +361,14 @@ __device__ __forceinline__ void solve_chunk_multi(const KArgs<T>& a, int start, 
   const int r = lane >> lg, q0 = lane & ((1 << lg) - 1);
   if (r >= cnt) return;
   const int k = start + r;
-  const int i = a.pos_row[k];
   const int e0 = a.off_ptr[k], e1 = a.off_ptr[k + 1];
   const T d = a.dinv[k];
   for (int q = q0; q < a.nrhs; q += (1 << lg)) {
-    const int64_t off = static_cast<int64_t>(q) * a.ld;
+    const int64_t kq = static_cast<int64_t>(k) * a.nrhs + q;
     const T sum = row_dot<T, kPoll>(a.off_pos, a.off_val, e0, e1, 1, a.xp + q, a.nrhs,
                                     a.spin_limit, a.status, a.poll != 0, T(0));
-    const T xi = canonical((a.b[off + i] - sum) * d);
-    publish<T, kPoll>(a.xp + static_cast<int64_t>(k) * a.nrhs + q, xi);
-    a.x[off + i] = xi;
+    const T xi = canonical((a.bp[kq] - sum) * d);
+    publish<T, kPoll>(a.xp + kq, xi);
   }
 }
 
@@ -421,9 +422,8 @@ __global__ void __launch_bounds__(256) k_self_value(KArgs<T> a) {
 // Each stage only stores raw loaded values; any arithmetic on them happens
 // one iteration later, so no wait for a load is needed before the next
 // stage's loads (and the x gathers) have been issued.  Loads whose result is
-// discarded use clamped in-range indices instead of branches.
-// kMulti: the lanes of a row take columns (as in solve_chunk_multi); columns
-// beyond the first 2^lg are finished by the same lanes, unpipelined.
+// discarded use clamped in-range indices instead of branches.  One
+// right-hand side (k_self_multi takes several).
 template <typename T> struct StageB {   // descriptor, raw
   int c, start, meta;
 };
@@ -438,7 +438,7 @@ template <typename T> struct StageD {   // first entries of the lane, raw
   T v[4];
 };
 
-template <typename T, bool kMulti, int kStride>
+template <typename T, int kStride>
 __global__ void __launch_bounds__(256)
 k_self_static(KArgs<T> a, const int* __restrict__ cstart, const int* __restrict__ cmeta,
               const int* __restrict__ wptr, const int* __restrict__ wlist) {
@@ -449,7 +449,7 @@ k_self_static(KArgs<T> a, const int* __restrict__ cstart, const int* __restrict_
   const int llast = a.nchunks - 1;    // clamp for the list load past the end
   const int nlast = a.n - 1;          // clamp for loads whose result is discarded
   const int64_t olast = a.noff > 0 ? a.noff - 1 : 0;
-  const int xs = kMulti ? a.nrhs : kStride;   // elements between xp values
+  const int xs = kStride;             // elements between xp values
   StageB<T> sb{-1, 0, 0};
   StageC<T> sc{-1, 0, -1, 0, 0, 0, T(1)};
   StageD<T> sd;
@@ -475,8 +475,7 @@ k_self_static(KArgs<T> a, const int* __restrict__ cstart, const int* __restrict_
       cur = wlist[t < te ? t : llast];
     }
     // ---- D (issue): gather x for the chunk whose entries arrived last time
-    const int qd = kMulti ? (lane & ((1 << sd.lg) - 1)) : 0;
-    const T* xq = a.xp + qd;
+    const T* xq = a.xp;
     T xv[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q)
@@ -486,8 +485,7 @@ k_self_static(KArgs<T> a, const int* __restrict__ cstart, const int* __restrict_
     {
       const int lg = sb.meta >> 16, cnt = sb.meta & 0xffff;
       const int r = lane >> lg;
-      bool live = sb.c >= 0 && r < cnt;
-      if (kMulti) live = live && (lane & ((1 << lg) - 1)) < a.nrhs;
+      const bool live = sb.c >= 0 && r < cnt;
       const int kk = live ? sb.start + r : nlast;
       nc.k = live ? kk : -1;
       nc.p0 = a.off_ptr[kk];
@@ -503,9 +501,9 @@ k_self_static(KArgs<T> a, const int* __restrict__ cstart, const int* __restrict_
     nd.i = sc.i;
     nd.d = sc.d;
     {
-      const int G = kMulti ? 1 : 1 << nd.lg;          // entry stride of the lane
-      const int gl = lane & ((1 << nd.lg) - 1);
-      nd.e = sc.p0 + (kMulti ? 0 : gl);
+      const int G = 1 << nd.lg;                       // entry stride of the lane
+      const int gl = lane & (G - 1);
+      nd.e = sc.p0 + gl;
       nd.e1 = sc.p1;
       const bool live = sc.c >= 0 && sc.k >= 0;
 #pragma unroll
@@ -518,13 +516,12 @@ k_self_static(KArgs<T> a, const int* __restrict__ cstart, const int* __restrict_
         nd.j[q] = ok ? jj : -1;
         nd.v[q] = ok ? vv : T(0);
       }
-      const int64_t boff = kMulti && live ? static_cast<int64_t>(gl) * a.ld : 0;
-      const T bb = a.b[boff + sc.i];
-      nd.bi = (live && (kMulti || gl == 0)) ? bb : T(0);
+      const T bb = a.b[sc.i];
+      nd.bi = (live && gl == 0) ? bb : T(0);
     }
     // ---- D (finish): wait, accumulate, rest of the row, group sum, publish
     if (sd.c >= 0) {
-      const int G = kMulti ? 1 : 1 << sd.lg;
+      const int G = 1 << sd.lg;
       T sum = T(0);
       if (sd.k >= 0) {
         wait_values<T, 4>(xq, xs, sd.j, xv, a.spin_limit, a.status, a.poll != 0);
@@ -537,28 +534,166 @@ k_self_static(KArgs<T> a, const int* __restrict__ cstart, const int* __restrict_
           sum = row_dot<T, true>(a.off_pos, a.off_val, sd.e + 4 * G, sd.e1, G, xq, xs,
                                  a.spin_limit, a.status, a.poll != 0, sum);
       }
-      if constexpr (kMulti) {
-        if (sd.k >= 0) {
-          const T xi = canonical((sd.bi - sum) * sd.d);
-          store_agent(a.xp + static_cast<int64_t>(sd.k) * xs + qd, xi);
-          a.x[static_cast<int64_t>(qd) * a.ld + sd.i] = xi;
-          // columns beyond the first 2^lg, same lane, unpipelined
-          const int KL = 1 << sd.lg;
-          for (int q = qd + KL; q < a.nrhs; q += KL) {
-            const int64_t off = static_cast<int64_t>(q) * a.ld;
-            const T s2 = row_dot<T, true>(a.off_pos, a.off_val, sd.e, sd.e1, 1, a.xp + q, xs,
-                                          a.spin_limit, a.status, a.poll != 0, T(0));
-            const T x2 = canonical((a.b[off + sd.i] - s2) * sd.d);
-            store_agent(a.xp + static_cast<int64_t>(sd.k) * xs + q, x2);
-            a.x[off + sd.i] = x2;
-          }
+      sum = group_sum(sum, sd.lg);
+      if (sd.k >= 0 && (lane & (G - 1)) == 0) {
+        const T xi = canonical((sd.bi - sum) * sd.d);
+        store_agent(a.xp + static_cast<int64_t>(sd.k) * xs, xi);
+        a.x[sd.i] = xi;
+      }
+    } else if (sc.c < 0 && sb.c < 0 && nb.c < 0) {
+      return;                         // pipeline drained
+    }
+    sd = nd;
+    sc = nc;
+    sb = nb;
+  }
+}
+
+// ------------------------- self, value sync, static pipeline, several RHS
+// The static schedule of k_self_static for several right-hand sides, in
+// position order: the right-hand sides come permuted into bp[k * nrhs + q]
+// and the solution stays in xp[k * nrhs + q] (launch_multi_in and
+// launch_multi_out move them from and to the caller's column-major B and X
+// with coalesced passes), so every access of a chunk is contiguous.  The 2^lg
+// lanes of a row take columns q = lane % 2^lg (2^lg >= nrhs, at most 64), so
+// a chunk has 64 >> lg lane groups, each owning R rows of it (rows g,
+// g + (64 >> lg), ...); a lane issues the x gathers of all R rows before it
+// waits on any.  Column q of a row walks all entries in stored order with
+// FMA, exactly as the one-lane single-RHS solve, so every column equals that
+// solve bit for bit.  Columns beyond the first 2^lg are finished by the same
+// lanes, unpipelined.  Same four stages as k_self_static (descriptor -> row
+// bounds -> first entries and b -> gather, wait, publish), one chunk apart.
+template <typename T, int R> struct MStageC {   // row bounds of R rows, raw
+  int c, meta;
+  int k[R], p0[R], p1[R];
+  T d[R];
+};
+template <typename T, int R> struct MStageD {   // first entries of R rows, raw
+  int c, lg;
+  int k[R], e[R], e1[R];
+  T d[R], bi[R];
+  int j[R][4];
+  T v[R][4];
+};
+
+template <typename T, int R>
+__global__ void __launch_bounds__(256)
+k_self_multi(KArgs<T> a, const int* __restrict__ cstart, const int* __restrict__ cmeta,
+             const int* __restrict__ wptr, const int* __restrict__ wlist) {
+  const int lane = threadIdx.x & 63;
+  const int w = wave_uniform(static_cast<int>((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+  const int tb = wptr[w], te = wptr[w + 1];
+  const int llast = a.nchunks - 1;
+  const int nlast = a.n - 1;
+  const int64_t olast = a.noff > 0 ? a.noff - 1 : 0;
+  const int xs = a.nrhs;
+  StageB<T> sb{-1, 0, 0};
+  MStageC<T, R> sc;
+  sc.c = -1;
+  sc.meta = 0;
+  MStageD<T, R> sd;
+  sd.c = -1;
+  sd.lg = 0;
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    sc.k[u] = -1;
+    sc.p0[u] = sc.p1[u] = 0;
+    sc.d[u] = T(1);
+    sd.k[u] = -1;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sd.j[u][q] = -1;
+  }
+  int t = tb;
+  int cur = wlist[tb < te ? tb : llast];
+  for (;;) {
+    // ---- A: descriptor of a new chunk
+    StageB<T> nb{-1, 0, 0};
+    {
+      const bool live = t < te;
+      const int cn = wave_uniform(cur);
+      nb.start = cstart[cn];
+      nb.meta = cmeta[cn];
+      if (live) {
+        nb.c = cn;
+        ++t;
+      }
+      cur = wlist[t < te ? t : llast];
+    }
+    // ---- D (issue): gather x of every row of the chunk whose entries arrived
+    const int qd = lane & ((1 << sd.lg) - 1);
+    const T* xq = a.xp + (qd < xs ? qd : 0);
+    T xv[R][4];
+#pragma unroll
+    for (int u = 0; u < R; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        xv[u][q] = load_agent(xq + static_cast<int64_t>(sd.j[u][q] >= 0 ? sd.j[u][q] : 0) * xs);
+    // ---- B: row bounds and diagonal of the R rows described last time
+    MStageC<T, R> nc;
+    nc.c = sb.c;
+    nc.meta = sb.meta;
+    {
+      const int lg = sb.meta >> 16, cnt = sb.meta & 0xffff;
+      const int g = lane >> lg, groups = 64 >> lg;
+      const bool col_ok = (lane & ((1 << lg) - 1)) < a.nrhs;
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        const int rr = g + groups * u;
+        const bool live = sb.c >= 0 && col_ok && rr < cnt;
+        const int kk = live ? sb.start + rr : nlast;
+        nc.k[u] = live ? kk : -1;
+        nc.p0[u] = a.off_ptr[kk];
+        nc.p1[u] = a.off_ptr[kk + 1];
+        nc.d[u] = a.dinv[kk];
+      }
+    }
+    // ---- C: first four entries and b of the R rows bounded last time
+    MStageD<T, R> nd;
+    nd.c = sc.c;
+    nd.lg = sc.meta >> 16;
+    {
+      const int gl = lane & ((1 << nd.lg) - 1);
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        nd.k[u] = sc.k[u];
+        nd.d[u] = sc.d[u];
+        nd.e[u] = sc.p0[u];
+        nd.e1[u] = sc.p1[u];
+        const bool live = sc.c >= 0 && sc.k[u] >= 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int ee = nd.e[u] + q;
+          const bool ok = live && ee < nd.e1[u];
+          const int64_t ec = ok ? ee : olast;
+          const int jj = a.off_pos[ec];
+          const T vv = a.off_val[ec];
+          nd.j[u][q] = ok ? jj : -1;
+          nd.v[u][q] = ok ? vv : T(0);
         }
-      } else {
-        sum = group_sum(sum, sd.lg);
-        if (sd.k >= 0 && (lane & (G - 1)) == 0) {
-          const T xi = canonical((sd.bi - sum) * sd.d);
-          store_agent(a.xp + static_cast<int64_t>(sd.k) * xs, xi);
-          a.x[sd.i] = xi;
+        const T bb = a.bp[live ? static_cast<int64_t>(sc.k[u]) * xs + gl : 0];
+        nd.bi[u] = live ? bb : T(0);
+      }
+    }
+    // ---- D (finish): per row, wait, accumulate, rest of the row, publish
+    if (sd.c >= 0) {
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        if (sd.k[u] < 0) continue;
+        wait_values<T, 4>(xq, xs, sd.j[u], xv[u], a.spin_limit, a.status, a.poll != 0);
+        T sum = T(0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (sd.j[u][q] >= 0) sum = fma_t(sd.v[u][q], xv[u][q], sum);
+        if (sd.e[u] + 4 < sd.e1[u])
+          sum = row_dot<T, true>(a.off_pos, a.off_val, sd.e[u] + 4, sd.e1[u], 1, xq, xs,
+                                 a.spin_limit, a.status, a.poll != 0, sum);
+        const int64_t kq = static_cast<int64_t>(sd.k[u]) * xs;
+        store_agent(a.xp + kq + qd, canonical((sd.bi[u] - sum) * sd.d[u]));
+        const int KL = 1 << sd.lg;
+        for (int q = qd + KL; q < a.nrhs; q += KL) {
+          const T s2 = row_dot<T, true>(a.off_pos, a.off_val, sd.e[u], sd.e1[u], 1, a.xp + q, xs,
+                                        a.spin_limit, a.status, a.poll != 0, T(0));
+          store_agent(a.xp + kq + q, canonical((a.bp[kq + q] - s2) * sd.d[u]));
         }
       }
     } else if (sc.c < 0 && sb.c < 0 && nb.c < 0) {
@@ -568,6 +703,70 @@ k_self_static(KArgs<T> a, const int* __restrict__ cstart, const int* __restrict_
     sc = nc;
     sb = nb;
   }
+}
+
+// ------------------------------- several right-hand sides: layout passes
+// The multi-RHS solves work in position order: bp[k * nrhs + q] and xp[k *
+// nrhs + q] for the row solved at position k (row_pos is the inverse of
+// pos_row).  The caller's B and X are column-major, where the rows of one
+// level are scattered (in natural order, consecutive rows sit in consecutive
+// levels), so reading B and writing X inside the solve would touch a
+// separate cache line per value.  These passes move a tile of 64
+// consecutive rows through LDS instead: down the columns of B / X (64 rows
+// contiguous per column) and along the rows of bp / xp (nrhs values
+// contiguous per row).
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_multi_in(int n, int nrhs, int ld, const T* __restrict__ B, const int* __restrict__ row_pos,
+           T* __restrict__ bp, T* __restrict__ xp, int fill) {
+  using U = typename Bits<T>::U;
+  __shared__ T tile[64][65];
+  const int i0 = blockIdx.x * 64, tid = threadIdx.x;
+  for (int q0 = 0; q0 < nrhs; q0 += 64) {
+    const int qc = nrhs - q0 < 64 ? nrhs - q0 : 64;
+    const int il = tid & 63;
+    if (i0 + il < n)
+      for (int qq = tid >> 6; qq < qc; qq += 4)
+        tile[il][qq] = B[static_cast<int64_t>(q0 + qq) * ld + i0 + il];
+    __syncthreads();
+    for (int e = tid; e < 64 * qc; e += 256) {
+      const int r = e / qc, qq = e - r * qc;
+      if (i0 + r < n) {
+        const int64_t o = static_cast<int64_t>(row_pos[i0 + r]) * nrhs + q0 + qq;
+        bp[o] = tile[r][qq];
+        if (fill) reinterpret_cast<U*>(xp)[o] = Bits<T>::kSentinel;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_multi_out(int n, int nrhs, int ld, const T* __restrict__ xp, const int* __restrict__ row_pos,
+            T* __restrict__ X) {
+  __shared__ T tile[64][65];
+  const int i0 = blockIdx.x * 64, tid = threadIdx.x;
+  for (int q0 = 0; q0 < nrhs; q0 += 64) {
+    const int qc = nrhs - q0 < 64 ? nrhs - q0 : 64;
+    for (int e = tid; e < 64 * qc; e += 256) {
+      const int r = e / qc, qq = e - r * qc;
+      if (i0 + r < n) tile[r][qq] = xp[static_cast<int64_t>(row_pos[i0 + r]) * nrhs + q0 + qq];
+    }
+    __syncthreads();
+    const int il = tid & 63;
+    if (i0 + il < n)
+      for (int qq = tid >> 6; qq < qc; qq += 4)
+        X[static_cast<int64_t>(q0 + qq) * ld + i0 + il] = tile[il][qq];
+    __syncthreads();
+  }
+}
+
+// row_pos[pos_row[k]] = k
+__global__ void __launch_bounds__(256) k_row_pos(int n, const int* __restrict__ pos_row,
+                                                 int* __restrict__ row_pos) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) row_pos[pos_row[k]] = k;
 }
 
 // ------------------------------------------- block: a workgroup per system
@@ -813,6 +1012,7 @@ template <typename T> KArgs<T> make_args(const SolveArgs& s) {
   a.b = static_cast<const T*>(s.b);
   a.x = static_cast<T*>(s.x);
   a.xp = static_cast<T*>(s.xp);
+  a.bp = static_cast<const T*>(s.bp);
   a.ld = s.ld;
   a.nrhs = s.nrhs;
   a.ticket = s.scratch.ticket;
@@ -855,6 +1055,28 @@ template <typename T> hipError_t launch_fill_sentinel(T* xp, int64_t count, hipS
 }
 
 template <typename T>
+hipError_t launch_multi_in(int n, int nrhs, int ld, const T* B, const int* row_pos, T* bp, T* xp,
+                           bool fill, hipStream_t s) {
+  if (n == 0 || nrhs == 0) return hipSuccess;
+  k_multi_in<T><<<(n + 63) / 64, 256, 0, s>>>(n, nrhs, ld, B, row_pos, bp, xp, fill ? 1 : 0);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_multi_out(int n, int nrhs, int ld, const T* xp, const int* row_pos, T* X,
+                            hipStream_t s) {
+  if (n == 0 || nrhs == 0) return hipSuccess;
+  k_multi_out<T><<<(n + 63) / 64, 256, 0, s>>>(n, nrhs, ld, xp, row_pos, X);
+  return hipGetLastError();
+}
+
+hipError_t launch_row_pos(int n, const int* pos_row, int* row_pos, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_row_pos<<<(n + 255) / 256, 256, 0, s>>>(n, pos_row, row_pos);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_level(const SolveArgs& sa, int cb, int ce, hipStream_t s) {
   if (ce <= cb) return hipSuccess;
   const int wpb = sa.wg / 64;
@@ -879,12 +1101,17 @@ template <typename T> hipError_t launch_self_static(const SolveArgs& sa, hipStre
   const int* wp = sa.wave_ptr;
   const int* wl = sa.wave_list;
   void* args[] = {&ka, &cs, &cm, &wp, &wl};
-  const void* fn = sa.nrhs > 1 ? reinterpret_cast<const void*>(k_self_static<T, true, 1>)
-                   : sa.xp_stride == 16 ? reinterpret_cast<const void*>(k_self_static<T, false, 16>)
-                   : sa.xp_stride == 8 ? reinterpret_cast<const void*>(k_self_static<T, false, 8>)
-                   : sa.xp_stride == 4 ? reinterpret_cast<const void*>(k_self_static<T, false, 4>)
-                   : sa.xp_stride == 2 ? reinterpret_cast<const void*>(k_self_static<T, false, 2>)
-                                       : reinterpret_cast<const void*>(k_self_static<T, false, 1>);
+  const void* fn;
+  if (sa.nrhs > 1)
+    fn = sa.mrows >= 4   ? reinterpret_cast<const void*>(k_self_multi<T, 4>)
+         : sa.mrows == 2 ? reinterpret_cast<const void*>(k_self_multi<T, 2>)
+                         : reinterpret_cast<const void*>(k_self_multi<T, 1>);
+  else
+    fn = sa.xp_stride == 16  ? reinterpret_cast<const void*>(k_self_static<T, 16>)
+         : sa.xp_stride == 8 ? reinterpret_cast<const void*>(k_self_static<T, 8>)
+         : sa.xp_stride == 4 ? reinterpret_cast<const void*>(k_self_static<T, 4>)
+         : sa.xp_stride == 2 ? reinterpret_cast<const void*>(k_self_static<T, 2>)
+                             : reinterpret_cast<const void*>(k_self_static<T, 1>);
   return hipLaunchCooperativeKernel(fn, dim3(sa.grid), dim3(sa.wg), args, 0, s);
 }
 
@@ -934,18 +1161,25 @@ template <typename T> int self_value_blocks_per_cu(int wg) {
 }
 template <typename T> int self_flag_blocks_per_cu(int wg) { return occupancy(k_self_flag<T>, wg); }
 template <typename T> int self_static_blocks_per_cu(int wg) {
-  const int a = occupancy(k_self_static<T, false, 1>, wg);
-  const int b = occupancy(k_self_static<T, true, 1>, wg);
-  const int c = occupancy(k_self_static<T, false, 2>, wg);
-  const int d = occupancy(k_self_static<T, false, 4>, wg);
-  const int e = occupancy(k_self_static<T, false, 8>, wg);
-  const int f = occupancy(k_self_static<T, false, 16>, wg);
-  return std::min(std::min(std::min(a, b), std::min(c, d)), std::min(e, f));
+  const int a = occupancy(k_self_static<T, 1>, wg);
+  const int c = occupancy(k_self_static<T, 2>, wg);
+  const int d = occupancy(k_self_static<T, 4>, wg);
+  const int e = occupancy(k_self_static<T, 8>, wg);
+  const int f = occupancy(k_self_static<T, 16>, wg);
+  return std::min(std::min(a, c), std::min(std::min(d, e), f));
+}
+template <typename T> int self_multi_blocks_per_cu(int wg, int rows) {
+  return rows >= 4   ? occupancy(k_self_multi<T, 4>, wg)
+         : rows == 2 ? occupancy(k_self_multi<T, 2>, wg)
+                     : occupancy(k_self_multi<T, 1>, wg);
 }
 
 #define SPTRSV_INSTANTIATE(T)                                                                    \
   template hipError_t launch_gather<T>(const DevPlan&, const T*, int*, hipStream_t);             \
   template hipError_t launch_fill_sentinel<T>(T*, int64_t, hipStream_t);                         \
+  template hipError_t launch_multi_in<T>(int, int, int, const T*, const int*, T*, T*, bool,       \
+                                         hipStream_t);                                           \
+  template hipError_t launch_multi_out<T>(int, int, int, const T*, const int*, T*, hipStream_t);  \
   template hipError_t launch_level<T>(const SolveArgs&, int, int, hipStream_t);                  \
   template hipError_t launch_self_value<T>(const SolveArgs&, hipStream_t);                       \
   template hipError_t launch_self_flag<T>(const SolveArgs&, hipStream_t);                        \
@@ -956,7 +1190,8 @@ template <typename T> int self_static_blocks_per_cu(int wg) {
                                           T*, hipStream_t);                                      \
   template int self_value_blocks_per_cu<T>(int);                                                 \
   template int self_flag_blocks_per_cu<T>(int);                                                  \
-  template int self_static_blocks_per_cu<T>(int);
+  template int self_static_blocks_per_cu<T>(int);                                                \
+  template int self_multi_blocks_per_cu<T>(int, int);
 
 SPTRSV_INSTANTIATE(double)
 SPTRSV_INSTANTIATE(float)

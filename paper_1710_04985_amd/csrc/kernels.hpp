@@ -18,6 +18,7 @@ struct DevPlan {
   int* off_src = nullptr;   // [noff]
   int* diag_src = nullptr;  // [n]
   int* pos_row = nullptr;   // [n]
+  int* row_pos = nullptr;   // [n] inverse of pos_row (built on first multi-RHS solve)
   void* off_val = nullptr;  // [noff] T
   void* diag = nullptr;     // [n] T, the diagonal (source of other plans' values)
   void* dinv = nullptr;     // [n] T, 1 / diagonal (what the solves multiply by)
@@ -52,11 +53,13 @@ struct SolveArgs {
   const void* b;     // caller's right-hand side(s), column stride ld
   void* x;           // caller's solution(s), column stride ld
   void* xp;          // [n * nrhs] position-ordered solution (internal)
+  const void* bp = nullptr;   // several right-hand sides: [n * nrhs] position-ordered b
   int nrhs = 1;
   int ld = 0;
   int spin_limit = 1 << 22;
   int poll = 1;      // waits: 1 = two overlapped rounds over all slots, 0 = pending only
   int xp_stride = 1; // static schedules, one right-hand side: elements between xp values
+  int mrows = 1;     // static schedule, several right-hand sides: rows per lane group (1, 2, 4)
   int grid = 0;      // persistent workgroups
   int wg = 64;       // threads per workgroup
   const int* wave_ptr = nullptr;   // static schedule: per-wavefront chunk lists (CSR)
@@ -67,7 +70,19 @@ template <typename T> hipError_t launch_gather(const DevPlan& p, const T* vals, 
                                                hipStream_t s);
 // xp[0 .. count) := the readiness sentinel (value sync)
 template <typename T> hipError_t launch_fill_sentinel(T* xp, int64_t count, hipStream_t s);
-// one launch per level for [chunk_begin, chunk_end) of one level (any nrhs)
+// Several right-hand sides in position order: bp[k * nrhs + q] :=
+// B[q * ld + pos_row[k]] (and xp := the readiness sentinel if fill), then,
+// after the solve, X[q * ld + i] := xp[row_pos[i] * nrhs + q].  Tiles of 64
+// rows through LDS: both sides coalesced.
+template <typename T> hipError_t launch_multi_in(int n, int nrhs, int ld, const T* B,
+                                                 const int* row_pos, T* bp, T* xp, bool fill,
+                                                 hipStream_t s);
+template <typename T> hipError_t launch_multi_out(int n, int nrhs, int ld, const T* xp,
+                                                  const int* row_pos, T* X, hipStream_t s);
+// row_pos[pos_row[k]] = k
+hipError_t launch_row_pos(int n, const int* pos_row, int* row_pos, hipStream_t s);
+// one launch per level for [chunk_begin, chunk_end) of one level (several
+// right-hand sides: in position order, bp in, xp out)
 template <typename T> hipError_t launch_level(const SolveArgs& a, int chunk_begin, int chunk_end,
                                               hipStream_t s);
 // self-scheduled, value sync, chunks claimed from a ticket (any nrhs)
@@ -75,7 +90,8 @@ template <typename T> hipError_t launch_self_value(const SolveArgs& a, hipStream
 // self-scheduled, flag sync, ticket (one right-hand side; reads and writes x)
 template <typename T> hipError_t launch_self_flag(const SolveArgs& a, hipStream_t s);
 // self-scheduled, value sync, static round-robin chunks over a cooperative
-// (all-resident) grid, pipelined (any nrhs)
+// (all-resident) grid, pipelined (any nrhs: several take k_self_multi with
+// mrows rows per lane group)
 template <typename T> hipError_t launch_self_static(const SolveArgs& a, hipStream_t s);
 // one workgroup of `threads` per independent system; lds_rows > 0: x of each
 // system in LDS (lds_rows >= the largest system), else in global memory
@@ -92,5 +108,6 @@ hipError_t launch_init_scratch(DevScratch sc, int n, hipStream_t s);
 template <typename T> int self_value_blocks_per_cu(int wg);
 template <typename T> int self_flag_blocks_per_cu(int wg);
 template <typename T> int self_static_blocks_per_cu(int wg);
+template <typename T> int self_multi_blocks_per_cu(int wg, int rows);
 
 }  // namespace sptrsv

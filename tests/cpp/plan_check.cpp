@@ -51,7 +51,9 @@ extern "C" int check_plan(int n, const int* rp, const int* col, int upper, int u
   for (int m = 0; m < p.nlev; ++m) {
     for (int c = t.level_chunk[m]; c < t.level_chunk[m + 1]; ++c) {
       const int cnt = t.meta[c] & 0xffff, lg = t.meta[c] >> 16;
-      const int cap = (lg == 0 && rows_fixed <= 0) ? 64 * rows_per_lane : 64;
+      // a G = 1 lane, or each lane group of a multi-RHS chunk, owns up to
+      // rows_per_lane rows
+      const int cap = (lg == 0 || rows_fixed > 0) ? 64 * rows_per_lane : 64;
       if (t.start[c] != next || cnt < 1 || lg < 0 || lg > 6 || (cnt << lg) > cap) return 11;
       if (rows_per_lane > kMaxRowsPerLane) return 16;
       if (t.start[c] < p.pos_ilev[m] || t.start[c] + cnt > p.pos_ilev[m + 1]) return 12;

@@ -239,7 +239,9 @@ def test_unit_diag(sp):
 
 @pytest.mark.parametrize("nrhs", [1, 3, 16, 70])
 @pytest.mark.parametrize("opts", [dict(algo=1), dict(algo=2), dict(algo=2, assign=1),
-                                  dict(algo=2, grid=3), dict(algo=2, assign=2, grid=32)])
+                                  dict(algo=2, grid=3), dict(algo=2, assign=2, grid=32),
+                                  dict(algo=2, multi_rows=1), dict(algo=2, multi_rows=2, grid=5),
+                                  dict(algo=2, multi_rows=4, assign=2, grid=16)])
 def test_multi_rhs(sp, nrhs, opts):
     o = oracle.get()
     T = W.laplacian_triangle((14, 13, 12), upper=True)
@@ -300,6 +302,28 @@ def test_multi_rhs_strided(sp, nrhs, assign):
     h32.status()
     ref = o.solve_multi(T.row_ptr, T.col_idx, v32.astype(np.float64), F32.T.astype(np.float64))
     assert relerr(X32.T, ref) <= TOL32
+
+
+@pytest.mark.parametrize("nrhs", [2, 6, 16, 33])
+def test_multi_rows_per_lane_group(sp, nrhs):
+    """Rows per lane group of the static multi-RHS kernel (1, 2, 4): the same
+    bits for every choice and grid, and every column equal to the one-lane
+    single-RHS solve; power-law rows long enough for several entry batches."""
+    o = oracle.get()
+    T = W.powerlaw_lower(40000, 17, window=4000)
+    F = np.stack([W.uniform_vector(T.n, 500 + r) for r in range(nrhs)], 0)
+    h = sp.Handle(*dev_tri(T)).configure(algo=2, group=1)
+    ref = None
+    for mr, grid, assign in ((1, 0, 0), (2, 7, 0), (4, 0, 2), (4, 64, 0), (0, 3, 2)):
+        h.configure(multi_rows=mr, grid=grid, assign=assign)
+        X = host(h.solve_multi(dev(F)))
+        h.status()
+        if ref is None:
+            ref = X
+            assert relerr(X.T, o.solve_multi(T.row_ptr, T.col_idx, T.vals, F.T)) <= TOL64
+        assert bits_equal(X, ref), (mr, grid, assign)
+    for r in (0, nrhs // 2, nrhs - 1):
+        assert bits_equal(ref[r], host(h.solve(dev(F[r]))))
 
 
 def test_two_streams_are_serialized(sp):
