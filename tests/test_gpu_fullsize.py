@@ -1,15 +1,17 @@
 """Full-size parity in the launch configurations the benchmark times: every
 workload at its real size, schedules chosen by the autotuner, against the
 FP64 oracle (relative inf-norm error <= 1e-12; FP32 <= 1e-5 against the
-oracle on the up-cast FP32 data).  The 96^3 ILU(0) adjoint is covered at full
-size in test_gpu_adjoint.py."""
+oracle on the up-cast FP32 data), and every GPU result held to the
+componentwise backward-error bound of substitution (scale-free: a small
+component cannot hide behind the norm).  The 96^3 ILU(0) adjoint is covered
+at full size in test_gpu_adjoint.py."""
 import numpy as np
 import pytest
 import torch
 
 import oracle
 import workloads as W
-from gpuhelp import dev, dev_tri, host, relerr
+from gpuhelp import backward_error_ok, dev, dev_tri, host, relerr
 
 pytestmark = pytest.mark.gpu
 
@@ -47,6 +49,7 @@ def test_c1_lap2d_64(sp):
         h.status()
         assert relerr(x, xo) <= TOL64
         assert relerr(x, xs) <= 1e-10          # the planted solution (well conditioned)
+        assert backward_error_ok(T, b, x)[0]
 
 
 def test_c2_lap3d_128_lower_then_upper(sp):
@@ -67,6 +70,8 @@ def test_c2_lap3d_128_lower_then_upper(sp):
         hU.status()
         assert relerr(host(y1), y1o) <= TOL64
         assert relerr(host(y2), y2o) <= TOL64
+        assert backward_error_ok(TL, bL, host(y1))[0]
+        assert backward_error_ok(TU, host(y1), host(y2))[0]
     # the transposed solves of the same handles
     g = W.uniform_vector(TL.n, 8)
     assert relerr(host(hsL.solve_t(dev(g))),
@@ -84,6 +89,7 @@ def test_c3_powerlaw_fp64_and_fp32(sp):
         x = host(h.solve(dev(b)))
         h.status()
         assert relerr(x, xo) <= TOL64
+        assert backward_error_ok(T, b, x)[0]
     v32 = T.vals.astype(np.float32)
     b32 = b.astype(np.float32)
     xo32 = o.solve(T.row_ptr, T.col_idx, v32.astype(np.float64), b32.astype(np.float64))
@@ -93,6 +99,8 @@ def test_c3_powerlaw_fp64_and_fp32(sp):
     x32 = host(h32.solve(dev(b32)))
     h32.status()
     assert relerr(x32, xo32) <= TOL32
+    T32 = W.Triangle(T.n, T.row_ptr, T.col_idx, v32.astype(np.float64))
+    assert backward_error_ok(T32, b32, x32, unit_roundoff=2.0 ** -24)[0]
 
 
 def test_c4a_batched_256_graph(sp):
@@ -102,6 +110,7 @@ def test_c4a_batched_256_graph(sp):
     tris, xs, bs = W.c4a_batch()
     devs = [dev_tri(t) for t in tris]
     xo = np.concatenate([o.solve(t.row_ptr, t.col_idx, t.vals, bb) for t, bb in zip(tris, bs)])
+    Tcat = W.concat_block_diagonal(tris)
     bd = dev(np.concatenate(bs))
     x = torch.empty_like(bd)
     for algo in (sp.ALGO_SELF, sp.ALGO_LEVEL, sp.ALGO_BLOCK):
@@ -117,6 +126,7 @@ def test_c4a_batched_256_graph(sp):
                 g.launch(s)
                 s.synchronize()
                 assert relerr(host(x), xo) <= TOL64, (algo, rep)
+            assert backward_error_ok(Tcat, np.concatenate(bs), host(x))[0], algo
             g.close()
         h.status()
 
@@ -133,3 +143,31 @@ def test_c4b_16_rhs(sp):
     h.status()
     Xo = o.solve_multi(T.row_ptr, T.col_idx, T.vals, B)
     assert relerr(Xd.T, Xo) <= TOL64
+    for q in (0, 7, 15):
+        assert backward_error_ok(T, B[:, q], Xd[q])[0], q
+
+
+def test_table2_deepest_grid_9pt(sp):
+    """The deepest grid of the paper's Table 2: the 9-point operator on
+    64 x 16384 (n = 2^20), lower then upper (32,830 levels each), self- and
+    level-scheduled."""
+    print("full size: Table 2 64x16384 9-point", flush=True)
+    o = oracle.get()
+    L = W.stencil_triangle((64, 16384), 9)
+    U = W.stencil_triangle((64, 16384), 9, upper=True)
+    b = W.uniform_vector(L.n, 7)
+    y1o = o.solve(L.row_ptr, L.col_idx, L.vals, b, False)
+    y2o = o.solve(U.row_ptr, U.col_idx, U.vals, y1o, True)
+    bd = dev(b)
+    hsL, hlL = _tuned_pair(sp, L, bd)
+    hsU, hlU = _tuned_pair(sp, U, bd)
+    assert hsL.info()["nlev"] == 32830 and hsU.info()["nlev"] == 32830
+    for hL, hU in ((hsL, hsU), (hlL, hlU)):
+        y1 = hL.solve(bd)
+        y2 = hU.solve(y1)
+        hL.status()
+        hU.status()
+        assert relerr(host(y1), y1o) <= TOL64
+        assert relerr(host(y2), y2o) <= TOL64
+        assert backward_error_ok(L, b, host(y1))[0]
+        assert backward_error_ok(U, host(y1), host(y2))[0]
