@@ -460,8 +460,9 @@ def pc_batched(sp, torch, steps, warmup, hop_ns):
     nnz = sum(t.nnz for t in tris)
     res = {"n": n, "nnz": nnz, "systems": len(tris), "dtype": "f64", "_tol": 1e-12}
     parts = ([dv[0] for dv in devs], [dv[1] for dv in devs], [dv[2] for dv in devs])
-    hs, setup_ms = _timed_handle(torch, lambda: sp.BatchedHandle(*parts))
-    hl = sp.BatchedHandle(*parts).configure(algo=sp.ALGO_LEVEL)
+    hs, setup_ms = _timed_handle(torch, lambda: sp.BatchedHandle(*parts, setup="device"))
+    hl, setup_host = _timed_handle(torch, lambda: sp.BatchedHandle(*parts, setup="host"))
+    hl.configure(algo=sp.ALGO_LEVEL)
     hb = sp.BatchedHandle(*parts).configure(algo=sp.ALGO_BLOCK)
     res["nlev"] = hs.info()["nlev"]
     hs.set_option("algo", sp.ALGO_SELF)
@@ -486,7 +487,7 @@ def pc_batched(sp, torch, steps, warmup, hop_ns):
         g.close()
     for h in (hs, hl, hb):
         h.close()
-    return _finish(res, lb_bytes(n, nnz), hop_ns, res["nlev"], setup_ms)
+    return _finish(res, lb_bytes(n, nnz), hop_ns, res["nlev"], setup_ms, setup_host, setup_host)
 
 
 def pc_multi(sp, torch, steps, warmup, hop_ns, nrhs=16):
@@ -525,15 +526,16 @@ def pc_adjoint(sp, torch, steps, warmup, hop_ns, side=96):
     xo, gbo, gvo = o.adjoint(T.row_ptr, T.col_idx, T.vals, b, w)
     wd = torch.from_numpy(w).to(DEV)
     bd0 = torch.from_numpy(b).to(DEV)
-    setup_ms = None
+    setup_ms = {}
     for tag, algo in (("self", sp.ALGO_SELF), ("level", sp.ALGO_LEVEL)):
-        def make():
-            h = sp.Handle(*d, setup="device").configure(algo=algo)
+        def make(route):
+            h = sp.Handle(*d, setup=route).configure(algo=algo)
             h.prepare_transpose()
             return h
-        h, ms = _timed_handle(torch, make)
         if tag == "self":
-            setup_ms = ms
+            hh, setup_ms["host"] = _timed_handle(torch, lambda: make("host"))
+            hh.close()
+        h, setup_ms[tag] = _timed_handle(torch, lambda: make("device" if tag == "self" else "host"))
         res["nlev"] = h.info()["nlev"]
         vals = d[2].clone().requires_grad_(True)
         bd = bd0.clone().requires_grad_(True)
@@ -555,7 +557,9 @@ def pc_adjoint(sp, torch, steps, warmup, hop_ns, side=96):
     lb_solve = lb_bytes(T.n, T.nnz)
     gather = T.nnz * 8 * 2 + T.nnz * 4
     grad = (T.n + 1) * 4 + T.nnz * 4 + T.n * 8 * 2 + T.nnz * 8
-    return _finish(res, 2 * lb_solve + gather + grad, hop_ns, 2 * res["nlev"], setup_ms)
+    # setup of the forward solve and of the adjoint's transposed analysis
+    return _finish(res, 2 * lb_solve + gather + grad, hop_ns, 2 * res["nlev"], setup_ms["self"],
+                   setup_ms["level"], setup_ms["host"])
 
 
 def per_config(sp, torch, steps, warmup, hop_ns):

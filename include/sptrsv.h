@@ -236,6 +236,17 @@ int sptrsv_analyze_batched(int32_t count, const int32_t *n, const int32_t *nnz,
                            const void *const *vals, sptrsv_dtype dtype, sptrsv_uplo uplo,
                            int unit_diag, hipStream_t stream, sptrsv_handle_t *out);
 
+/* sptrsv_analyze_batched with a choice of route (sptrsv_setup).  The device
+ * route concatenates the systems in device memory and analyses the
+ * concatenation there (only nlev, ilev and row pointers come to the host);
+ * a system whose pattern it does not take, and every invalid one, goes
+ * through the host route, which names the error.  Same plan, bit for bit,
+ * on both routes. */
+int sptrsv_analyze_batched_ex(int32_t count, const int32_t *n, const int32_t *nnz,
+                              const int32_t *const *row_ptr, const int32_t *const *col_idx,
+                              const void *const *vals, sptrsv_dtype dtype, sptrsv_uplo uplo,
+                              int unit_diag, int setup, hipStream_t stream, sptrsv_handle_t *out);
+
 /* Re-gather new values for the same pattern (the caller's vals, device).
  * Asynchronous on `stream`; a zero pivot is reported through
  * sptrsv_get_status after the stream has been synchronised. */
@@ -273,7 +284,9 @@ int sptrsv_solve_noalloc(sptrsv_handle_t h, const void *b, void *x, hipStream_t 
 /* Solve T^T x = b.  Uses the analysis of T^T (the column-wise view of
  * Sec. 3.2: rows of T^T are the columns of T, levels from the reversed
  * sweep); built on first use, which then blocks, or in advance by
- * sptrsv_prepare_transpose. */
+ * sptrsv_prepare_transpose.  A handle analysed on the device route builds it
+ * on the device as well (the transposed pattern by a stable radix sort of
+ * the entries by column, then the same device analysis). */
 int sptrsv_solve_transpose(sptrsv_handle_t h, const void *b, void *x, hipStream_t stream);
 
 /* Build the analysis of T^T now (blocking). */

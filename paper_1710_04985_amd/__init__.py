@@ -309,7 +309,10 @@ class BatchedHandle(_Base):
     """Independent triangles solved as one block-diagonal system; b and x are
     the concatenations of the systems' vectors."""
 
-    def __init__(self, row_ptrs, col_idxs, valss, uplo="L", unit_diag=False, stream=None):
+    def __init__(self, row_ptrs, col_idxs, valss, uplo="L", unit_diag=False, stream=None,
+                 setup="host"):
+        if setup not in SETUP:
+            raise ValueError("setup must be one of %s" % sorted(SETUP))
         count = len(row_ptrs)
         if not (count == len(col_idxs) == len(valss)) or count == 0:
             raise ValueError("need the same positive number of row_ptrs, col_idxs, vals")
@@ -332,10 +335,18 @@ class BatchedHandle(_Base):
         P = ctypes.c_void_p * count
         h = ctypes.c_void_p()
         arr = lambda ts: ctypes.cast(P(*[t.data_ptr() for t in ts]), ctypes.c_void_p)
-        check(lib.sptrsv_analyze_batched(
+        check(lib.sptrsv_analyze_batched_ex(
             count, I32(*self.sizes), I32(*self.nnzs), arr(row_ptrs), arr(col_idxs), arr(valss),
-            _DT[dt], int(uplo.upper() == "U"), int(unit_diag), _stream(stream), ctypes.byref(h)))
+            _DT[dt], int(uplo.upper() == "U"), int(unit_diag), SETUP[setup], _stream(stream),
+            ctypes.byref(h)))
         self._h = h
+
+    def setup_info(self):
+        """(route, milliseconds) of the analysis, as for Handle."""
+        route = ctypes.c_int32()
+        ms = ctypes.c_double()
+        check(lib.sptrsv_get_setup(self._h, ctypes.byref(route), ctypes.byref(ms)))
+        return {v: k for k, v in SETUP.items()}[route.value], ms.value
 
     def update_values(self, valss, stream=None):
         if len(valss) != self.count:

@@ -52,6 +52,8 @@ SIGNATURES = {
     "sptrsv_probe_hop": (_int, [_int, _i32, ctypes.POINTER(ctypes.c_double)]),
     "sptrsv_get_setup": (_int, [_v, _pi32, ctypes.POINTER(ctypes.c_double)]),
     "sptrsv_analyze_batched": (_int, [_i32, _pi32, _pi32, _v, _v, _v, _int, _int, _int, _v, _pv]),
+    "sptrsv_analyze_batched_ex": (_int, [_i32, _pi32, _pi32, _v, _v, _v, _int, _int, _int, _int,
+                                         _v, _pv]),
     "sptrsv_update_values": (_int, [_v, _v, _v]),
     "sptrsv_update_values_batched": (_int, [_v, _v, _v]),
     "sptrsv_solve": (_int, [_v, _v, _v, _v]),

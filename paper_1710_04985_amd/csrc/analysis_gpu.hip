@@ -325,6 +325,108 @@ struct Temps {
   }
 };
 
+__global__ void __launch_bounds__(256) k_fill_iota(int* p, int64_t count) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < count; t += stride)
+    p[t] = static_cast<int>(t);
+}
+
+// row_of[e] = the row of entry e
+__global__ void __launch_bounds__(256) k_row_of(int n, const int* __restrict__ rp,
+                                                int* __restrict__ row_of) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < n; t += stride) {
+    const int i = static_cast<int>(t);
+    for (int e = rp[i]; e < rp[i + 1]; ++e) row_of[e] = i;
+  }
+}
+
+// entries of T^T (sorted by (column of T, entry)): column = row of T, source
+// = entry of T; row pointers of T^T from the first entry of each column
+__global__ void __launch_bounds__(256) k_transpose_fill(int n, int64_t nnz,
+                                                        const int* __restrict__ col_sorted,
+                                                        const int* __restrict__ src_sorted,
+                                                        const int* __restrict__ row_of,
+                                                        int* __restrict__ colT, int* __restrict__ rpT) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < nnz; t += stride) {
+    colT[t] = row_of[src_sorted[t]];
+    // the first entry of column c (and of every empty column before it)
+    const int c = col_sorted[t];
+    const int cprev = t > 0 ? col_sorted[t - 1] : -1;
+    for (int j = cprev + 1; j <= c; ++j) rpT[j] = static_cast<int>(t);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const int clast = nnz > 0 ? col_sorted[nnz - 1] : -1;
+    for (int j = clast + 1; j <= n; ++j) rpT[j] = static_cast<int>(nnz);
+  }
+}
+
+// loc[e] = where entry e of the caller's T sits in the forward plan's value
+// buffer (off-diagonals, then the diagonal)
+__global__ void __launch_bounds__(256) k_value_loc(int n, int64_t noff, const int* __restrict__ off_src,
+                                                   const int* __restrict__ diag_src,
+                                                   int* __restrict__ loc) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  const int64_t total = noff > n ? noff : n;
+  for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < total; t += stride) {
+    if (t < noff) loc[off_src[t]] = static_cast<int>(t);
+    if (t < n && diag_src[t] >= 0) loc[diag_src[t]] = static_cast<int>(noff + t);
+  }
+}
+
+// value sources of the T^T plan: entries of T^T -> entries of T -> value
+// buffer of the forward plan
+__global__ void __launch_bounds__(256) k_compose_src(int n, int64_t noff, const int* __restrict__ srcT,
+                                                     const int* __restrict__ loc,
+                                                     int* __restrict__ off_src,
+                                                     int* __restrict__ diag_src) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  const int64_t total = noff > n ? noff : n;
+  for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < total; t += stride) {
+    if (t < noff) off_src[t] = loc[srcT[off_src[t]]];
+    if (t < n && diag_src[t] >= 0) diag_src[t] = loc[srcT[diag_src[t]]];
+  }
+}
+
+// block-diagonal concatenation of `count` systems (one row of the grid per
+// system): row pointers and columns shifted by the systems before, values
+// copied; a column outside its own system, or row pointers that do not run
+// from 0 to the system's nnz, raise the flag
+struct SysDesc {
+  const int* rp;
+  const int* col;
+  const void* vals;
+  int n;
+  int nnz;
+  int roff;
+  int eoff;
+};
+
+__global__ void __launch_bounds__(256) k_concat(const SysDesc* __restrict__ sys, int vb,
+                                                int* __restrict__ rp_cat, int* __restrict__ col_cat,
+                                                unsigned char* __restrict__ vals_cat, int* flags) {
+  const SysDesc d = sys[blockIdx.y];
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  int f = 0;
+  const int64_t total = d.nnz > d.n ? d.nnz : d.n;
+  for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < total; t += stride) {
+    if (t < d.n) rp_cat[d.roff + t] = d.rp[t] + d.eoff;
+    if (t < d.nnz) {
+      const int j = d.col[t];
+      if (j < 0 || j >= d.n) f = 1;
+      col_cat[d.eoff + t] = j + d.roff;
+      if (vb == 8)
+        reinterpret_cast<unsigned long long*>(vals_cat)[d.eoff + t] =
+            static_cast<const unsigned long long*>(d.vals)[t];
+      else
+        reinterpret_cast<unsigned*>(vals_cat)[d.eoff + t] = static_cast<const unsigned*>(d.vals)[t];
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0 && (d.rp[0] != 0 || d.rp[d.n] != d.nnz)) f = 1;
+  if (f) atomicOr(flags, 1);
+}
+
 }  // namespace
 
 void free_device_analysis(DeviceAnalysis& a) {
@@ -467,6 +569,119 @@ int device_analysis(int n, int64_t nnz, const int* row_ptr, const int* col, bool
   DCHK(hipGetLastError());
   DCHK(hipStreamSynchronize(s));
   return kOk;
+}
+
+}  // namespace sptrsv
+
+namespace sptrsv {
+
+int device_transpose(int n, int64_t nnz, const int* row_ptr, const int* col, hipStream_t s,
+                     int** rpT, int** colT, int** srcT) {
+  *rpT = *colT = *srcT = nullptr;
+  if (n < 1 || nnz < 0 || nnz > INT32_MAX) return kErrNotSupported;
+  int *keys = nullptr, *keys_s = nullptr, *vals = nullptr, *row_of = nullptr;
+  void* tmp = nullptr;
+  int st = kOk;
+  auto cleanup = [&]() {
+    for (void* p : {static_cast<void*>(keys), static_cast<void*>(keys_s), static_cast<void*>(vals),
+                    static_cast<void*>(row_of), tmp})
+      if (p) (void)hipFree(p);
+  };
+  if (dmalloc(&keys_s, nnz) || dmalloc(&vals, nnz) || dmalloc(&row_of, nnz) ||
+      dmalloc(rpT, static_cast<int64_t>(n) + 1) || dmalloc(colT, nnz) || dmalloc(srcT, nnz)) {
+    st = kErrOom;
+  }
+  int col_bits = 1;
+  while (col_bits < 31 && (1ll << col_bits) < n) ++col_bits;
+  if (!st && nnz > 0) {
+    // entries by column, stably: (column, entry) ascending, i.e. the rows of
+    // T^T with their columns (rows of T) strictly increasing
+    if (dmalloc(&keys, nnz) ||
+        hipMemcpyAsync(keys, col, static_cast<size_t>(nnz) * sizeof(int), hipMemcpyDeviceToDevice,
+                       s) != hipSuccess) {
+      st = kErrOom;
+    } else {
+      k_fill_iota<<<blocks(nnz), 256, 0, s>>>(vals, nnz);
+      size_t tb = 0;
+      if (rocprim::radix_sort_pairs(nullptr, tb, keys, keys_s, vals, *srcT,
+                                    static_cast<unsigned>(nnz), 0, col_bits, s) != hipSuccess ||
+          hipMalloc(&tmp, tb > 0 ? tb : 1) != hipSuccess ||
+          rocprim::radix_sort_pairs(tmp, tb, keys, keys_s, vals, *srcT, static_cast<unsigned>(nnz),
+                                    0, col_bits, s) != hipSuccess)
+        st = kErrHip;
+    }
+  }
+  if (!st) {
+    k_row_of<<<blocks(n), 256, 0, s>>>(n, row_ptr, row_of);
+    k_transpose_fill<<<blocks(nnz > 0 ? nnz : 1), 256, 0, s>>>(n, nnz, keys_s, *srcT, row_of, *colT,
+                                                               *rpT);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) st = kErrHip;
+  }
+  cleanup();
+  if (st) {
+    for (int** p : {rpT, colT, srcT})
+      if (*p) {
+        (void)hipFree(*p);
+        *p = nullptr;
+      }
+  }
+  return st;
+}
+
+int device_value_sources(int n, int64_t noff_f, const int* off_src_f, const int* diag_src_f,
+                         int64_t nnz, const int* srcT, DeviceAnalysis& t, hipStream_t s) {
+  int* loc = nullptr;
+  if (dmalloc(&loc, nnz)) return kErrOom;
+  const int64_t tot_f = noff_f > n ? noff_f : n;
+  const int64_t tot_t = t.noff > n ? t.noff : n;
+  k_value_loc<<<blocks(tot_f), 256, 0, s>>>(n, noff_f, off_src_f, diag_src_f, loc);
+  k_compose_src<<<blocks(tot_t), 256, 0, s>>>(n, t.noff, srcT, loc, t.off_src, t.diag_src);
+  int st = kOk;
+  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) st = kErrHip;
+  (void)hipFree(loc);
+  return st;
+}
+
+int device_concat(const std::vector<ConcatSystem>& systems, int vb, int* rp_cat, int* col_cat,
+                  void* vals_cat, hipStream_t s) {
+  const int count = static_cast<int>(systems.size());
+  std::vector<SysDesc> host(count);
+  int64_t roff = 0, eoff = 0, maxw = 1;
+  for (int k = 0; k < count; ++k) {
+    const ConcatSystem& c = systems[k];
+    host[k] = SysDesc{c.row_ptr, c.col, c.vals, c.n, c.nnz, static_cast<int>(roff),
+                      static_cast<int>(eoff)};
+    roff += c.n;
+    eoff += c.nnz;
+    maxw = std::max<int64_t>(maxw, std::max<int64_t>(c.n, c.nnz));
+  }
+  SysDesc* dsys = nullptr;
+  int* flags = nullptr;
+  int st = kOk;
+  if (dmalloc(&dsys, count) || dmalloc(&flags, 1)) st = kErrOom;
+  int f = 0;
+  if (!st && (hipMemcpyAsync(dsys, host.data(), count * sizeof(SysDesc), hipMemcpyHostToDevice, s) !=
+                  hipSuccess ||
+              hipMemsetAsync(flags, 0, sizeof(int), s) != hipSuccess))
+    st = kErrHip;
+  if (!st) {
+    const int bx = static_cast<int>(std::min<int64_t>((maxw + 255) / 256, 1024));
+    k_concat<<<dim3(bx, count), 256, 0, s>>>(dsys, vb, rp_cat, col_cat,
+                                             static_cast<unsigned char*>(vals_cat), flags);
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(&f, flags, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      st = kErrHip;
+  }
+  if (!st) {
+    // the last row pointer: total nnz
+    const int last = static_cast<int>(eoff);
+    if (hipMemcpy(rp_cat + roff, &last, sizeof(int), hipMemcpyHostToDevice) != hipSuccess) st = kErrHip;
+  }
+  if (dsys) (void)hipFree(dsys);
+  if (flags) (void)hipFree(flags);
+  if (!st && f) st = kErrNotSupported;
+  return st;
 }
 
 }  // namespace sptrsv

@@ -52,6 +52,13 @@ struct PlanState {
   bool built = false;
   HostPlan h;
   DevPlan d;
+  // analysed on the device: the host plan holds only nlev, ilev, pos_ilev
+  // and off_ptr until something needs the rest (ensure_plan_host), which is
+  // then downloaded from d and the analysis arrays below
+  bool host_complete = true;
+  int* a_level = nullptr;
+  int* a_depcnt = nullptr;
+  int* a_jlev = nullptr;
   PushState push;
   void* vals_buf = nullptr;       // [noff + 2n] values: off-diagonals, diagonal, 1/diagonal
   // (group, epl, rows_fixed, rows_per_lane)
@@ -123,15 +130,12 @@ struct sptrsv_handle_s {
   int lds_limit = 65536;          // bytes of LDS one workgroup may use
   std::vector<int> rp_h, col_h;   // caller's pattern (host copy)
   PlanState fwd, trn;
-  // device setup: the forward host plan holds only nlev, ilev and off_ptr
-  // until something needs the rest (transpose, block plan, export, tuner
-  // hash), which then downloads it and the handle's copy of the pattern
-  bool host_plan = true;
+  // device setup: the handle's own device copy of the pattern (for T^T and
+  // batched handles the concatenated pattern), downloaded to rp_h / col_h
+  // only when the host needs it
+  bool pattern_host = true;
   int* rp_dev = nullptr;
   int* col_dev = nullptr;
-  int* dev_level = nullptr;
-  int* dev_depcnt = nullptr;
-  int* dev_jlev = nullptr;
   void* col_acc = nullptr;         // column-wise solves: accumulators [n]
   int* col_cnt = nullptr;          // and arrival counts [n]
   int setup = SPTRSV_SETUP_HOST;  // route the analysis took
@@ -278,9 +282,14 @@ void free_plan(PlanState& ps) {
   dfree(ps.d.pos_row);
   dfree(ps.d.row_pos);
   dfree(ps.vals_buf);
+  dfree(ps.a_level);
+  dfree(ps.a_depcnt);
+  dfree(ps.a_jlev);
   free_push(ps.push);
   ps.d = DevPlan();
   ps.vals_buf = nullptr;
+  ps.a_level = ps.a_depcnt = ps.a_jlev = nullptr;
+  ps.host_complete = true;
   ps.built = false;
 }
 
@@ -317,15 +326,13 @@ int upload_plan(PlanState& ps, size_t vb, hipStream_t s) {
   return kOk;
 }
 
-// Completes the forward host plan of a handle analysed on the device: its
-// pattern and every plan array are downloaded once (blocking).
-int ensure_host_plan(sptrsv_handle_t h) {
-  if (h->host_plan) return kOk;
-  const size_t n = static_cast<size_t>(h->n);
-  HostPlan& p = h->fwd.h;
-  const DevPlan& d = h->fwd.d;
-  h->rp_h.resize(n + 1);
-  h->col_h.resize(h->nnz);
+// Completes the host plan of a plan analysed on the device: every plan
+// array is downloaded once (blocking).
+int ensure_plan_host(PlanState& ps) {
+  if (ps.host_complete) return kOk;
+  const size_t n = static_cast<size_t>(ps.h.n);
+  HostPlan& p = ps.h;
+  const DevPlan& d = ps.d;
   p.level.resize(n);
   p.depcnt.resize(n);
   p.jlev.resize(n);
@@ -335,20 +342,38 @@ int ensure_host_plan(sptrsv_handle_t h) {
   p.off_src.resize(p.noff);
   p.diag_src.resize(n);
   const std::pair<int*, const int*> parts[] = {
-      {h->rp_h.data(), h->rp_dev},     {h->col_h.data(), h->col_dev},
-      {p.level.data(), h->dev_level},  {p.depcnt.data(), h->dev_depcnt},
-      {p.jlev.data(), h->dev_jlev},    {p.pos_row.data(), d.pos_row},
-      {p.off_col.data(), d.off_col},   {p.off_pos.data(), d.off_pos},
-      {p.off_src.data(), d.off_src},   {p.diag_src.data(), d.diag_src}};
-  const size_t counts[] = {n + 1, static_cast<size_t>(h->nnz), n, n, n, n,
-                           static_cast<size_t>(p.noff), static_cast<size_t>(p.noff),
+      {p.level.data(), ps.a_level},  {p.depcnt.data(), ps.a_depcnt},
+      {p.jlev.data(), ps.a_jlev},    {p.pos_row.data(), d.pos_row},
+      {p.off_col.data(), d.off_col}, {p.off_pos.data(), d.off_pos},
+      {p.off_src.data(), d.off_src}, {p.diag_src.data(), d.diag_src}};
+  const size_t counts[] = {n, n, n, n, static_cast<size_t>(p.noff), static_cast<size_t>(p.noff),
                            static_cast<size_t>(p.noff), n};
   for (size_t q = 0; q < sizeof(counts) / sizeof(counts[0]); ++q)
     if (counts[q] > 0)
       HIPCHK(hipMemcpy(parts[q].first, parts[q].second, counts[q] * sizeof(int),
                        hipMemcpyDeviceToHost));
-  h->host_plan = true;
+  ps.host_complete = true;
   return kOk;
+}
+
+// The handle's pattern on the host (downloaded once from its device copy).
+int ensure_pattern_host(sptrsv_handle_t h) {
+  if (h->pattern_host) return kOk;
+  h->rp_h.resize(static_cast<size_t>(h->n) + 1);
+  h->col_h.resize(h->nnz);
+  HIPCHK(hipMemcpy(h->rp_h.data(), h->rp_dev, (static_cast<size_t>(h->n) + 1) * sizeof(int),
+                   hipMemcpyDeviceToHost));
+  if (h->nnz > 0)
+    HIPCHK(hipMemcpy(h->col_h.data(), h->col_dev, static_cast<size_t>(h->nnz) * sizeof(int),
+                     hipMemcpyDeviceToHost));
+  h->pattern_host = true;
+  return kOk;
+}
+
+// Pattern and forward plan on the host.
+int ensure_host_plan(sptrsv_handle_t h) {
+  if (const int st = ensure_pattern_host(h)) return st;
+  return ensure_plan_host(h->fwd);
 }
 
 int gather(sptrsv_handle_t h, PlanState& ps, const void* vals, hipStream_t s) {
@@ -373,13 +398,35 @@ int read_status(sptrsv_handle_t h, hipStream_t s, bool clear) {
   return kOk;
 }
 
+int install_device_plan(sptrsv_handle_t h, PlanState& ps, DeviceAnalysis& da, bool upper);
+
 // Builds the analysis of T^T: rows of T^T are the columns of T; each value is
 // taken from the forward plan's value buffer (so the caller's vals need not
-// outlive the analysis).
+// outlive the analysis).  A handle analysed on the device builds it on the
+// device too (transposed pattern by a stable radix sort, the device level
+// sweep on it, value sources composed there); otherwise on the host.
 int build_transpose(sptrsv_handle_t h, hipStream_t s) {
   if (h->trn.built) return kOk;
-  if (const int st = ensure_host_plan(h)) return st;
   const int n = h->n;
+  if (h->rp_dev && n > 0) {
+    int *rT = nullptr, *cT = nullptr, *sT = nullptr;
+    int st = device_transpose(n, h->nnz, h->rp_dev, h->col_dev, s, &rT, &cT, &sT);
+    DeviceAnalysis da;
+    if (!st) st = device_analysis(n, h->nnz, rT, cT, !h->upper, h->unit, h->num_cu, s, da);
+    if (!st)
+      st = device_value_sources(n, h->fwd.d.noff, h->fwd.d.off_src, h->fwd.d.diag_src, h->nnz, sT,
+                                da, s);
+    for (int* q : {rT, cT, sT}) dfree(q);
+    if (!st) st = install_device_plan(h, h->trn, da, !h->upper);
+    if (!st) st = gather(h, h->trn, h->fwd.vals_buf, s);
+    if (!st && hipStreamSynchronize(s) != hipSuccess) st = kErrHip;
+    if (st) {
+      free_device_analysis(da);
+      free_plan(h->trn);
+    }
+    if (st != kErrNotSupported) return st;   // else the host route below decides
+  }
+  if (const int st = ensure_host_plan(h)) return st;
   const HostPlan& f = h->fwd.h;
   // location of every caller entry in the forward value buffer
   std::vector<int> loc(h->nnz, -1);
@@ -406,8 +453,8 @@ void free_block(BlockState& b);
 int build_block(sptrsv_handle_t h, int dir, hipStream_t s) {
   BlockState& b = h->blk[dir];
   if (b.built) return kOk;
-  if (const int st = ensure_host_plan(h)) return st;
   PlanState& base = dir ? h->trn : h->fwd;
+  if (const int st = ensure_plan_host(base)) return st;
   std::vector<int> seg_row0(1, 0);
   if (h->batched)
     for (int ni : h->sys_n) seg_row0.push_back(seg_row0.back() + ni);
@@ -671,8 +718,7 @@ bool is_column(int algo) {
 // (blocking; built on first use).
 int build_push_state(sptrsv_handle_t h, PlanState& ps, hipStream_t s) {
   if (ps.push.built) return kOk;
-  if (&ps == &h->fwd)
-    if (const int st = ensure_host_plan(h)) return st;
+  if (const int st = ensure_plan_host(ps)) return st;
   std::vector<int> dst, src;
   build_push(ps.h, ps.push.h_ptr, dst, src);
   DevPush& d = ps.push.d;
@@ -1035,33 +1081,24 @@ int analyze_from_host(sptrsv_handle_t h, const void* vals, hipStream_t s) {
   return read_status(h, s, true);
 }
 
-// Setup on the device (levels, level-ordered layout) from the caller's device
-// pattern; the plan stays on the device, only nlev, ilev and off_ptr come to
-// the host (for the chunk tables).  Returns kErrNotSupported for a pattern
-// the device route does not take; the caller then runs the host route.
-int analyze_on_device(sptrsv_handle_t h, const int* row_ptr, const int* col_idx, const void* vals,
-                      hipStream_t s) {
-  (void)hipGetDevice(&h->device);
-  int ncu = 0;
-  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device) == hipSuccess &&
-      ncu > 0)
-    h->num_cu = ncu;
-  DeviceAnalysis da;
-  int st = device_analysis(h->n, h->nnz, row_ptr, col_idx, h->upper, h->unit, h->num_cu, s, da);
-  if (st) return st;
-  HostPlan& p = h->fwd.h;
+// Takes over the arrays of a device analysis as plan ps (the host plan keeps
+// nlev, ilev and off_ptr; the rest is downloaded only if the host needs it)
+// and allocates its value buffer.
+int install_device_plan(sptrsv_handle_t h, PlanState& ps, DeviceAnalysis& da, bool upper) {
+  HostPlan& p = ps.h;
   p = HostPlan();
   p.n = h->n;
   p.nlev = da.nlev;
   p.nnz = h->nnz;
   p.noff = da.noff;
-  p.upper = h->upper;
+  p.upper = upper;
   p.unit_diag = h->unit;
   p.ilev = std::move(da.ilev);
   p.pos_ilev = p.ilev;
   p.off_ptr = std::move(da.off_ptr_h);
   p.max_row_len = da.max_row_len;
-  DevPlan& d = h->fwd.d;
+  DevPlan& d = ps.d;
+  d = DevPlan();
   d.n = h->n;
   d.nlev = da.nlev;
   d.noff = da.noff;
@@ -1071,27 +1108,57 @@ int analyze_on_device(sptrsv_handle_t h, const int* row_ptr, const int* col_idx,
   d.off_src = da.off_src;
   d.diag_src = da.diag_src;
   d.pos_row = da.pos_row;
-  h->dev_level = da.level;
-  h->dev_depcnt = da.depcnt;
-  h->dev_jlev = da.jlev;
-  h->host_plan = false;
+  ps.a_level = da.level;
+  ps.a_depcnt = da.depcnt;
+  ps.a_jlev = da.jlev;
+  ps.host_complete = false;
+  da = DeviceAnalysis();        // the plan owns the arrays now
   int err = kOk;
-  h->fwd.vals_buf =
-      dalloc<char>((static_cast<size_t>(da.noff) + 2 * static_cast<size_t>(h->n)) * h->vb, &err);
-  if (!h->fwd.vals_buf) return err;
-  d.off_val = h->fwd.vals_buf;
-  d.diag = static_cast<char*>(h->fwd.vals_buf) + static_cast<size_t>(da.noff) * h->vb;
+  ps.vals_buf =
+      dalloc<char>((static_cast<size_t>(d.noff) + 2 * static_cast<size_t>(h->n)) * h->vb, &err);
+  if (!ps.vals_buf) return err;
+  d.off_val = ps.vals_buf;
+  d.diag = static_cast<char*>(ps.vals_buf) + static_cast<size_t>(d.noff) * h->vb;
   d.dinv = static_cast<char*>(d.diag) + static_cast<size_t>(h->n) * h->vb;
-  h->fwd.built = true;
-  // the handle's own copy of the pattern, for what is built later
-  h->rp_dev = dalloc<int>(static_cast<size_t>(h->n) + 1, &err);
-  h->col_dev = dalloc<int>(static_cast<size_t>(h->nnz), &err);
-  if (err) return err;
-  HIPCHK(hipMemcpyAsync(h->rp_dev, row_ptr, (static_cast<size_t>(h->n) + 1) * sizeof(int),
-                        hipMemcpyDeviceToDevice, s));
-  if (h->nnz > 0)
-    HIPCHK(hipMemcpyAsync(h->col_dev, col_idx, static_cast<size_t>(h->nnz) * sizeof(int),
+  ps.built = true;
+  return kOk;
+}
+
+// Setup on the device (levels, level-ordered layout) from the caller's device
+// pattern; the plan stays on the device, only nlev, ilev and off_ptr come to
+// the host (for the chunk tables).  Returns kErrNotSupported for a pattern
+// the device route does not take; the caller then runs the host route.
+int analyze_on_device(sptrsv_handle_t h, const int* row_ptr, const int* col_idx, const void* vals,
+                      hipStream_t s, bool copy_pattern = true) {
+  (void)hipGetDevice(&h->device);
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device) == hipSuccess &&
+      ncu > 0)
+    h->num_cu = ncu;
+  DeviceAnalysis da;
+  int st = device_analysis(h->n, h->nnz, row_ptr, col_idx, h->upper, h->unit, h->num_cu, s, da);
+  if (st) return st;
+  if ((st = install_device_plan(h, h->fwd, da, h->upper))) {
+    free_device_analysis(da);
+    return st;
+  }
+  int err = kOk;
+  // the handle's own copy of the pattern, for what is built later (a
+  // batched handle's concatenation already is its own)
+  h->pattern_host = false;
+  if (!copy_pattern) {
+    h->rp_dev = const_cast<int*>(row_ptr);
+    h->col_dev = const_cast<int*>(col_idx);
+  } else {
+    h->rp_dev = dalloc<int>(static_cast<size_t>(h->n) + 1, &err);
+    h->col_dev = dalloc<int>(static_cast<size_t>(h->nnz), &err);
+    if (err) return err;
+    HIPCHK(hipMemcpyAsync(h->rp_dev, row_ptr, (static_cast<size_t>(h->n) + 1) * sizeof(int),
                           hipMemcpyDeviceToDevice, s));
+    if (h->nnz > 0)
+      HIPCHK(hipMemcpyAsync(h->col_dev, col_idx, static_cast<size_t>(h->nnz) * sizeof(int),
+                            hipMemcpyDeviceToDevice, s));
+  }
   if ((st = init_handle_common(h, s))) return st;
   if ((st = gather(h, h->fwd, vals, s))) return st;
   return read_status(h, s, true);
@@ -1122,11 +1189,8 @@ void destroy_handle(sptrsv_handle_t h) {
   dfree(h->rp_cat);
   dfree(h->col_cat);
   dfree(h->vals_cat);
-  dfree(h->rp_dev);
-  dfree(h->col_dev);
-  dfree(h->dev_level);
-  dfree(h->dev_depcnt);
-  dfree(h->dev_jlev);
+  if (h->rp_dev != h->rp_cat) dfree(h->rp_dev);
+  if (h->col_dev != h->col_cat) dfree(h->col_dev);
   dfree(h->col_acc);
   dfree(h->col_cnt);
   for (auto& pr : h->ev_pool) {
@@ -1230,14 +1294,15 @@ int sptrsv_get_setup(sptrsv_handle_t h, int32_t* route, double* ms) {
   return kOk;
 }
 
-int sptrsv_analyze_batched(int32_t count, const int32_t* n, const int32_t* nnz,
-                           const int32_t* const* row_ptr, const int32_t* const* col_idx,
-                           const void* const* vals, sptrsv_dtype dtype, sptrsv_uplo uplo,
-                           int unit_diag, hipStream_t stream, sptrsv_handle_t* out) {
+int sptrsv_analyze_batched_ex(int32_t count, const int32_t* n, const int32_t* nnz,
+                              const int32_t* const* row_ptr, const int32_t* const* col_idx,
+                              const void* const* vals, sptrsv_dtype dtype, sptrsv_uplo uplo,
+                              int unit_diag, int setup, hipStream_t stream, sptrsv_handle_t* out) {
   if (!out) return kErrInvalidArg;
   *out = nullptr;
   if (count < 1 || !n || !nnz || !row_ptr || !col_idx || !vals ||
-      (dtype != SPTRSV_F64 && dtype != SPTRSV_F32) || (uplo != SPTRSV_LOWER && uplo != SPTRSV_UPPER))
+      (dtype != SPTRSV_F64 && dtype != SPTRSV_F32) || (uplo != SPTRSV_LOWER && uplo != SPTRSV_UPPER) ||
+      (setup != SPTRSV_SETUP_HOST && setup != SPTRSV_SETUP_DEVICE))
     return kErrInvalidArg;
   int64_t ntot = 0, nnztot = 0;
   for (int s = 0; s < count; ++s) {
@@ -1247,6 +1312,44 @@ int sptrsv_analyze_batched(int32_t count, const int32_t* n, const int32_t* nnz,
     nnztot += nnz[s];
   }
   if (ntot > INT32_MAX || nnztot > INT32_MAX) return kErrInvalidArg;
+  const auto t0 = std::chrono::steady_clock::now();
+  if (setup == SPTRSV_SETUP_DEVICE && ntot > 0) {
+    // concatenation and analysis in device memory; a pattern this route
+    // does not take (or an invalid one) goes to the host route below
+    sptrsv_handle_t h = new (std::nothrow) sptrsv_handle_s;
+    if (!h) return kErrOom;
+    h->n = static_cast<int>(ntot);
+    h->nnz = nnztot;
+    h->dtype = dtype;
+    h->vb = dtype == SPTRSV_F64 ? 8 : 4;
+    h->upper = uplo == SPTRSV_UPPER;
+    h->unit = unit_diag != 0;
+    h->batched = true;
+    h->sys_n.assign(n, n + count);
+    h->sys_nnz.assign(nnz, nnz + count);
+    int err = kOk;
+    h->rp_cat = dalloc<int>(static_cast<size_t>(ntot) + 1, &err);
+    h->col_cat = dalloc<int>(static_cast<size_t>(nnztot), &err);
+    h->vals_cat = dalloc<char>(static_cast<size_t>(nnztot) * h->vb, &err);
+    int st = err;
+    if (!st) {
+      std::vector<ConcatSystem> sys(count);
+      for (int k = 0; k < count; ++k) sys[k] = ConcatSystem{row_ptr[k], col_idx[k], vals[k], n[k], nnz[k]};
+      st = device_concat(sys, static_cast<int>(h->vb), h->rp_cat, h->col_cat, h->vals_cat, stream);
+    }
+    if (!st) st = analyze_on_device(h, h->rp_cat, h->col_cat, h->vals_cat, stream, false);
+    if (!st) st = prepare_schedule(h, false, resolve(h), stream);
+    if (!st && hipStreamSynchronize(stream) != hipSuccess) st = kErrHip;
+    if (!st) {
+      h->setup = SPTRSV_SETUP_DEVICE;
+      h->setup_ms =
+          std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+      *out = h;
+      return kOk;
+    }
+    destroy_handle(h);
+    if (st != kErrNotSupported) return st;
+  }
   sptrsv_handle_t h = new (std::nothrow) sptrsv_handle_s;
   if (!h) return kErrOom;
   h->n = static_cast<int>(ntot);
@@ -1303,8 +1406,18 @@ int sptrsv_analyze_batched(int32_t count, const int32_t* n, const int32_t* nnz,
     destroy_handle(h);
     return st;
   }
+  h->setup = SPTRSV_SETUP_HOST;
+  h->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   *out = h;
   return kOk;
+}
+
+int sptrsv_analyze_batched(int32_t count, const int32_t* n, const int32_t* nnz,
+                           const int32_t* const* row_ptr, const int32_t* const* col_idx,
+                           const void* const* vals, sptrsv_dtype dtype, sptrsv_uplo uplo,
+                           int unit_diag, hipStream_t stream, sptrsv_handle_t* out) {
+  return sptrsv_analyze_batched_ex(count, n, nnz, row_ptr, col_idx, vals, dtype, uplo, unit_diag,
+                                   SPTRSV_SETUP_HOST, stream, out);
 }
 
 int sptrsv_update_values(sptrsv_handle_t h, const void* vals, hipStream_t stream) {
@@ -1482,7 +1595,7 @@ int sptrsv_tune(sptrsv_handle_t h, const void* b, void* x, hipStream_t stream) {
   if (h->n == 0) return kOk;
   if (!b || !x || b == x) return kErrInvalidArg;
   if (!h->hash_valid) {
-    if (const int st = ensure_host_plan(h)) return st;
+    if (const int st = ensure_pattern_host(h)) return st;
     h->hash = pattern_hash(h->n, h->rp_h.data(), h->col_h.data(), h->upper, h->unit);
     h->hash_valid = true;
   }
@@ -1743,7 +1856,7 @@ int sptrsv_export_analysis(sptrsv_handle_t h, int transpose, int32_t* level, int
     const int st = build_transpose(h, h->last_stream);
     if (st) return st;
   }
-  if (const int st = ensure_host_plan(h)) return st;
+  if (const int st = ensure_plan_host(transpose ? h->trn : h->fwd)) return st;
   const HostPlan& p = transpose ? h->trn.h : h->fwd.h;
   if (level) std::copy(p.level.begin(), p.level.end(), level);
   if (ilev) std::copy(p.ilev.begin(), p.ilev.end(), ilev);

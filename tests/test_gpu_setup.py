@@ -180,3 +180,116 @@ def test_device_analysis_full_size_powerlaw(sp):
     assert np.array_equal(jlev, jl) and np.array_equal(dep, dc)
     hh = _handle(sp, T, "host")
     assert bits_equal(h.solve(dev(b)), hh.solve(dev(b)))
+
+
+def _batch(seed, count, lo, hi):
+    rng = np.random.default_rng(seed)
+    tris = []
+    for k in range(count):
+        sx, sy = (int(v) for v in rng.integers(lo, hi + 1, 2))
+        T = W.ilu0_lower((sx, sy))
+        T.vals = T.vals * W.uniform_vector(T.nnz, 100 + k, 0.9, 1.1)
+        tris.append(T)
+    return tris
+
+
+def _batched(sp, tris, setup, **kw):
+    d = [dev_tri(t) for t in tris]
+    return sp.BatchedHandle([x[0] for x in d], [x[1] for x in d], [x[2] for x in d], setup=setup,
+                            **kw)
+
+
+def test_batched_device_route(sp):
+    """The batch concatenated and analysed in device memory: analysis of the
+    concatenation (and of its transpose) bit-exact against the oracle, every
+    schedule's solve, transposed solve and value gradient bitwise equal to the
+    host route's."""
+    o = oracle.get()
+    tris = _batch(5, 24, 4, 40)
+    hd = _batched(sp, tris, "device")
+    hh = _batched(sp, tris, "host")
+    assert hd.setup_info()[0] == "device" and hh.setup_info()[0] == "host"
+    C = W.concat_block_diagonal(tris)
+    lv, nlev, il, jl, dc = o.analyze(C.row_ptr, C.col_idx, False)
+    level, ilev, jlev, dep = hd.export_analysis()
+    assert np.array_equal(level, lv) and np.array_equal(ilev, il)
+    assert np.array_equal(jlev, jl) and np.array_equal(dep, dc)
+    rT, cT, _ = o.transpose(C.row_ptr, C.col_idx)
+    lvT, _, ilT, jlT, dcT = o.analyze(rT, cT, True)
+    level, ilev, jlev, dep = hd.export_analysis(transpose=True)
+    assert np.array_equal(level, lvT) and np.array_equal(ilev, ilT)
+    assert np.array_equal(jlev, jlT) and np.array_equal(dep, dcT)
+    b = dev(W.uniform_vector(C.n, 6))
+    for opts in SCHEDULES:
+        hd.configure(**opts)
+        hh.configure(**opts)
+        assert bits_equal(hd.solve(b), hh.solve(b)), opts
+        assert bits_equal(hd.solve_t(b), hh.solve_t(b)), opts
+    x = hd.solve(b)
+    gb = hd.solve_t(b)
+    assert bits_equal(hd.grad_vals(gb, x), hh.grad_vals(gb, x))
+    hd.status()
+    hh.status()
+    assert np.abs(host(x) - o.solve(C.row_ptr, C.col_idx, C.vals, host(b))).max() <= \
+        1e-12 * np.abs(host(x)).max()
+
+
+def test_batched_device_route_invalid_system(sp):
+    """A system whose column lies outside it (but inside the concatenation)
+    and one with a bad row pointer: the device route hands them to the host
+    route, which reports the same error either way."""
+    tris = _batch(7, 5, 3, 6)
+    for k, mutate, want in ((2, "col", -4), (3, "rp", -2)):
+        bad = [W.Triangle(t.n, t.row_ptr.copy(), t.col_idx.copy(), t.vals.copy()) for t in tris]
+        if mutate == "col":
+            bad[k].col_idx[bad[k].row_ptr[1]] = bad[k].n + 1   # past its own system
+        else:
+            bad[k].row_ptr[-1] -= 1
+        got = []
+        for setup in ("device", "host"):
+            try:
+                _batched(sp, bad, setup)
+                got.append(0)
+            except sp.SpTRSVError as e:
+                got.append(e.status)
+        assert got[0] == got[1] and got[0] < 0, (mutate, got)
+
+
+def test_batched_device_route_full_size_c4a(sp):
+    """The 256 ILU(0) factors at full size on the device route: analysis
+    bit-exact against the host route's plan (solves bitwise equal)."""
+    print("batched device setup C4a", flush=True)
+    tris, xs, bs = W.c4a_batch()
+    hd = _batched(sp, tris, "device")
+    route, ms = hd.setup_info()
+    print("C4a device setup %.1f ms" % ms, flush=True)
+    assert route == "device"
+    hh = _batched(sp, tris, "host")
+    b = dev(np.concatenate(bs))
+    for opts in (dict(algo=2), dict(algo=1)):
+        hd.configure(**opts)
+        hh.configure(**opts)
+        assert bits_equal(hd.solve(b), hh.solve(b))
+    hd.status()
+
+
+def test_transpose_on_device_full_size_ilu96(sp):
+    """The 96^3 ILU(0) factor analysed on the device: its transposed
+    analysis (the adjoint's) is also built on the device, bit-exact against
+    the oracle's analysis of T^T, and the transposed solve equals the host
+    route's bit for bit."""
+    print("device transpose ILU(0) 96^3", flush=True)
+    o = oracle.get()
+    T = W.c5_ilu3d()[0]
+    h = _handle(sp, T, "device")
+    h.prepare_transpose()
+    rT, cT, _ = o.transpose(T.row_ptr, T.col_idx)
+    lvT, nlevT, ilT, jlT, dcT = o.analyze(rT, cT, True)
+    level, ilev, jlev, dep = h.export_analysis(transpose=True)
+    assert nlevT == 286
+    assert np.array_equal(level, lvT) and np.array_equal(ilev, ilT)
+    assert np.array_equal(jlev, jlT) and np.array_equal(dep, dcT)
+    g = dev(W.uniform_vector(T.n, 9))
+    hh = _handle(sp, T, "host")
+    assert bits_equal(h.solve_t(g), hh.solve_t(g))
+    h.status()
