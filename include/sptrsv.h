@@ -77,8 +77,12 @@ typedef enum {
     SPTRSV_ERR_NOT_SUPPORTED = -11, /* valid request the library does not implement */
     SPTRSV_ERR_BUSY = -12,          /* sptrsv_destroy: graphs captured from the handle are
                                        still alive (destroy them first) */
-    SPTRSV_ERR_TOO_LARGE = -13      /* sptrsv_solve_noalloc: the schedule needs more than
+    SPTRSV_ERR_TOO_LARGE = -13,     /* sptrsv_solve_noalloc: the schedule needs more than
                                        SPTRSV_NOALLOC_SCRATCH_BYTES of scratch */
+    SPTRSV_ERR_NOT_RESIDENT = -14   /* a cooperatively launched static schedule found its grid
+                                       not all resident (other work held the GPU): it drained
+                                       without a result; the ticket schedule (ASSIGN_TICKET)
+                                       needs no residency */
 } sptrsv_status;
 
 typedef enum { SPTRSV_F64 = 0, SPTRSV_F32 = 1 } sptrsv_dtype;
@@ -143,12 +147,18 @@ typedef enum {
                                      where dependencies are scattered, slower where polls
                                      coalesce.  The autotuner tries packed values and 32- and
                                      64-byte slots.  Ignored by the other schedules */
-    SPTRSV_OPT_MULTI_ROWS = 12    /* several right-hand sides, static schedules: rows each
+    SPTRSV_OPT_MULTI_ROWS = 12,   /* several right-hand sides, static schedules: rows each
                                      group of a row's lanes owns in a chunk (1, 2 or 4; 0 =
                                      default: 4 when a row takes 8 or more lanes, 2 at 4
                                      lanes, else 1).  A wavefront issues the gathers of all
                                      its rows before it waits on any, so larger values mean
                                      fewer waits per level.  Results do not depend on it */
+    SPTRSV_OPT_RESIDENCY_LIMIT = 13  /* polls a wavefront of a cooperatively launched (static)
+                                     schedule waits at its start for the rest of the grid to
+                                     sign in (default 2^20); the grid gives up with
+                                     SPTRSV_ERR_NOT_RESIDENT if it never fills.  0 makes every
+                                     wavefront but the last to arrive give up at once (a test
+                                     hook that forces the failure) */
 } sptrsv_option;
 
 typedef enum {

@@ -16,7 +16,7 @@ STATUS = {
     -3: "SPTRSV_ERR_BAD_COLIDX", -4: "SPTRSV_ERR_NOT_TRIANGULAR", -5: "SPTRSV_ERR_DUPLICATE",
     -6: "SPTRSV_ERR_MISSING_DIAG", -7: "SPTRSV_ERR_ZERO_PIVOT", -8: "SPTRSV_ERR_HIP",
     -9: "SPTRSV_ERR_OOM", -10: "SPTRSV_ERR_TIMEOUT", -11: "SPTRSV_ERR_NOT_SUPPORTED",
-    -12: "SPTRSV_ERR_BUSY", -13: "SPTRSV_ERR_TOO_LARGE",
+    -12: "SPTRSV_ERR_BUSY", -13: "SPTRSV_ERR_TOO_LARGE", -14: "SPTRSV_ERR_NOT_RESIDENT",
 }
 
 

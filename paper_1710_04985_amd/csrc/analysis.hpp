@@ -24,6 +24,7 @@ enum : int {
   kErrNotSupported = -11,
   kErrBusy = -12,
   kErrTooLarge = -13,
+  kErrNotResident = -14,
 };
 
 // Checks the problem statement of Sec. 3, eq. (1) on the pattern: row_ptr

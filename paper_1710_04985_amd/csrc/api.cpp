@@ -168,6 +168,7 @@ struct sptrsv_handle_s {
   int poll = 1;
   int xp_stride = 1;
   int mrows = 0;
+  int res_limit = 1 << 20;
   // autotuner result
   bool tuned = false;
   Config tuned_cfg{SPTRSV_ALGO_SELF, 0, 4, SPTRSV_SYNC_VALUE, 1, 0, SPTRSV_ASSIGN_STATIC};
@@ -393,6 +394,7 @@ int read_status(sptrsv_handle_t h, hipStream_t s, bool clear) {
     const int zero = 0;
     HIPCHK(hipMemcpy(h->scratch.status, &zero, sizeof(int), hipMemcpyHostToDevice));
   }
+  if (st & kStatusNotResident) return kErrNotResident;
   if (st & kStatusTimeout) return kErrTimeout;
   if (st & kStatusZeroPivot) return kErrZeroPivot;
   return kOk;
@@ -633,15 +635,17 @@ int blocks_per_cu(sptrsv_handle_t h, int kind) {
 }
 
 // Workgroups of a persistent launch: the explicit choice, else one
-// wavefront per CU; never more than chunks need, than the occupancy figure
-// allows, or than 8 wavefronts per CU (a quarter of a CU's wave slots, so
-// the all-resident schedules keep a wide margin below capacity).
+// wavefront per CU; never more than chunks need, than half of what the
+// occupancy figure allows, or than 8 wavefronts per CU (a quarter of a CU's
+// wave slots), so the all-resident schedules keep at least a factor of two
+// below the reported capacity (the cooperative launches also check
+// residency when they start).
 int persistent_grid(sptrsv_handle_t h, int kind, int grid, int nchunks) {
   const int per_cu = blocks_per_cu(h, kind);
   const int waves_per_block = h->wg / 64;
   const int need = (nchunks + waves_per_block - 1) / waves_per_block;
   int g = grid > 0 ? grid : (h->num_cu + waves_per_block - 1) / waves_per_block;
-  const int cap_per_cu = std::max(1, std::min(per_cu, 8 / waves_per_block));
+  const int cap_per_cu = std::max(1, std::min(per_cu / 2, 8 / waves_per_block));
   g = std::min(g, cap_per_cu * h->num_cu);
   return std::max(1, std::min(g, need));
 }
@@ -792,6 +796,8 @@ int solve_column(sptrsv_handle_t h, PlanState& ps, const Config& c, const void* 
   a.acc = h->col_acc;
   a.cnt = h->col_cnt;
   a.status = h->scratch.status;
+  a.arrive = h->scratch.arrive;
+  a.res_limit = h->res_limit;
   a.spin_limit = h->spin_limit;
   a.wg = h->wg;
   if (launch_column_init<T>(a, s) != hipSuccess) return kErrHip;
@@ -884,6 +890,7 @@ int solve_impl(sptrsv_handle_t h, PlanState& ps, const Config& c_in, const void*
   a.spin_limit = h->spin_limit;
   a.poll = c.poll;
   a.xp_stride = stride;
+  a.res_limit = h->res_limit;
   a.mrows = use_static ? mrows : 1;
   a.wg = h->wg;
   hipEvent_t stop;
@@ -909,7 +916,7 @@ int solve_impl(sptrsv_handle_t h, PlanState& ps, const Config& c_in, const void*
   const bool level = c.algo == SPTRSV_ALGO_LEVEL || c.algo == SPTRSV_ALGO_BLOCK;
   if (multi && launch_multi_in<T>(n, nrhs, ld, static_cast<const T*>(b), ps.d.row_pos,
                                   static_cast<T*>(h->bp), static_cast<T*>(xp), !level,
-                                  s) != hipSuccess)
+                                  h->scratch.arrive, s) != hipSuccess)
     return kErrHip;
   auto multi_out = [&]() {
     return !multi || launch_multi_out<T>(n, nrhs, ld, static_cast<const T*>(xp), ps.d.row_pos,
@@ -937,7 +944,8 @@ int solve_impl(sptrsv_handle_t h, PlanState& ps, const Config& c_in, const void*
   }
   // value sync: xp starts as the sentinel (b == x needs no copy: a row reads
   // its own b before any write of its own x, and x is only written)
-  if (!multi && launch_fill_sentinel<T>(static_cast<T*>(xp), xp_need, s) != hipSuccess)
+  if (!multi &&
+      launch_fill_sentinel<T>(static_cast<T*>(xp), xp_need, h->scratch.arrive, s) != hipSuccess)
     return kErrHip;
   a.grid = persistent_grid(h, use_static ? multi_kind(multi ? mrows : 0) : 0, c.grid,
                            ch->d.count);
@@ -1062,6 +1070,7 @@ int init_handle_common(sptrsv_handle_t h, hipStream_t s) {
   h->scratch.status = dalloc<int>(1, &err);
   h->scratch.epoch = dalloc<unsigned>(1, &err);
   h->scratch.flags = dalloc<unsigned>(h->n, &err);
+  h->scratch.arrive = dalloc<int>(1, &err);
   if (err) return err;
   if ((err = ensure_xp(h, h->n))) return err;
   HIPCHK(hipEventCreateWithFlags(&h->order_ev, hipEventDisableTiming));
@@ -1183,6 +1192,7 @@ void destroy_handle(sptrsv_handle_t h) {
   dfree(h->scratch.status);
   dfree(h->scratch.epoch);
   dfree(h->scratch.flags);
+  dfree(h->scratch.arrive);
   h->xp_buf.reset();
   h->xp = nullptr;
   dfree(h->bp);
@@ -1566,6 +1576,10 @@ int sptrsv_set_option(sptrsv_handle_t h, sptrsv_option key, int64_t v) {
       if (v != 0 && v != 1 && v != 2 && v != 4) return kErrInvalidArg;
       h->mrows = static_cast<int>(v);
       return kOk;
+    case SPTRSV_OPT_RESIDENCY_LIMIT:
+      if (v < 0 || v > INT32_MAX) return kErrInvalidArg;
+      h->res_limit = static_cast<int>(v);
+      return kOk;
   }
   return kErrInvalidArg;
 }
@@ -1586,6 +1600,7 @@ int sptrsv_get_option(sptrsv_handle_t h, sptrsv_option key, int64_t* v) {
     case SPTRSV_OPT_POLL: *v = h->poll; return kOk;
     case SPTRSV_OPT_XP_STRIDE: *v = h->xp_stride; return kOk;
     case SPTRSV_OPT_MULTI_ROWS: *v = h->mrows; return kOk;
+    case SPTRSV_OPT_RESIDENCY_LIMIT: *v = h->res_limit; return kOk;
   }
   return kErrInvalidArg;
 }
@@ -1898,6 +1913,7 @@ const char* sptrsv_status_string(int status) {
     case SPTRSV_ERR_NOT_SUPPORTED: return "not supported";
     case SPTRSV_ERR_BUSY: return "handle still has live graphs";
     case SPTRSV_ERR_TOO_LARGE: return "request exceeds the fixed scratch capacity";
+    case SPTRSV_ERR_NOT_RESIDENT: return "cooperative grid not all resident";
   }
   return "unknown status";
 }

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include "column.hpp"
+#include "residency.hpp"
 
 namespace sptrsv {
 namespace {
@@ -48,8 +49,10 @@ template <typename T> struct CArgs {
   T* acc;
   int* cnt;
   int* status;
+  int* arrive;
   int n;
   int spin_limit;
+  int res_limit;
 };
 
 template <typename T>
@@ -64,6 +67,7 @@ __global__ void __launch_bounds__(256) k_push_gather(int64_t nnz, const int* __r
 
 template <typename T> __global__ void __launch_bounds__(256) k_column_init(CArgs<T> a) {
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *a.arrive = 0;
   for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < a.n;
        t += stride) {
     const int k = static_cast<int>(t);
@@ -153,6 +157,7 @@ __global__ void __launch_bounds__(256)
 k_column_self(CArgs<T> a, const int* __restrict__ cstart, const int* __restrict__ cmeta,
               const int* __restrict__ wptr, const int* __restrict__ wlist) {
   const int lane = threadIdx.x & 63;
+  if (!grid_resident(a.arrive, a.res_limit, a.status)) return;
   const int wave = static_cast<int>((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   const int lb = wptr[wave], le = wptr[wave + 1];
   for (int t = lb; t < le; ++t) {
@@ -174,8 +179,10 @@ template <typename T> CArgs<T> make_cargs(const ColumnArgs& s) {
   a.acc = static_cast<T*>(s.acc);
   a.cnt = s.cnt;
   a.status = s.status;
+  a.arrive = s.arrive;
   a.n = s.plan->n;
   a.spin_limit = s.spin_limit;
+  a.res_limit = s.res_limit;
   return a;
 }
 

@@ -32,7 +32,9 @@ struct ColumnArgs {
   void* acc;                 // [n] T, position order: b minus the pushed updates
   int* cnt;                  // [n] updates received per position
   int* status;
+  int* arrive = nullptr;     // residency check of the cooperative launch
   int spin_limit = 1 << 22;
+  int res_limit = 1 << 20;
   int grid = 0;
   int wg = 64;
   const int* wave_ptr = nullptr;    // self-scheduled: per-wavefront chunk lists

@@ -37,6 +37,7 @@
 
 #include "analysis.hpp"
 #include "kernels.hpp"
+#include "residency.hpp"
 
 namespace sptrsv {
 namespace {
@@ -196,6 +197,8 @@ template <typename T> struct KArgs {
   int* status;
   unsigned* epoch;
   unsigned* flags;
+  int* arrive;
+  int res_limit;
   int spin_limit;
   int poll;          // 1: overlapped polling of all slots, 0: single rounds of pending ones
 };
@@ -443,6 +446,7 @@ __global__ void __launch_bounds__(256)
 k_self_static(KArgs<T> a, const int* __restrict__ cstart, const int* __restrict__ cmeta,
               const int* __restrict__ wptr, const int* __restrict__ wlist) {
   const int lane = threadIdx.x & 63;
+  if (!grid_resident(a.arrive, a.res_limit, a.status)) return;
   const int w = wave_uniform(static_cast<int>((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
   // this wavefront's chunks: wlist[wptr[w] .. wptr[w+1]), increasing
   const int tb = wptr[w], te = wptr[w + 1];
@@ -581,6 +585,7 @@ __global__ void __launch_bounds__(256)
 k_self_multi(KArgs<T> a, const int* __restrict__ cstart, const int* __restrict__ cmeta,
              const int* __restrict__ wptr, const int* __restrict__ wlist) {
   const int lane = threadIdx.x & 63;
+  if (!grid_resident(a.arrive, a.res_limit, a.status)) return;
   const int w = wave_uniform(static_cast<int>((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
   const int tb = wptr[w], te = wptr[w + 1];
   const int llast = a.nchunks - 1;
@@ -718,10 +723,11 @@ k_self_multi(KArgs<T> a, const int* __restrict__ cstart, const int* __restrict__
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_multi_in(int n, int nrhs, int ld, const T* __restrict__ B, const int* __restrict__ row_pos,
-           T* __restrict__ bp, T* __restrict__ xp, int fill) {
+           T* __restrict__ bp, T* __restrict__ xp, int fill, int* arrive) {
   using U = typename Bits<T>::U;
   __shared__ T tile[64][65];
   const int i0 = blockIdx.x * 64, tid = threadIdx.x;
+  if (blockIdx.x == 0 && tid == 0) *arrive = 0;
   for (int q0 = 0; q0 < nrhs; q0 += 64) {
     const int qc = nrhs - q0 < 64 ? nrhs - q0 : 64;
     const int il = tid & 63;
@@ -959,9 +965,10 @@ __global__ void __launch_bounds__(256) k_gather(int64_t noff, int n, const int* 
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_fill_sentinel(T* xp, int64_t count) {
+__global__ void __launch_bounds__(256) k_fill_sentinel(T* xp, int64_t count, int* arrive) {
   using U = typename Bits<T>::U;
   U* u = reinterpret_cast<U*>(xp);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *arrive = 0;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
   for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < count;
        t += stride)
@@ -986,12 +993,13 @@ __global__ void __launch_bounds__(256) k_grad_vals(int n, const int* __restrict_
 }
 
 __global__ void __launch_bounds__(256) k_init_scratch(int* ticket, int* status, unsigned* epoch,
-                                                      unsigned* flags, int n) {
+                                                      unsigned* flags, int* arrive, int n) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t == 0) {
     *ticket = 0;
     *status = 0;
     *epoch = 1u;
+    *arrive = 0;
   }
   for (int i = t; i < n; i += gridDim.x * blockDim.x) flags[i] = 0u;
 }
@@ -1019,6 +1027,8 @@ template <typename T> KArgs<T> make_args(const SolveArgs& s) {
   a.status = s.scratch.status;
   a.epoch = s.scratch.epoch;
   a.flags = s.scratch.flags;
+  a.arrive = s.scratch.arrive;
+  a.res_limit = s.res_limit;
   a.spin_limit = s.spin_limit;
   a.poll = s.poll;
   return a;
@@ -1048,17 +1058,18 @@ hipError_t launch_gather(const DevPlan& p, const T* vals, int* status, hipStream
   return hipGetLastError();
 }
 
-template <typename T> hipError_t launch_fill_sentinel(T* xp, int64_t count, hipStream_t s) {
-  if (count == 0) return hipSuccess;
-  k_fill_sentinel<T><<<blocks_for(count, 256, 8192), 256, 0, s>>>(xp, count);
+template <typename T>
+hipError_t launch_fill_sentinel(T* xp, int64_t count, int* arrive, hipStream_t s) {
+  k_fill_sentinel<T><<<blocks_for(count, 256, 8192), 256, 0, s>>>(xp, count, arrive);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_multi_in(int n, int nrhs, int ld, const T* B, const int* row_pos, T* bp, T* xp,
-                           bool fill, hipStream_t s) {
+                           bool fill, int* arrive, hipStream_t s) {
   if (n == 0 || nrhs == 0) return hipSuccess;
-  k_multi_in<T><<<(n + 63) / 64, 256, 0, s>>>(n, nrhs, ld, B, row_pos, bp, xp, fill ? 1 : 0);
+  k_multi_in<T><<<(n + 63) / 64, 256, 0, s>>>(n, nrhs, ld, B, row_pos, bp, xp, fill ? 1 : 0,
+                                               arrive);
   return hipGetLastError();
 }
 
@@ -1149,8 +1160,8 @@ hipError_t launch_grad_vals(int n, const int* row_ptr, const int* col, int unit_
 }
 
 hipError_t launch_init_scratch(DevScratch sc, int n, hipStream_t s) {
-  k_init_scratch<<<blocks_for(n > 0 ? n : 1, 256, 4096), 256, 0, s>>>(sc.ticket, sc.status,
-                                                                      sc.epoch, sc.flags, n);
+  k_init_scratch<<<blocks_for(n > 0 ? n : 1, 256, 4096), 256, 0, s>>>(
+      sc.ticket, sc.status, sc.epoch, sc.flags, sc.arrive, n);
   return hipGetLastError();
 }
 
@@ -1176,9 +1187,9 @@ template <typename T> int self_multi_blocks_per_cu(int wg, int rows) {
 
 #define SPTRSV_INSTANTIATE(T)                                                                    \
   template hipError_t launch_gather<T>(const DevPlan&, const T*, int*, hipStream_t);             \
-  template hipError_t launch_fill_sentinel<T>(T*, int64_t, hipStream_t);                         \
+  template hipError_t launch_fill_sentinel<T>(T*, int64_t, int*, hipStream_t);                   \
   template hipError_t launch_multi_in<T>(int, int, int, const T*, const int*, T*, T*, bool,       \
-                                         hipStream_t);                                           \
+                                         int*, hipStream_t);                                     \
   template hipError_t launch_multi_out<T>(int, int, int, const T*, const int*, T*, hipStream_t);  \
   template hipError_t launch_level<T>(const SolveArgs&, int, int, hipStream_t);                  \
   template hipError_t launch_self_value<T>(const SolveArgs&, hipStream_t);                       \

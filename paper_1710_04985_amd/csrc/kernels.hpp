@@ -37,9 +37,10 @@ struct DevScratch {
   int* status = nullptr;     // bit 0: timeout, bit 1: zero pivot
   unsigned* epoch = nullptr; // current flag epoch (flag sync)
   unsigned* flags = nullptr; // [n] per-row ready flags (flag sync)
+  int* arrive = nullptr;     // wavefronts signed in (cooperative kernels' residency check)
 };
 
-enum : int { kStatusTimeout = 1, kStatusZeroPivot = 2 };
+enum : int { kStatusTimeout = 1, kStatusZeroPivot = 2, kStatusNotResident = 4 };
 
 // Arguments of one solve.  The solve kernels (except flag sync and block)
 // keep the solution in position order in xp: xp[k * nrhs + q] is column q of
@@ -59,6 +60,7 @@ struct SolveArgs {
   int spin_limit = 1 << 22;
   int poll = 1;      // waits: 1 = two overlapped rounds over all slots, 0 = pending only
   int xp_stride = 1; // static schedules, one right-hand side: elements between xp values
+  int res_limit = 1 << 20;   // residency check: polls before a cooperative grid is given up
   int mrows = 1;     // static schedule, several right-hand sides: rows per lane group (1, 2, 4)
   int grid = 0;      // persistent workgroups
   int wg = 64;       // threads per workgroup
@@ -68,15 +70,17 @@ struct SolveArgs {
 
 template <typename T> hipError_t launch_gather(const DevPlan& p, const T* vals, int* status,
                                                hipStream_t s);
-// xp[0 .. count) := the readiness sentinel (value sync)
-template <typename T> hipError_t launch_fill_sentinel(T* xp, int64_t count, hipStream_t s);
+// xp[0 .. count) := the readiness sentinel (value sync); *arrive := 0 (the
+// residency check of the cooperative kernel that follows)
+template <typename T> hipError_t launch_fill_sentinel(T* xp, int64_t count, int* arrive,
+                                                      hipStream_t s);
 // Several right-hand sides in position order: bp[k * nrhs + q] :=
 // B[q * ld + pos_row[k]] (and xp := the readiness sentinel if fill), then,
 // after the solve, X[q * ld + i] := xp[row_pos[i] * nrhs + q].  Tiles of 64
 // rows through LDS: both sides coalesced.
 template <typename T> hipError_t launch_multi_in(int n, int nrhs, int ld, const T* B,
                                                  const int* row_pos, T* bp, T* xp, bool fill,
-                                                 hipStream_t s);
+                                                 int* arrive, hipStream_t s);
 template <typename T> hipError_t launch_multi_out(int n, int nrhs, int ld, const T* xp,
                                                   const int* row_pos, T* X, hipStream_t s);
 // row_pos[pos_row[k]] = k

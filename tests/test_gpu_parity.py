@@ -518,6 +518,33 @@ def test_watchdog_timeout_is_reported_and_recovers(sp, sync, assign, poll):
     assert np.array_equal(x, np.arange(1, n + 1, dtype=np.float64))
 
 
+@pytest.mark.parametrize("opts,nrhs", [(dict(algo=2, assign=0, grid=16), 1),
+                                       (dict(algo=2, assign=2, grid=64), 1),
+                                       (dict(algo=2, assign=0, grid=32, wg=256), 1),
+                                       (dict(algo=2, assign=0, grid=24), 16),
+                                       (dict(algo=5, assign=0, grid=16), 1)])
+def test_residency_check_forced(sp, opts, nrhs):
+    """The cooperative static schedules' residency check, forced to fail
+    from the host (limit 0: every wavefront but the last to sign in gives
+    up): the grid drains, the status is NOT_RESIDENT (distinct from the wait
+    watchdog's TIMEOUT), and with the default limit the same handle solves
+    correctly again."""
+    T = W.laplacian_triangle((30, 28, 26))
+    o = oracle.get()
+    F = np.stack([W.uniform_vector(T.n, 60 + r) for r in range(nrhs)], 0)
+    h = sp.Handle(*dev_tri(T)).configure(residency_limit=0, **opts)
+    run = (lambda: h.solve(dev(F[0]))) if nrhs == 1 else (lambda: h.solve_multi(dev(F)))
+    run()
+    with pytest.raises(sp.SpTRSVError) as e:
+        h.status()
+    assert e.value.status == -14
+    h.set_option("residency_limit", 1 << 20)
+    X = host(run()).reshape(nrhs, T.n)
+    h.status()
+    Xo = o.solve_multi(T.row_ptr, T.col_idx, T.vals, F.T)
+    assert relerr(X.T, Xo) <= TOL64
+
+
 @pytest.mark.parametrize("opts", [dict(algo=1), dict(algo=2, sync=0), dict(algo=2, sync=1),
                                   dict(algo=3),
                                   dict(algo=2, sync=0, xp_stride=2)])
