@@ -324,12 +324,14 @@ int sptrsv_set_option(sptrsv_handle_t h, sptrsv_option key, int64_t value);
 int sptrsv_get_option(sptrsv_handle_t h, sptrsv_option key, int64_t *value);
 
 /* Time short trials of the candidate schedules on (b, x) -- both device
- * vectors of n elements, x overwritten -- and keep the fastest (lanes per
- * row rule, rows per lane, sync, persistent grid, assignment, polling mode;
- * and the algorithm when ALGO is AUTO, else only candidates of the fixed
- * ALGO; the column-wise solves only when fixed).  Results are cached per
- * pattern hash in the process.  Changing a schedule option afterwards drops
- * the tuned choice. */
+ * vectors of n elements, x overwritten -- and keep the fastest (rows per
+ * lane, sync, persistent grid, assignment, polling mode, slot width; and the
+ * algorithm when ALGO is AUTO, else only candidates of the fixed ALGO; the
+ * column-wise solves only when fixed).  The lanes of each row (GROUP and
+ * ENTRIES_PER_LANE) stay as set, so every candidate computes the same bits:
+ * the tuned result does not depend on which candidate timing picks.
+ * Results are cached per pattern hash in the process.  Changing a schedule
+ * option afterwards drops the tuned choice. */
 int sptrsv_tune(sptrsv_handle_t h, const void *b, void *x, hipStream_t stream);
 
 /* Autotuner for solves with nrhs >= 2 right-hand sides (column-major, column

@@ -575,7 +575,8 @@ Config resolve_multi(sptrsv_handle_t h, int nrhs) {
 
 uint64_t tune_key(sptrsv_handle_t h) {
   return h->hash ^ (h->dtype == SPTRSV_F32 ? 0x9e3779b97f4a7c15ull : 0) ^
-         (static_cast<uint64_t>(h->algo) << 56);
+         (static_cast<uint64_t>(h->algo) << 56) ^ (static_cast<uint64_t>(h->group) << 48) ^
+         (static_cast<uint64_t>(h->epl) << 32);
 }
 
 // Grows the position-ordered solution buffer to `elems` values.  Work the
@@ -1625,49 +1626,50 @@ int sptrsv_tune(sptrsv_handle_t h, const void* b, void* x, hipStream_t stream) {
     }
   }
   // candidate schedules, restricted to the algorithm the options fix (all of
-  // them under ALGO_AUTO): the lane rule (entries per lane), rows per lane
-  // and, for the self-scheduled solve, the persistent grid and the sync
+  // them under ALGO_AUTO).  Every candidate keeps the handle's lane rule (the
+  // GROUP and ENTRIES_PER_LANE options), which fixes each row's summation
+  // order, so all of them compute the same bits: timing noise may change
+  // which one wins, never the result.  Varied: rows per lane, and for the
+  // self-scheduled solve the persistent grid, chunk assignment, sync,
+  // polling mode and slot width; level vs self (vs block, whose one lane per
+  // row matches the rule only when every row gets one lane).
   std::vector<Config> cand;
   const int ncu = h->num_cu;
+  const int grp = h->group, epl = h->epl;
   const bool self_ok = h->algo == SPTRSV_ALGO_AUTO || h->algo == SPTRSV_ALGO_SELF;
   const bool level_ok = h->algo == SPTRSV_ALGO_AUTO || h->algo == SPTRSV_ALGO_LEVEL;
-  for (int epl : {1, 2, 4, 8}) {
-    if (self_ok) {
-      for (int grid : {ncu / 2, ncu, 2 * ncu, 4 * ncu}) {
-        for (int poll : {1, 0})
-          // values packed, or one per 32- or 64-byte slot (fewer per cache line
-          // under concurrent stores and polls)
-          for (int slot : {0, 32, 64}) {
-            const int stride = slot == 0 ? 1 : slot / static_cast<int>(h->vb);
-            Config c1{SPTRSV_ALGO_SELF, 0, epl, SPTRSV_SYNC_VALUE, 1, grid, SPTRSV_ASSIGN_STATIC};
-            Config c2{SPTRSV_ALGO_SELF, 0, epl, SPTRSV_SYNC_VALUE, 1, grid, SPTRSV_ASSIGN_XCD};
-            c1.poll = c2.poll = poll;
-            c1.stride = c2.stride = stride;
-            cand.push_back(c1);
-            cand.push_back(c2);
+  if (self_ok) {
+    for (int grid : {ncu / 2, ncu, 2 * ncu, 4 * ncu})
+      for (int poll : {1, 0})
+        // values packed, or one per 32- or 64-byte slot (fewer per cache line
+        // under concurrent stores and polls)
+        for (int slot : {0, 32, 64}) {
+          const int stride = slot == 0 ? 1 : slot / static_cast<int>(h->vb);
+          for (int as : {SPTRSV_ASSIGN_STATIC, SPTRSV_ASSIGN_XCD}) {
+            Config c{SPTRSV_ALGO_SELF, grp, epl, SPTRSV_SYNC_VALUE, 1, grid, as};
+            c.poll = poll;
+            c.stride = stride;
+            cand.push_back(c);
           }
-      }
-      for (int rpl : {1, 4})
-        cand.push_back({SPTRSV_ALGO_SELF, 0, epl, SPTRSV_SYNC_VALUE, rpl, ncu, SPTRSV_ASSIGN_TICKET});
-      if (epl == 1 || epl == 4)
-        cand.push_back({SPTRSV_ALGO_SELF, 0, epl, SPTRSV_SYNC_FLAG, 1, ncu, SPTRSV_ASSIGN_TICKET});
-    }
-    if (level_ok)
-      for (int rpl : {1, 4})
-        cand.push_back({SPTRSV_ALGO_LEVEL, 0, epl, SPTRSV_SYNC_VALUE, rpl, 0, SPTRSV_ASSIGN_TICKET});
+        }
+    for (int rpl : {1, 4})
+      cand.push_back({SPTRSV_ALGO_SELF, grp, epl, SPTRSV_SYNC_VALUE, rpl, ncu, SPTRSV_ASSIGN_TICKET});
+    cand.push_back({SPTRSV_ALGO_SELF, grp, epl, SPTRSV_SYNC_FLAG, 1, ncu, SPTRSV_ASSIGN_TICKET});
   }
+  if (level_ok)
+    for (int rpl : {1, 4})
+      cand.push_back({SPTRSV_ALGO_LEVEL, grp, epl, SPTRSV_SYNC_VALUE, rpl, 0, SPTRSV_ASSIGN_TICKET});
   if (h->algo == SPTRSV_ALGO_COLUMN_SELF)
-    for (int epl : {1, 2, 4, 8})
-      for (int grid : {ncu / 2, ncu, 2 * ncu, 4 * ncu})
-        for (int as : {SPTRSV_ASSIGN_STATIC, SPTRSV_ASSIGN_XCD})
-          cand.push_back({SPTRSV_ALGO_COLUMN_SELF, 0, epl, SPTRSV_SYNC_VALUE, 1, grid, as});
+    for (int grid : {ncu / 2, ncu, 2 * ncu, 4 * ncu})
+      for (int as : {SPTRSV_ASSIGN_STATIC, SPTRSV_ASSIGN_XCD})
+        cand.push_back({SPTRSV_ALGO_COLUMN_SELF, grp, epl, SPTRSV_SYNC_VALUE, 1, grid, as});
   if (h->algo == SPTRSV_ALGO_COLUMN_LEVEL)
-    for (int epl : {1, 2, 4, 8})
-      cand.push_back({SPTRSV_ALGO_COLUMN_LEVEL, 0, epl, SPTRSV_SYNC_VALUE, 1, 0, SPTRSV_ASSIGN_STATIC});
-  if (h->algo == SPTRSV_ALGO_AUTO || h->algo == SPTRSV_ALGO_BLOCK) {
+    cand.push_back({SPTRSV_ALGO_COLUMN_LEVEL, grp, epl, SPTRSV_SYNC_VALUE, 1, 0, SPTRSV_ASSIGN_STATIC});
+  const bool one_lane = grp == 1 || (grp == 0 && h->fwd.h.max_row_len <= epl);
+  if (h->algo == SPTRSV_ALGO_BLOCK || (h->algo == SPTRSV_ALGO_AUTO && one_lane)) {
     const int st0 = build_block(h, 0, stream);
     if (st0) return st0;
-    cand.push_back({SPTRSV_ALGO_BLOCK, 0, 4, SPTRSV_SYNC_VALUE, 1, 0, SPTRSV_ASSIGN_TICKET});
+    cand.push_back({SPTRSV_ALGO_BLOCK, grp, epl, SPTRSV_SYNC_VALUE, 1, 0, SPTRSV_ASSIGN_TICKET});
   }
   bool capturing = false;
   if (const int so = order_begin(h, stream, &capturing)) return so;
