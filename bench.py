@@ -58,6 +58,10 @@ def parse():
                     help="also run a plain device copy of this size (counter calibration)")
     ap.add_argument("--no-per-config", action="store_true",
                     help="skip the other workloads (C1, C3, C4a, C4b, C5) in the JSON line")
+    ap.add_argument("--configs", default="all",
+                    help="comma-separated per-configuration records to run (default all)")
+    ap.add_argument("--poll", type=int, default=None, help="fixed polling mode (with --no-tune)")
+    ap.add_argument("--xp-stride", type=int, default=None, help="fixed slot width (with --no-tune)")
     ap.add_argument("--suite", action="store_true")
     ap.add_argument("--setup", action="store_true",
                     help="also time the host and device setup routes (bench_setup.jsonl)")
@@ -186,6 +190,10 @@ def main():
                 h.set_option("grid", args.grid)
             if args.assign is not None:
                 h.set_option("assign", args.assign)
+            if args.poll is not None:
+                h.set_option("poll", args.poll)
+            if args.xp_stride is not None:
+                h.set_option("xp_stride", args.xp_stride)
         tuned = {"L": hL.info(), "U": hU.info()}
 
     def step(hl, hu, out1, out2):
@@ -367,7 +375,9 @@ def main():
         for h in (hL, hU, lvL, lvU):
             h.close()
         torch.cuda.synchronize()
-        out["per_config"] = bench_suite.per_config(sp, torch, args.steps, args.warmup, hop_same)
+        names = bench_suite.CONFIGS if args.configs == "all" else tuple(args.configs.split(","))
+        out["per_config"] = bench_suite.per_config(sp, torch, args.steps, args.warmup, hop_same,
+                                                   names=names, tune=not args.no_tune)
     if not args.no_cpu_baseline:
         t_cpu, reps = cpu_baseline(TL, TU, bL, args.cpu_seconds)
         model, ncpu, mhz = cpu_info()

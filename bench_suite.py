@@ -410,8 +410,22 @@ def _timed_handle(torch, make):
     return h, (time.perf_counter() - t0) * 1e3
 
 
-def pc_single(sp, torch, T, b, steps, warmup, hop_ns, dtype=None, tol=1e-12, block=False):
-    """One triangle, one right-hand side: self (tuned) vs level (tuned)."""
+# The schedules the autotuner usually picks for each workload (used instead
+# of tuning when the bench runs with --no-tune, e.g. under a profiler)
+FIXED_SCHEDULES = {
+    "c1_lap2d_64_lower": dict(algo=2, grid=256, assign=1),
+    "c3_powerlaw_1M_f64": dict(algo=2, grid=512, assign=2, poll=1, xp_stride=4),
+    "c3_powerlaw_1M_f32": dict(algo=2, grid=512, assign=2, poll=1, xp_stride=16),
+    "c4a_batched_256_ilu0_2d": dict(algo=2, grid=512, assign=2, poll=1),
+    "c4b_lap3d_128_lower_16rhs": dict(algo=2, grid=2048, assign=0, poll=1, multi_rows=1),
+    "c5_ilu0_3d_96_fwd_adjoint": dict(algo=2),
+}
+
+
+def pc_single(sp, torch, T, b, steps, warmup, hop_ns, dtype=None, tol=1e-12, block=False,
+              schedule=None):
+    """One triangle, one right-hand side: self (tuned, or `schedule`) vs
+    level (tuned, or its default)."""
     dtype = dtype or torch.float64
     o = oracle.get()
     vals64 = T.vals if dtype == torch.float64 else T.vals.astype(np.float32).astype(np.float64)
@@ -429,10 +443,13 @@ def pc_single(sp, torch, T, b, steps, warmup, hop_ns, dtype=None, tol=1e-12, blo
     hl = sp.Handle(*d, uplo=uplo).configure(algo=sp.ALGO_LEVEL)
     res["nlev"] = hs.info()["nlev"]
     hs.set_option("algo", sp.ALGO_SELF)
-    t0 = time.perf_counter()
-    hs.tune(bd, x)
-    res["tune_ms"] = round((time.perf_counter() - t0) * 1e3, 1)
-    hl.tune(bd, x)
+    if schedule is None:
+        t0 = time.perf_counter()
+        hs.tune(bd, x)
+        res["tune_ms"] = round((time.perf_counter() - t0) * 1e3, 1)
+        hl.tune(bd, x)
+    else:
+        hs.configure(**schedule)
     res["schedule_self"] = _schedule(hs.info())
     hands = [("self", hs), ("level", hl)]
     if block:
@@ -450,7 +467,7 @@ def pc_single(sp, torch, T, b, steps, warmup, hop_ns, dtype=None, tol=1e-12, blo
                    setup_host)
 
 
-def pc_batched(sp, torch, steps, warmup, hop_ns):
+def pc_batched(sp, torch, steps, warmup, hop_ns, schedule=None):
     o = oracle.get()
     tris, xs, bs = W.c4a_batch()
     devs = [_tri(torch, t) for t in tris]
@@ -466,8 +483,11 @@ def pc_batched(sp, torch, steps, warmup, hop_ns):
     hb = sp.BatchedHandle(*parts).configure(algo=sp.ALGO_BLOCK)
     res["nlev"] = hs.info()["nlev"]
     hs.set_option("algo", sp.ALGO_SELF)
-    hs.tune(bd, x)
-    hl.tune(bd, x)
+    if schedule is None:
+        hs.tune(bd, x)
+        hl.tune(bd, x)
+    else:
+        hs.configure(**schedule)
     res["schedule_self"] = _schedule(hs.info())
     xo = np.concatenate([o.solve(t.row_ptr, t.col_idx, t.vals, b) for t, b in zip(tris, bs)])
     for tag, h in (("self", hs), ("level", hl), ("block", hb)):
@@ -490,7 +510,7 @@ def pc_batched(sp, torch, steps, warmup, hop_ns):
     return _finish(res, lb_bytes(n, nnz), hop_ns, res["nlev"], setup_ms, setup_host, setup_host)
 
 
-def pc_multi(sp, torch, steps, warmup, hop_ns, nrhs=16):
+def pc_multi(sp, torch, steps, warmup, hop_ns, nrhs=16, schedule=None):
     o = oracle.get()
     T, X, B = W.c4b_multi(nrhs=nrhs)
     d = _tri(torch, T)
@@ -502,7 +522,10 @@ def pc_multi(sp, torch, steps, warmup, hop_ns, nrhs=16):
     hl = sp.Handle(*d).configure(algo=sp.ALGO_LEVEL)
     res["nlev"] = hs.info()["nlev"]
     Xo = o.solve_multi(T.row_ptr, T.col_idx, T.vals, B)
-    hs.tune_multi(Bd)
+    if schedule is None:
+        hs.tune_multi(Bd)
+    else:
+        hs.configure(**schedule)
     for tag, h in (("self", hs), ("level", hl)):
         h.solve_multi(Bd, out=Xd)
         h.status()
@@ -516,7 +539,7 @@ def pc_multi(sp, torch, steps, warmup, hop_ns, nrhs=16):
     return _finish(res, lb_bytes(T.n, T.nnz, 8, nrhs), hop_ns, res["nlev"], setup_ms)
 
 
-def pc_adjoint(sp, torch, steps, warmup, hop_ns, side=96):
+def pc_adjoint(sp, torch, steps, warmup, hop_ns, side=96, schedule=None):
     """Forward solve plus adjoint (transposed solve and gradient on the
     pattern) through torch.autograd, self vs level."""
     o = oracle.get()
@@ -562,22 +585,35 @@ def pc_adjoint(sp, torch, steps, warmup, hop_ns, side=96):
                    setup_ms["level"], setup_ms["host"])
 
 
-def per_config(sp, torch, steps, warmup, hop_ns):
-    """{config name: record} for C1, C3 (FP64, FP32), C4a, C4b and C5."""
+CONFIGS = ("c1_lap2d_64_lower", "c3_powerlaw_1M_f64", "c3_powerlaw_1M_f32",
+           "c4a_batched_256_ilu0_2d", "c4b_lap3d_128_lower_16rhs", "c5_ilu0_3d_96_fwd_adjoint")
+
+
+def per_config(sp, torch, steps, warmup, hop_ns, names=CONFIGS, tune=True):
+    """{config name: record} for C1, C3 (FP64, FP32), C4a, C4b and C5 (or the
+    subset `names`); tune=False uses FIXED_SCHEDULES instead of the tuner."""
     out = {}
-    T, _, b = W.c1_lap2d_64()
-    _log("per-config: c1")
-    out["c1_lap2d_64_lower"] = pc_single(sp, torch, T, b, steps, warmup, hop_ns, block=True)
-    T, _, b = W.c3_powerlaw()
-    _log("per-config: c3 f64")
-    out["c3_powerlaw_1M_f64"] = pc_single(sp, torch, T, b, steps, warmup, hop_ns)
-    _log("per-config: c3 f32")
-    out["c3_powerlaw_1M_f32"] = pc_single(sp, torch, T, b, steps, warmup, hop_ns,
-                                          dtype=torch.float32, tol=1e-5)
-    _log("per-config: c4a")
-    out["c4a_batched_256_ilu0_2d"] = pc_batched(sp, torch, steps, warmup, hop_ns)
-    _log("per-config: c4b")
-    out["c4b_lap3d_128_lower_16rhs"] = pc_multi(sp, torch, steps, warmup, hop_ns)
-    _log("per-config: c5")
-    out["c5_ilu0_3d_96_fwd_adjoint"] = pc_adjoint(sp, torch, steps, warmup, hop_ns)
+    c3 = None
+    for name in names:
+        if name not in CONFIGS:
+            raise ValueError("unknown configuration %r (one of %s)" % (name, ", ".join(CONFIGS)))
+        sched = None if tune else FIXED_SCHEDULES[name]
+        _log("per-config:", name)
+        if name == "c1_lap2d_64_lower":
+            T, _, b = W.c1_lap2d_64()
+            out[name] = pc_single(sp, torch, T, b, steps, warmup, hop_ns, block=True, schedule=sched)
+        elif name.startswith("c3_"):
+            if c3 is None:
+                c3 = W.c3_powerlaw()
+            T, _, b = c3
+            f32 = name.endswith("f32")
+            out[name] = pc_single(sp, torch, T, b, steps, warmup, hop_ns,
+                                  dtype=torch.float32 if f32 else None, tol=1e-5 if f32 else 1e-12,
+                                  schedule=sched)
+        elif name.startswith("c4a"):
+            out[name] = pc_batched(sp, torch, steps, warmup, hop_ns, schedule=sched)
+        elif name.startswith("c4b"):
+            out[name] = pc_multi(sp, torch, steps, warmup, hop_ns, schedule=sched)
+        else:
+            out[name] = pc_adjoint(sp, torch, steps, warmup, hop_ns, schedule=sched)
     return out
