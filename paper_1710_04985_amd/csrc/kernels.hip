@@ -717,27 +717,32 @@ k_self_multi(KArgs<T> a, const int* __restrict__ cstart, const int* __restrict__
 // level are scattered (in natural order, consecutive rows sit in consecutive
 // levels), so reading B and writing X inside the solve would touch a
 // separate cache line per value.  These passes move a tile of 64
-// consecutive rows through LDS instead: down the columns of B / X (64 rows
-// contiguous per column) and along the rows of bp / xp (nrhs values
-// contiguous per row).
-template <typename T>
+// consecutive rows and up to QC columns through LDS instead: down the
+// columns of B / X (64 rows contiguous per column) and along the rows of bp
+// / xp (the tile's columns contiguous per row).  The tile is only as wide as
+// the column count needs (QC = 8, 16, 32 or 64, one padding column against
+// bank conflicts), so narrow solves keep many workgroups per CU and enough
+// loads in flight to stream at close to the copy rate.
+template <typename T, int QC>
 __global__ void __launch_bounds__(256)
 k_multi_in(int n, int nrhs, int ld, const T* __restrict__ B, const int* __restrict__ row_pos,
            T* __restrict__ bp, T* __restrict__ xp, int fill, int* arrive) {
   using U = typename Bits<T>::U;
-  __shared__ T tile[64][65];
+  __shared__ T tile[64][QC + 1];
   const int i0 = blockIdx.x * 64, tid = threadIdx.x;
   if (blockIdx.x == 0 && tid == 0) *arrive = 0;
-  for (int q0 = 0; q0 < nrhs; q0 += 64) {
-    const int qc = nrhs - q0 < 64 ? nrhs - q0 : 64;
-    const int il = tid & 63;
+  const int il = tid & 63;
+  for (int q0 = 0; q0 < nrhs; q0 += QC) {
+    const int qc = nrhs - q0 < QC ? nrhs - q0 : QC;
     if (i0 + il < n)
-      for (int qq = tid >> 6; qq < qc; qq += 4)
-        tile[il][qq] = B[static_cast<int64_t>(q0 + qq) * ld + i0 + il];
+#pragma unroll
+      for (int qq = tid >> 6; qq < QC; qq += 4)
+        if (qq < qc) tile[il][qq] = B[static_cast<int64_t>(q0 + qq) * ld + i0 + il];
     __syncthreads();
-    for (int e = tid; e < 64 * qc; e += 256) {
+#pragma unroll
+    for (int e = tid; e < 64 * QC; e += 256) {
       const int r = e / qc, qq = e - r * qc;
-      if (i0 + r < n) {
+      if (r < 64 && i0 + r < n) {
         const int64_t o = static_cast<int64_t>(row_pos[i0 + r]) * nrhs + q0 + qq;
         bp[o] = tile[r][qq];
         if (fill) reinterpret_cast<U*>(xp)[o] = Bits<T>::kSentinel;
@@ -747,23 +752,26 @@ k_multi_in(int n, int nrhs, int ld, const T* __restrict__ B, const int* __restri
   }
 }
 
-template <typename T>
+template <typename T, int QC>
 __global__ void __launch_bounds__(256)
 k_multi_out(int n, int nrhs, int ld, const T* __restrict__ xp, const int* __restrict__ row_pos,
             T* __restrict__ X) {
-  __shared__ T tile[64][65];
+  __shared__ T tile[64][QC + 1];
   const int i0 = blockIdx.x * 64, tid = threadIdx.x;
-  for (int q0 = 0; q0 < nrhs; q0 += 64) {
-    const int qc = nrhs - q0 < 64 ? nrhs - q0 : 64;
-    for (int e = tid; e < 64 * qc; e += 256) {
+  const int il = tid & 63;
+  for (int q0 = 0; q0 < nrhs; q0 += QC) {
+    const int qc = nrhs - q0 < QC ? nrhs - q0 : QC;
+#pragma unroll
+    for (int e = tid; e < 64 * QC; e += 256) {
       const int r = e / qc, qq = e - r * qc;
-      if (i0 + r < n) tile[r][qq] = xp[static_cast<int64_t>(row_pos[i0 + r]) * nrhs + q0 + qq];
+      if (r < 64 && i0 + r < n)
+        tile[r][qq] = xp[static_cast<int64_t>(row_pos[i0 + r]) * nrhs + q0 + qq];
     }
     __syncthreads();
-    const int il = tid & 63;
     if (i0 + il < n)
-      for (int qq = tid >> 6; qq < qc; qq += 4)
-        X[static_cast<int64_t>(q0 + qq) * ld + i0 + il] = tile[il][qq];
+#pragma unroll
+      for (int qq = tid >> 6; qq < QC; qq += 4)
+        if (qq < qc) X[static_cast<int64_t>(q0 + qq) * ld + i0 + il] = tile[il][qq];
     __syncthreads();
   }
 }
@@ -1068,8 +1076,12 @@ template <typename T>
 hipError_t launch_multi_in(int n, int nrhs, int ld, const T* B, const int* row_pos, T* bp, T* xp,
                            bool fill, int* arrive, hipStream_t s) {
   if (n == 0 || nrhs == 0) return hipSuccess;
-  k_multi_in<T><<<(n + 63) / 64, 256, 0, s>>>(n, nrhs, ld, B, row_pos, bp, xp, fill ? 1 : 0,
-                                               arrive);
+  const dim3 grid((n + 63) / 64);
+  const int f = fill ? 1 : 0;
+  if (nrhs <= 8) k_multi_in<T, 8><<<grid, 256, 0, s>>>(n, nrhs, ld, B, row_pos, bp, xp, f, arrive);
+  else if (nrhs <= 16) k_multi_in<T, 16><<<grid, 256, 0, s>>>(n, nrhs, ld, B, row_pos, bp, xp, f, arrive);
+  else if (nrhs <= 32) k_multi_in<T, 32><<<grid, 256, 0, s>>>(n, nrhs, ld, B, row_pos, bp, xp, f, arrive);
+  else k_multi_in<T, 64><<<grid, 256, 0, s>>>(n, nrhs, ld, B, row_pos, bp, xp, f, arrive);
   return hipGetLastError();
 }
 
@@ -1077,7 +1089,11 @@ template <typename T>
 hipError_t launch_multi_out(int n, int nrhs, int ld, const T* xp, const int* row_pos, T* X,
                             hipStream_t s) {
   if (n == 0 || nrhs == 0) return hipSuccess;
-  k_multi_out<T><<<(n + 63) / 64, 256, 0, s>>>(n, nrhs, ld, xp, row_pos, X);
+  const dim3 grid((n + 63) / 64);
+  if (nrhs <= 8) k_multi_out<T, 8><<<grid, 256, 0, s>>>(n, nrhs, ld, xp, row_pos, X);
+  else if (nrhs <= 16) k_multi_out<T, 16><<<grid, 256, 0, s>>>(n, nrhs, ld, xp, row_pos, X);
+  else if (nrhs <= 32) k_multi_out<T, 32><<<grid, 256, 0, s>>>(n, nrhs, ld, xp, row_pos, X);
+  else k_multi_out<T, 64><<<grid, 256, 0, s>>>(n, nrhs, ld, xp, row_pos, X);
   return hipGetLastError();
 }
 
