@@ -95,9 +95,10 @@ typedef enum {
     SPTRSV_ALGO_BLOCK = 3,  /* level-scheduled inside one workgroup per independent
                                system (each system of a batched handle; the whole
                                triangle otherwise): the level barrier is a workgroup
-                               barrier, not a launch; x of a system is kept in LDS when
-                               the largest system fits.  One right-hand side (several:
-                               the level-scheduled solve is used). */
+                               barrier, not a launch; a system's whole level-ordered
+                               copy, or else its x, is kept in LDS when the largest system
+                               fits (SPTRSV_OPT_BLOCK_RESIDENT).  One right-hand side
+                               (several: the level-scheduled solve is used). */
     SPTRSV_ALGO_COLUMN_LEVEL = 4, /* column-wise, level-scheduled (Sec. 3.2 sweep, Sec. 4.1
                                LEVC): one launch per level; each finished x_k is pushed
                                into the accumulators of the rows depending on it with
@@ -153,12 +154,19 @@ typedef enum {
                                      lanes, else 1).  A wavefront issues the gathers of all
                                      its rows before it waits on any, so larger values mean
                                      fewer waits per level.  Results do not depend on it */
-    SPTRSV_OPT_RESIDENCY_LIMIT = 13  /* polls a wavefront of a cooperatively launched (static)
+    SPTRSV_OPT_RESIDENCY_LIMIT = 13, /* polls a wavefront of a cooperatively launched (static)
                                      schedule waits at its start for the rest of the grid to
                                      sign in (default 2^20); the grid gives up with
                                      SPTRSV_ERR_NOT_RESIDENT if it never fills.  0 makes every
                                      wavefront but the last to arrive give up at once (a test
                                      hook that forces the failure) */
+    SPTRSV_OPT_BLOCK_RESIDENT = 14 /* SPTRSV_ALGO_BLOCK: 1 (default) keeps each system's whole
+                                     level-ordered copy (b/x, 1/diagonal, off-diagonal values,
+                                     16-bit local indices) in LDS when every system fits (at
+                                     most 65,535 rows and off-diagonals per system and the
+                                     device's per-workgroup LDS), so its levels touch no global
+                                     memory; 0 keeps only x there and streams the row data.
+                                     Same results either way */
 } sptrsv_option;
 
 typedef enum {

@@ -331,6 +331,22 @@ void build_block_plan(const HostPlan& f, const std::vector<int>& seg_row0, HostP
   info.seg_base[nseg] = static_cast<int>(info.lev_pos.size());
 }
 
+int64_t block_resident_bytes(const HostPlan& p, const BlockInfo& info, int vb) {
+  int64_t best = 0;
+  const int nseg = static_cast<int>(info.seg_base.size()) - 1;
+  for (int s = 0; s < nseg; ++s) {
+    const int lb = info.seg_base[s], nl = info.seg_base[s + 1] - lb - 1;
+    if (nl <= 0) continue;
+    const int q0 = info.lev_pos[lb], q1 = info.lev_pos[lb + nl];
+    const int64_t ns = q1 - q0;
+    const int64_t ne = static_cast<int64_t>(p.off_ptr[q1]) - p.off_ptr[q0];
+    if (ns > 65535 || ne > 65535) return -1;
+    const int64_t bytes = vb * (2 * ns + ne) + 2 * (ns + 1) + 2 * ne + 2 * (nl + 1);
+    best = std::max(best, bytes);
+  }
+  return best;
+}
+
 void build_wave_lists(const ChunkTable& t, int W, int regions, std::vector<int>& ptr,
                       std::vector<int>& list) {
   const int nch = static_cast<int>(t.start.size());

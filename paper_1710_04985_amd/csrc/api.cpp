@@ -65,6 +65,10 @@ struct PlanState {
   std::map<std::tuple<int, int, int, int>, ChunkEntry> chunks;
 };
 
+// Workgroup of the resident block kernel (SPTRSV_OPT_BLOCK_RESIDENT): the
+// copy in and out of LDS takes every thread, the level walk one wavefront.
+constexpr int kResidentThreads = 1024;
+
 // Block-ordered plan (SPTRSV_ALGO_BLOCK) of one direction, on the device.
 struct BlockState {
   bool built = false;
@@ -73,6 +77,7 @@ struct BlockState {
   int* seg_row0 = nullptr;
   int* seg_base = nullptr;
   int* lev_pos = nullptr;
+  int64_t res_bytes = -1;   // LDS bytes of the resident kernel (-1: some system needs wider indices)
   ChunkEntry dummy;   // unused chunk table (the block kernel needs none)
 };
 
@@ -128,6 +133,7 @@ struct sptrsv_handle_s {
   int device = 0;
   int num_cu = 256;
   int lds_limit = 65536;          // bytes of LDS one workgroup may use
+  int block_resident = 1;         // block schedule: whole system in LDS when it fits
   std::vector<int> rp_h, col_h;   // caller's pattern (host copy)
   PlanState fwd, trn;
   // device setup: the handle's own device copy of the pattern (for T^T and
@@ -463,6 +469,7 @@ int build_block(sptrsv_handle_t h, int dir, hipStream_t s) {
   else
     seg_row0.push_back(h->n);
   build_block_plan(base.h, seg_row0, b.ps.h, b.info);
+  b.res_bytes = block_resident_bytes(b.ps.h, b.info, h->vb);
   int st = upload_plan(b.ps, h->vb, s);
   if (!st) st = upload_ints(&b.seg_row0, b.info.seg_row0, s);
   if (!st) st = upload_ints(&b.seg_base, b.info.seg_base, s);
@@ -905,10 +912,17 @@ int solve_impl(sptrsv_handle_t h, PlanState& ps, const Config& c_in, const void*
     const size_t lds_bytes = static_cast<size_t>(bs.info.max_rows) * sizeof(T);
     const int lds_rows = lds_bytes <= static_cast<size_t>(h->lds_limit) ? bs.info.max_rows : 0;
     const int nseg = static_cast<int>(bs.info.seg_row0.size()) - 1;
+    // whole systems in LDS when they fit and one wavefront takes every level
+    // (with wider levels the streamed kernel's barrier loop was faster)
+    const bool resident = h->block_resident && bs.res_bytes > 0 &&
+                          bs.res_bytes <= h->lds_limit && bs.info.max_level <= 64;
     timing_begin(h, s, &stop, ext.no_alloc);
-    if (launch_block<T>(a, bs.seg_row0, bs.seg_base, bs.lev_pos, nseg, threads, lds_rows, s) !=
-        hipSuccess)
-      return kErrHip;
+    const hipError_t le =
+        resident ? launch_block_res<T>(a, bs.seg_base, bs.lev_pos, nseg, kResidentThreads,
+                                       static_cast<int>(bs.res_bytes), s)
+                 : launch_block<T>(a, bs.seg_row0, bs.seg_base, bs.lev_pos, nseg, threads,
+                                   lds_rows, s);
+    if (le != hipSuccess) return kErrHip;
     timing_end(s, stop);
     return kOk;
   }
@@ -1066,6 +1080,12 @@ int init_handle_common(sptrsv_handle_t h, hipStream_t s) {
           hipSuccess &&
       lds > 0)
     h->lds_limit = lds;
+  // a kernel may opt in to more than the default per-workgroup LDS
+  int optin = 0;
+  if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, h->device) ==
+          hipSuccess &&
+      optin > h->lds_limit)
+    h->lds_limit = optin;
   int err = kOk;
   h->scratch.ticket = dalloc<int>(1, &err);
   h->scratch.status = dalloc<int>(1, &err);
@@ -1581,6 +1601,10 @@ int sptrsv_set_option(sptrsv_handle_t h, sptrsv_option key, int64_t v) {
       if (v < 0 || v > INT32_MAX) return kErrInvalidArg;
       h->res_limit = static_cast<int>(v);
       return kOk;
+    case SPTRSV_OPT_BLOCK_RESIDENT:
+      if (v != 0 && v != 1) return kErrInvalidArg;
+      h->block_resident = static_cast<int>(v);
+      return kOk;
   }
   return kErrInvalidArg;
 }
@@ -1602,6 +1626,7 @@ int sptrsv_get_option(sptrsv_handle_t h, sptrsv_option key, int64_t* v) {
     case SPTRSV_OPT_XP_STRIDE: *v = h->xp_stride; return kOk;
     case SPTRSV_OPT_MULTI_ROWS: *v = h->mrows; return kOk;
     case SPTRSV_OPT_RESIDENCY_LIMIT: *v = h->res_limit; return kOk;
+    case SPTRSV_OPT_BLOCK_RESIDENT: *v = h->block_resident; return kOk;
   }
   return kErrInvalidArg;
 }

@@ -890,6 +890,192 @@ k_block(KArgs<T> a, const int* __restrict__ seg_row0, const int* __restrict__ se
   }
 }
 
+// ------------------------------------- block, whole system resident in LDS
+// The block schedule for systems small enough to live entirely in LDS: the
+// workgroup first copies its system's level-ordered data there (values,
+// dependency positions and row offsets as 16-bit indices local to the
+// system, 1/diagonal, and b, which the solution then overwrites in place:
+// row p's b is read only by row p, before its x is stored), then walks the
+// levels touching LDS only; x goes to the caller's vector at the end.  A
+// lane's row of each level moves through three stages, one level apart, so
+// that the loads of a level depend only on values loaded one level earlier
+// and a level costs one LDS gather and the row's FMAs:
+//   bounds: the row's position, from the level bounds (two levels ahead)
+//   row:    its entry range, 1/diagonal and b (one level ahead)
+//   entries: its first four dependency positions and values (next level)
+// Same arithmetic as every one-lane-per-row solve: entries in stored order,
+// FMA from zero, (b - sum) * (1/diagonal).
+struct ResBounds {   // bounds stage: raw level bounds
+  int m, q0, q1;
+};
+template <typename T> struct ResRowB {   // row stage: raw
+  int m, q0, q1, e, e1;
+  T d, bi;
+};
+template <typename T> struct ResRowC {   // entries stage: raw
+  int m, q0, q1, e, e1;
+  T d, bi;
+  int j[4];
+  T v[4];
+};
+
+template <typename T>
+__global__ void __launch_bounds__(1024)
+k_block_res(KArgs<T> a, const int* __restrict__ seg_base, const int* __restrict__ lev_pos) {
+  extern __shared__ __align__(16) unsigned char blk_smem[];
+  const int lb = seg_base[blockIdx.x];
+  const int nl = seg_base[blockIdx.x + 1] - lb - 1;   // levels of this system (-1 if empty)
+  if (nl <= 0) return;
+  const int tid = threadIdx.x, NT = blockDim.x;
+  const int p0 = lev_pos[lb];
+  const int ns = lev_pos[lb + nl] - p0;
+  const int e0 = a.off_ptr[p0];
+  const int ne = a.off_ptr[p0 + ns] - e0;
+  T* xv = reinterpret_cast<T*>(blk_smem);       // [ns] b, then x, by local position
+  T* dv = xv + ns;                              // [ns] 1/diagonal
+  T* vv = dv + ns;                              // [ne] off-diagonal values
+  unsigned short* rp = reinterpret_cast<unsigned short*>(vv + ne);   // [ns+1] entry offsets
+  unsigned short* cp = rp + ns + 1;             // [ne] local position of each dependency
+  unsigned short* lp = cp + ne;                 // [nl+1] level bounds
+  // staging: U rows / entries per thread in flight (clamped in-range indices
+  // for the loads of a batch's missing tail, whose results are dropped)
+  constexpr int U = 4;
+  for (int base = tid; base < ns; base += NT * U) {
+    int pr[U], op[U];
+    T dd[U], bb[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int p = base + u * NT;
+      const int pc = p < ns ? p : ns - 1;
+      pr[u] = a.pos_row[p0 + pc];
+      dd[u] = a.dinv[p0 + pc];
+      op[u] = a.off_ptr[p0 + pc];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) bb[u] = a.b[pr[u]];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int p = base + u * NT;
+      if (p < ns) {
+        xv[p] = bb[u];
+        dv[p] = dd[u];
+        rp[p] = static_cast<unsigned short>(op[u] - e0);
+      }
+    }
+  }
+  for (int base = tid; base < ne; base += NT * 2 * U) {
+    int cc[2 * U];
+    T va[2 * U];
+#pragma unroll
+    for (int u = 0; u < 2 * U; ++u) {
+      const int e = base + u * NT;
+      const int ec = e < ne ? e : ne - 1;
+      va[u] = a.off_val[e0 + ec];
+      cc[u] = a.off_pos[e0 + ec];
+    }
+#pragma unroll
+    for (int u = 0; u < 2 * U; ++u) {
+      const int e = base + u * NT;
+      if (e < ne) {
+        vv[e] = va[u];
+        cp[e] = static_cast<unsigned short>(cc[u] - p0);
+      }
+    }
+  }
+  for (int m = tid; m <= nl; m += NT) lp[m] = static_cast<unsigned short>(lev_pos[lb + m] - p0);
+  if (tid == 0) rp[ns] = static_cast<unsigned short>(ne);
+  __syncthreads();
+  const int elast = ne > 0 ? ne - 1 : 0;
+  // Each stage only loads: what it loaded is tested (is there a row, is the
+  // entry the row's) one level later, so no stage waits for its own loads.
+  // bounds stage: level m's position range (clamped past the last level)
+  auto stage_bounds = [&](int m) {
+    const int mc = m < nl ? m : nl - 1;
+    return ResBounds{m, lp[mc], lp[mc + 1]};
+  };
+  // this thread's first row of the level, or -1
+  auto row_of = [&](int m, int q0, int q1) {
+    const int p = q0 + tid;
+    return m < nl && p < q1 ? p : -1;
+  };
+  // row stage (reads b of a row two levels before that row is solved)
+  auto stage_row = [&](const ResBounds& bd) {
+    const int p = row_of(bd.m, bd.q0, bd.q1);
+    const int pc = p >= 0 ? p : 0;
+    return ResRowB<T>{bd.m, bd.q0, bd.q1, rp[pc], rp[pc + 1], dv[pc], xv[pc]};
+  };
+  // entries stage: four loads at once, clamped in range
+  auto stage_entries = [&](const ResRowB<T>& r) {
+    ResRowC<T> c{r.m, r.q0, r.q1, r.e, r.e1, r.d, r.bi, {}, {}};
+    const bool live = row_of(r.m, r.q0, r.q1) >= 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int ee = live ? r.e + q : elast;
+      const int ec = ee < elast ? ee : elast;
+      c.j[q] = cp[ec];
+      c.v[q] = vv[ec];
+    }
+    return c;
+  };
+  // the levels, walked by the first `nt` threads (one wavefront)
+  auto walk = [&](int nt) {
+    ResRowC<T> sc = stage_entries(stage_row(stage_bounds(0)));
+    ResRowB<T> sb = stage_row(stage_bounds(1));
+    ResBounds sa = stage_bounds(2);
+    for (int m = 0; m < nl; ++m) {
+      // gather of level m first: the stage loads below do not wait for it
+      const int p = row_of(sc.m, sc.q0, sc.q1);
+      bool ok[4];
+      T xg[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        ok[q] = p >= 0 && sc.e + q < sc.e1;
+        xg[q] = xv[ok[q] ? sc.j[q] : 0];
+      }
+      const ResRowC<T> nc = stage_entries(sb);     // level m+1
+      const ResRowB<T> nb = stage_row(sa);         // level m+2 (its b is not written yet)
+      const ResBounds na = stage_bounds(m + 3);
+      if (p >= 0) {
+        T sum = T(0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (ok[q]) sum = fma_t(sc.v[q], xg[q], sum);
+        for (int e = sc.e + 4; e < sc.e1; ++e) sum = fma_t(vv[e], xv[cp[e]], sum);
+        xv[p] = canonical((sc.bi - sum) * sc.d);
+      }
+      // rows of this level beyond the first nt, not staged ahead
+      for (int r = sc.q0 + tid + nt; r < sc.q1; r += nt) {
+        T sum = T(0);
+        for (int e = rp[r]; e < rp[r + 1]; ++e) sum = fma_t(vv[e], xv[cp[e]], sum);
+        xv[r] = canonical((xv[r] - sum) * dv[r]);
+      }
+      __builtin_amdgcn_wave_barrier();   // keeps the level's LDS accesses in order
+      sc = nc;
+      sb = nb;
+      sa = na;
+    }
+  };
+  // Wavefront 0 walks the levels with no barrier: the LDS performs one
+  // wavefront's accesses in issue order, so a value stored at level m is what
+  // a lane of level m+1 reads.  (Rows of a level beyond its 64 lanes are
+  // solved one pass after another; the library picks this kernel when every
+  // level fits.)  The other wavefronts wait at the barrier below and help with
+  // the copy out.
+  if (tid < 64) walk(64);
+  __syncthreads();
+  for (int base = tid; base < ns; base += NT * U) {
+    int pr[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int p = base + u * NT;
+      pr[u] = a.pos_row[p0 + (p < ns ? p : ns - 1)];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (base + u * NT < ns) a.x[pr[u]] = xv[base + u * NT];
+  }
+}
+
 // ------------------------------------------------------ self, flag sync
 // Rows of a chunk: wait for the flags of all their dependencies, acquire,
 // solve reading the caller's x (same per-row order as solve_chunk), release,
@@ -1160,6 +1346,17 @@ hipError_t launch_block(const SolveArgs& sa, const int* seg_row0, const int* seg
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_block_res(const SolveArgs& sa, const int* seg_base, const int* lev_pos, int nseg,
+                           int threads, int lds_bytes, hipStream_t s) {
+  if (nseg == 0) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_block_res<T>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+  if (e != hipSuccess) return e;
+  k_block_res<T><<<nseg, threads, lds_bytes, s>>>(make_args<T>(sa), seg_base, lev_pos);
+  return hipGetLastError();
+}
+
 template <typename T> hipError_t launch_self_flag(const SolveArgs& sa, hipStream_t s) {
   if (sa.chunks->count == 0) return hipSuccess;
   k_self_flag<T><<<sa.grid, sa.wg, 0, s>>>(make_args<T>(sa));
@@ -1213,6 +1410,8 @@ template <typename T> int self_multi_blocks_per_cu(int wg, int rows) {
   template hipError_t launch_self_static<T>(const SolveArgs&, hipStream_t);                      \
   template hipError_t launch_block<T>(const SolveArgs&, const int*, const int*, const int*, int, \
                                       int, int, hipStream_t);                                    \
+  template hipError_t launch_block_res<T>(const SolveArgs&, const int*, const int*, int, int, int, \
+                                          hipStream_t);                                          \
   template hipError_t launch_grad_vals<T>(int, const int*, const int*, int, const T*, const T*,  \
                                           T*, hipStream_t);                                      \
   template int self_value_blocks_per_cu<T>(int);                                                 \

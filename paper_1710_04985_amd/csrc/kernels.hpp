@@ -102,6 +102,12 @@ template <typename T> hipError_t launch_self_static(const SolveArgs& a, hipStrea
 template <typename T> hipError_t launch_block(const SolveArgs& a, const int* seg_row0,
                                               const int* seg_base, const int* lev_pos, int nseg,
                                               int threads, int lds_rows, hipStream_t s);
+// one workgroup of `threads` per independent system, each system's whole
+// level-ordered copy in `lds_bytes` of LDS (block_resident_bytes): all
+// threads copy it in and out, one wavefront walks the levels
+template <typename T> hipError_t launch_block_res(const SolveArgs& a, const int* seg_base,
+                                                  const int* lev_pos, int nseg, int threads,
+                                                  int lds_bytes, hipStream_t s);
 template <typename T> hipError_t launch_grad_vals(int n, const int* row_ptr, const int* col,
                                                   int unit_diag, const T* grad_b, const T* x,
                                                   T* grad_vals, hipStream_t s);

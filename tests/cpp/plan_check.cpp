@@ -1,6 +1,7 @@
 // CPU check of the library's level-ordered layout and work chunks (the
 // indexing every solve kernel relies on).  Built with g++ together with the
 // library's host analysis source; called from tests/test_plan_cpu.py.
+#include <cmath>
 #include <cstdint>
 #include <vector>
 
@@ -109,5 +110,88 @@ extern "C" int check_plan(int n, const int* rp, const int* col, int upper, int u
         }
     }
   }
+  return 0;
+}
+
+// Model of the resident block kernel (one workgroup per system, the whole
+// system in LDS) on the CPU: the same byte layout, staging and level loop,
+// with every LDS access bounds-checked against the size the library
+// requests (block_resident_bytes).  Values are synthetic (entry e of the
+// block plan weighs 1/(e+2), b[row] = row+1, 1/diagonal = 1/2); the result is
+// compared bit for bit with plain substitution in the block plan's order.
+// Returns 0, or the number of the violated check; *bytes gets the LDS size.
+extern "C" int check_block_resident(int n, const int* rp, const int* col, int upper, int nseg,
+                                    const int* seg_row0_in, int vb, long long* bytes) {
+  HostPlan f;
+  build_plan(n, rp, col, nullptr, upper != 0, false, f);
+  std::vector<int> seg_row0(seg_row0_in, seg_row0_in + nseg + 1);
+  HostPlan p;
+  BlockInfo info;
+  build_block_plan(f, seg_row0, p, info);
+  const int64_t need = block_resident_bytes(p, info, vb);
+  *bytes = need;
+  if (need < 0) return 0;   // not eligible: nothing to model
+  std::vector<double> b(n), x(n, 0.0), xref(n, 0.0);
+  for (int i = 0; i < n; ++i) b[i] = i + 1.0;
+  auto val = [](int64_t e) { return 1.0 / static_cast<double>(e + 2); };
+  const double dinv = 0.5;
+  for (int s = 0; s < nseg; ++s) {
+    const int lb = info.seg_base[s], nl = info.seg_base[s + 1] - lb - 1;
+    if (nl <= 0) continue;
+    const int p0 = info.lev_pos[lb], ns = info.lev_pos[lb + nl] - p0;
+    const int e0 = p.off_ptr[p0], ne = p.off_ptr[p0 + ns] - e0;
+    // byte layout of the kernel: T xv[ns], T dv[ns], T vv[ne], u16 rp[ns+1], u16 cp[ne], u16 lp[nl+1]
+    const int64_t o_xv = 0, o_dv = o_xv + int64_t(vb) * ns, o_vv = o_dv + int64_t(vb) * ns;
+    const int64_t o_rp = o_vv + int64_t(vb) * ne, o_cp = o_rp + 2 * int64_t(ns + 1);
+    const int64_t o_lp = o_cp + 2 * int64_t(ne), end = o_lp + 2 * int64_t(nl + 1);
+    if (end > need) return 40;
+    std::vector<double> xv(ns), dv(ns), vv(ne);
+    std::vector<int> lrp(ns + 1), lcp(ne), llp(nl + 1);
+    for (int q = 0; q < ns; ++q) {
+      const int r = p.pos_row[p0 + q];
+      if (r < seg_row0[s] || r >= seg_row0[s + 1]) return 41;
+      xv[q] = b[r];
+      dv[q] = dinv;
+      const int off = p.off_ptr[p0 + q] - e0;
+      if (off < 0 || off > 65535) return 42;
+      lrp[q] = off;
+    }
+    lrp[ns] = ne;
+    for (int e = 0; e < ne; ++e) {
+      vv[e] = val(e0 + e);
+      const int c = p.off_pos[e0 + e] - p0;
+      if (c < 0 || c >= ns || c > 65535) return 43;
+      lcp[e] = c;
+    }
+    for (int m = 0; m <= nl; ++m) {
+      const int v = info.lev_pos[lb + m] - p0;
+      if (v < 0 || v > ns || v > 65535) return 44;
+      llp[m] = v;
+    }
+    for (int q = 0; q < ns; ++q)
+      if (lrp[q] > lrp[q + 1]) return 45;
+    for (int m = 0; m < nl; ++m) {
+      if (llp[m] >= llp[m + 1]) return 46;
+      for (int q = llp[m]; q < llp[m + 1]; ++q) {
+        double sum = 0.0;
+        for (int e = lrp[q]; e < lrp[q + 1]; ++e) {
+          // a dependency must come from an earlier level of the same system
+          if (lcp[e] >= llp[m]) return 47;
+          sum = std::fma(vv[e], xv[lcp[e]], sum);
+        }
+        xv[q] = (xv[q] - sum) * dv[q];
+      }
+    }
+    for (int q = 0; q < ns; ++q) x[p.pos_row[p0 + q]] = xv[q];
+    // plain substitution over the block plan, global indices
+    for (int q = p0; q < p0 + ns; ++q) {
+      double sum = 0.0;
+      for (int e = p.off_ptr[q]; e < p.off_ptr[q + 1]; ++e)
+        sum = std::fma(val(e), xref[p.off_col[e]], sum);
+      xref[p.pos_row[q]] = (b[p.pos_row[q]] - sum) * dinv;
+    }
+  }
+  for (int i = 0; i < n; ++i)
+    if (x[i] != xref[i]) return 48;
   return 0;
 }

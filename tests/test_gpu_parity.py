@@ -44,6 +44,7 @@ def _small_cases():
 CASES = _small_cases()
 SCHEDULES = [("level", dict(algo=1)), ("self_value", dict(algo=2, sync=0)),
              ("block", dict(algo=3)), ("block_wg_ignored", dict(algo=3, group=4)),
+             ("block_streamed", dict(algo=3, block_resident=0)),
              ("self_ticket", dict(algo=2, sync=0, assign=1)),
              ("self_static_g4_grid3", dict(algo=2, sync=0, assign=0, group=4, grid=3)),
              ("self_static_wg256", dict(algo=2, sync=0, assign=0, wg=256, grid=2)),
@@ -400,6 +401,34 @@ def test_batched(sp):
     for t, b in zip(tris, bs):
         assert relerr(x[off:off + t.n], o.solve(t.row_ptr, t.col_idx, t.vals * 0.5, b)) <= TOL64
         off += t.n
+
+
+def test_block_resident_matches_streamed(sp):
+    """Whole systems in LDS (the 2-D 64x64 triangle; a batch of small ILU(0)
+    and mesh factors) against the streamed block kernel bit for bit, both
+    directions, and against the oracle."""
+    o = oracle.get()
+    for tris in ([W.c1_lap2d_64()[0]],
+                 [W.ilu0_lower((9, 14)), W.laplacian_triangle((5, 4, 3)), W.ilu0_lower((30, 31)),
+                  W.ilu0_lower((1, 1))]):
+        devs = [dev_tri(t) for t in tris]
+        bs = [W.uniform_vector(t.n, 80 + i) for i, t in enumerate(tris)]
+        bb = dev(np.concatenate(bs))
+        mk = lambda **kw: sp.BatchedHandle([d[0] for d in devs], [d[1] for d in devs],
+                                           [d[2] for d in devs]).configure(algo=3, **kw)
+        hr, hs = mk(), mk(block_resident=0)
+        assert hr.get_option("block_resident") == 1 and hs.get_option("block_resident") == 0
+        x, xt = hr.solve(bb), hr.solve_t(bb)
+        assert bits_equal(x, hs.solve(bb)) and bits_equal(xt, hs.solve_t(bb))
+        x, xt = host(x), host(xt)
+        off = 0
+        for t, b in zip(tris, bs):
+            assert relerr(x[off:off + t.n], o.solve(t.row_ptr, t.col_idx, t.vals, b)) <= TOL64
+            assert relerr(xt[off:off + t.n],
+                          o.solve_transpose(t.row_ptr, t.col_idx, t.vals, b)) <= TOL64
+            off += t.n
+        hr.status()
+        hs.status()
 
 
 def test_block_global_x_path(sp):
