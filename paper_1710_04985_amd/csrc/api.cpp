@@ -941,9 +941,13 @@ int solve_impl(sptrsv_handle_t h, PlanState& ps, const Config& c_in, const void*
   };
   if (level) {
     timing_begin(h, s, &stop, ext.no_alloc);
+    // one lane per row everywhere and one right-hand side: a thread per row,
+    // straight from the level's position range
+    const bool flat = !multi && ch->max_lg == 0;
     for (int m = 0; m < ps.h.nlev; ++m) {
-      const int cb = ch->level_chunk[m], ce = ch->level_chunk[m + 1];
-      const hipError_t e = launch_level<T>(a, cb, ce, s);
+      const hipError_t e =
+          flat ? launch_level_flat<T>(a, ps.h.pos_ilev[m], ps.h.pos_ilev[m + 1], s)
+               : launch_level<T>(a, ch->level_chunk[m], ch->level_chunk[m + 1], s);
       if (e != hipSuccess) return kErrHip;
     }
     timing_end(s, stop);

@@ -400,6 +400,42 @@ __global__ void __launch_bounds__(256) k_level(KArgs<T> a, int chunk_begin, int 
   else solve_chunk<T, false>(a, a.chunk_start[c], a.chunk_meta[c], lane);
 }
 
+// Level-scheduled, one lane per row, one right-hand side: the rows of a
+// level are the positions [k0, k1), one per thread, so no chunk descriptor
+// sits in front of the row's loads.  Same per-row arithmetic as solve_chunk
+// with one lane per row (first four entries, then the rest of the row in
+// order, FMA from zero).
+template <typename T>
+__global__ void __launch_bounds__(256) k_level_flat(KArgs<T> a, int k0, int k1) {
+  const int k = k0 + static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
+  if (k >= k1) return;
+  const int e0 = a.off_ptr[k], e1 = a.off_ptr[k + 1];
+  const int i = a.pos_row[k];
+  const T d = a.dinv[k];
+  int j[4];
+  T v[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int ee = e0 + q;
+    j[q] = ee < e1 ? a.off_pos[ee] : -1;
+    v[q] = ee < e1 ? a.off_val[ee] : T(0);
+  }
+  const T bi = a.b[i];
+  T xv[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) xv[q] = j[q] >= 0 ? a.xp[j[q]] : T(0);
+  T sum = T(0);
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (j[q] >= 0) sum = fma_t(v[q], xv[q], sum);
+  if (e1 > e0 + 4)
+    sum = row_dot<T, false>(a.off_pos, a.off_val, e0 + 4, e1, 1, a.xp, 1, a.spin_limit, a.status,
+                            false, sum);
+  const T xi = canonical((bi - sum) * d);
+  a.xp[k] = xi;
+  a.x[i] = xi;
+}
+
 // ------------------------------------------------ self, value sync, ticket
 template <typename T, bool kMulti>
 __global__ void __launch_bounds__(256) k_self_value(KArgs<T> a) {
@@ -1290,6 +1326,13 @@ hipError_t launch_row_pos(int n, const int* pos_row, int* row_pos, hipStream_t s
 }
 
 template <typename T>
+hipError_t launch_level_flat(const SolveArgs& sa, int k0, int k1, hipStream_t s) {
+  if (k1 <= k0) return hipSuccess;
+  k_level_flat<T><<<blocks_for(k1 - k0, 256, 1 << 30), 256, 0, s>>>(make_args<T>(sa), k0, k1);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_level(const SolveArgs& sa, int cb, int ce, hipStream_t s) {
   if (ce <= cb) return hipSuccess;
   const int wpb = sa.wg / 64;
@@ -1410,6 +1453,7 @@ template <typename T> int self_multi_blocks_per_cu(int wg, int rows) {
   template hipError_t launch_self_static<T>(const SolveArgs&, hipStream_t);                      \
   template hipError_t launch_block<T>(const SolveArgs&, const int*, const int*, const int*, int, \
                                       int, int, hipStream_t);                                    \
+  template hipError_t launch_level_flat<T>(const SolveArgs&, int, int, hipStream_t);          \
   template hipError_t launch_block_res<T>(const SolveArgs&, const int*, const int*, int, int, int, \
                                           hipStream_t);                                          \
   template hipError_t launch_grad_vals<T>(int, const int*, const int*, int, const T*, const T*,  \

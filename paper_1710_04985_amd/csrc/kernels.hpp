@@ -92,6 +92,10 @@ template <typename T> hipError_t launch_level(const SolveArgs& a, int chunk_begi
 // self-scheduled, value sync, chunks claimed from a ticket (any nrhs)
 template <typename T> hipError_t launch_self_value(const SolveArgs& a, hipStream_t s);
 // self-scheduled, flag sync, ticket (one right-hand side; reads and writes x)
+// level-scheduled, one lane per row, one right-hand side: positions [k0, k1)
+// of one level, a thread per row
+template <typename T> hipError_t launch_level_flat(const SolveArgs& a, int k0, int k1,
+                                                   hipStream_t s);
 template <typename T> hipError_t launch_self_flag(const SolveArgs& a, hipStream_t s);
 // self-scheduled, value sync, static round-robin chunks over a cooperative
 // (all-resident) grid, pipelined (any nrhs: several take k_self_multi with
