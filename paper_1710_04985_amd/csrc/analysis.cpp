@@ -341,7 +341,7 @@ int64_t block_resident_bytes(const HostPlan& p, const BlockInfo& info, int vb) {
     const int64_t ns = q1 - q0;
     const int64_t ne = static_cast<int64_t>(p.off_ptr[q1]) - p.off_ptr[q0];
     if (ns > 65535 || ne > 65535) return -1;
-    const int64_t bytes = vb * (2 * ns + ne) + 2 * (ns + 1) + 2 * ne + 2 * (nl + 1);
+    const int64_t bytes = vb * (2 * ns + ne + 2) + 2 * (ns + 1) + 2 * (ne + 1) + 2 * (nl + 1);
     best = std::max(best, bytes);
   }
   return best;

@@ -127,7 +127,8 @@ void build_block_plan(const HostPlan& f, const std::vector<int>& seg_row0, HostP
 
 // LDS bytes the resident block kernel needs for the largest system of a block
 // plan (values of vb bytes: b/x, 1/diagonal and off-diagonals; 16-bit row
-// offsets, dependency positions and level bounds), or -1 if some system has
+// offsets, dependency positions and level bounds; one dummy entry and one
+// zero slot of x for rows with fewer than four entries), or -1 if some system has
 // more than 65,535 rows or off-diagonals (its local indices would not fit in
 // 16 bits).  0 for a plan without rows.
 int64_t block_resident_bytes(const HostPlan& p, const BlockInfo& info, int vb);

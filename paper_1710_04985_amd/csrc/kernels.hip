@@ -967,12 +967,14 @@ k_block_res(KArgs<T> a, const int* __restrict__ seg_base, const int* __restrict_
   const int ns = lev_pos[lb + nl] - p0;
   const int e0 = a.off_ptr[p0];
   const int ne = a.off_ptr[p0 + ns] - e0;
-  T* xv = reinterpret_cast<T*>(blk_smem);       // [ns] b, then x, by local position
-  T* dv = xv + ns;                              // [ns] 1/diagonal
-  T* vv = dv + ns;                              // [ne] off-diagonal values
-  unsigned short* rp = reinterpret_cast<unsigned short*>(vv + ne);   // [ns+1] entry offsets
-  unsigned short* cp = rp + ns + 1;             // [ne] local position of each dependency
-  unsigned short* lp = cp + ne;                 // [nl+1] level bounds
+  // entry ne is a dummy (value 0, dependency: slot ns of xv, which holds 0)
+  // that rows with fewer than four entries use for the missing ones
+  T* xv = reinterpret_cast<T*>(blk_smem);       // [ns+1] b, then x, by local position
+  T* dv = xv + ns + 1;                          // [ns] 1/diagonal
+  T* vv = dv + ns;                              // [ne+1] off-diagonal values
+  unsigned short* rp = reinterpret_cast<unsigned short*>(vv + ne + 1);   // [ns+1] entry offsets
+  unsigned short* cp = rp + ns + 1;             // [ne+1] local position of each dependency
+  unsigned short* lp = cp + ne + 1;             // [nl+1] level bounds
   // staging: U rows / entries per thread in flight (clamped in-range indices
   // for the loads of a batch's missing tail, whose results are dropped)
   constexpr int U = 4;
@@ -1019,9 +1021,13 @@ k_block_res(KArgs<T> a, const int* __restrict__ seg_base, const int* __restrict_
     }
   }
   for (int m = tid; m <= nl; m += NT) lp[m] = static_cast<unsigned short>(lev_pos[lb + m] - p0);
-  if (tid == 0) rp[ns] = static_cast<unsigned short>(ne);
+  if (tid == 0) {
+    rp[ns] = static_cast<unsigned short>(ne);
+    xv[ns] = T(0);
+    vv[ne] = T(0);
+    cp[ne] = static_cast<unsigned short>(ns);
+  }
   __syncthreads();
-  const int elast = ne > 0 ? ne - 1 : 0;
   // Each stage only loads: what it loaded is tested (is there a row, is the
   // entry the row's) one level later, so no stage waits for its own loads.
   // bounds stage: level m's position range (clamped past the last level)
@@ -1040,14 +1046,16 @@ k_block_res(KArgs<T> a, const int* __restrict__ seg_base, const int* __restrict_
     const int pc = p >= 0 ? p : 0;
     return ResRowB<T>{bd.m, bd.q0, bd.q1, rp[pc], rp[pc + 1], dv[pc], xv[pc]};
   };
-  // entries stage: four loads at once, clamped in range
+  // entries stage: four loads at once; entries the row lacks (or every
+  // entry, if the thread has no row) read the dummy.  A product 0 * 0 added
+  // to the sum leaves its bits unchanged: the sum starts at +0 and an FMA
+  // rounding to nearest never yields -0 from it, so sum + (+0) == sum.
   auto stage_entries = [&](const ResRowB<T>& r) {
     ResRowC<T> c{r.m, r.q0, r.q1, r.e, r.e1, r.d, r.bi, {}, {}};
     const bool live = row_of(r.m, r.q0, r.q1) >= 0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int ee = live ? r.e + q : elast;
-      const int ec = ee < elast ? ee : elast;
+      const int ec = live && r.e + q < r.e1 ? r.e + q : ne;
       c.j[q] = cp[ec];
       c.v[q] = vv[ec];
     }
@@ -1061,21 +1069,16 @@ k_block_res(KArgs<T> a, const int* __restrict__ seg_base, const int* __restrict_
     for (int m = 0; m < nl; ++m) {
       // gather of level m first: the stage loads below do not wait for it
       const int p = row_of(sc.m, sc.q0, sc.q1);
-      bool ok[4];
       T xg[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        ok[q] = p >= 0 && sc.e + q < sc.e1;
-        xg[q] = xv[ok[q] ? sc.j[q] : 0];
-      }
+      for (int q = 0; q < 4; ++q) xg[q] = xv[sc.j[q]];
       const ResRowC<T> nc = stage_entries(sb);     // level m+1
       const ResRowB<T> nb = stage_row(sa);         // level m+2 (its b is not written yet)
       const ResBounds na = stage_bounds(m + 3);
       if (p >= 0) {
         T sum = T(0);
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-          if (ok[q]) sum = fma_t(sc.v[q], xg[q], sum);
+        for (int q = 0; q < 4; ++q) sum = fma_t(sc.v[q], xg[q], sum);
         for (int e = sc.e + 4; e < sc.e1; ++e) sum = fma_t(vv[e], xv[cp[e]], sum);
         xv[p] = canonical((sc.bi - sum) * sc.d);
       }

@@ -117,8 +117,10 @@ extern "C" int check_plan(int n, const int* rp, const int* col, int upper, int u
 // system in LDS) on the CPU: the same byte layout, staging and level loop,
 // with every LDS access bounds-checked against the size the library
 // requests (block_resident_bytes).  Values are synthetic (entry e of the
-// block plan weighs 1/(e+2), b[row] = row+1, 1/diagonal = 1/2); the result is
-// compared bit for bit with plain substitution in the block plan's order.
+// block plan weighs +-1/(e+2) or 0, b[row] = +-(row+1) or 0, 1/diagonal =
+// 1/2); the result, computed in the kernel's order (four slots per row, the
+// missing ones reading a zero dummy), is compared bit for bit with plain
+// substitution in the block plan's order.
 // Returns 0, or the number of the violated check; *bytes gets the LDS size.
 extern "C" int check_block_resident(int n, const int* rp, const int* col, int upper, int nseg,
                                     const int* seg_row0_in, int vb, long long* bytes) {
@@ -131,22 +133,26 @@ extern "C" int check_block_resident(int n, const int* rp, const int* col, int up
   const int64_t need = block_resident_bytes(p, info, vb);
   *bytes = need;
   if (need < 0) return 0;   // not eligible: nothing to model
+  // signed values with exact zeros among them, so that sums of zero occur
   std::vector<double> b(n), x(n, 0.0), xref(n, 0.0);
-  for (int i = 0; i < n; ++i) b[i] = i + 1.0;
-  auto val = [](int64_t e) { return 1.0 / static_cast<double>(e + 2); };
+  for (int i = 0; i < n; ++i) b[i] = i % 5 == 0 ? 0.0 : (i & 1 ? -(i + 1.0) : i + 1.0);
+  auto val = [](int64_t e) {
+    return e % 7 == 3 ? 0.0 : (e & 1 ? -1.0 : 1.0) / static_cast<double>(e + 2);
+  };
   const double dinv = 0.5;
   for (int s = 0; s < nseg; ++s) {
     const int lb = info.seg_base[s], nl = info.seg_base[s + 1] - lb - 1;
     if (nl <= 0) continue;
     const int p0 = info.lev_pos[lb], ns = info.lev_pos[lb + nl] - p0;
     const int e0 = p.off_ptr[p0], ne = p.off_ptr[p0 + ns] - e0;
-    // byte layout of the kernel: T xv[ns], T dv[ns], T vv[ne], u16 rp[ns+1], u16 cp[ne], u16 lp[nl+1]
-    const int64_t o_xv = 0, o_dv = o_xv + int64_t(vb) * ns, o_vv = o_dv + int64_t(vb) * ns;
-    const int64_t o_rp = o_vv + int64_t(vb) * ne, o_cp = o_rp + 2 * int64_t(ns + 1);
-    const int64_t o_lp = o_cp + 2 * int64_t(ne), end = o_lp + 2 * int64_t(nl + 1);
+    // byte layout of the kernel: T xv[ns+1], T dv[ns], T vv[ne+1], u16 rp[ns+1],
+    // u16 cp[ne+1], u16 lp[nl+1]; entry ne is a dummy pointing at xv[ns] = 0
+    const int64_t o_xv = 0, o_dv = o_xv + int64_t(vb) * (ns + 1), o_vv = o_dv + int64_t(vb) * ns;
+    const int64_t o_rp = o_vv + int64_t(vb) * (ne + 1), o_cp = o_rp + 2 * int64_t(ns + 1);
+    const int64_t o_lp = o_cp + 2 * int64_t(ne + 1), end = o_lp + 2 * int64_t(nl + 1);
     if (end > need) return 40;
-    std::vector<double> xv(ns), dv(ns), vv(ne);
-    std::vector<int> lrp(ns + 1), lcp(ne), llp(nl + 1);
+    std::vector<double> xv(ns + 1), dv(ns), vv(ne + 1);
+    std::vector<int> lrp(ns + 1), lcp(ne + 1), llp(nl + 1);
     for (int q = 0; q < ns; ++q) {
       const int r = p.pos_row[p0 + q];
       if (r < seg_row0[s] || r >= seg_row0[s + 1]) return 41;
@@ -157,6 +163,10 @@ extern "C" int check_block_resident(int n, const int* rp, const int* col, int up
       lrp[q] = off;
     }
     lrp[ns] = ne;
+    xv[ns] = 0.0;
+    vv[ne] = 0.0;
+    lcp[ne] = ns;
+    if (ns > 65535) return 49;
     for (int e = 0; e < ne; ++e) {
       vv[e] = val(e0 + e);
       const int c = p.off_pos[e0 + e] - p0;
@@ -173,9 +183,18 @@ extern "C" int check_block_resident(int n, const int* rp, const int* col, int up
     for (int m = 0; m < nl; ++m) {
       if (llp[m] >= llp[m + 1]) return 46;
       for (int q = llp[m]; q < llp[m + 1]; ++q) {
+        // the kernel's order: four slots (missing entries read the dummy),
+        // then the row's remaining entries
         double sum = 0.0;
-        for (int e = lrp[q]; e < lrp[q + 1]; ++e) {
+        for (int u = 0; u < 4; ++u) {
+          const int ec = lrp[q] + u < lrp[q + 1] ? lrp[q] + u : ne;
+          if (ec < 0 || ec > ne) return 50;
           // a dependency must come from an earlier level of the same system
+          if (ec < ne && lcp[ec] >= llp[m]) return 47;
+          if (lcp[ec] > ns) return 51;
+          sum = std::fma(vv[ec], xv[lcp[ec]], sum);
+        }
+        for (int e = lrp[q] + 4; e < lrp[q + 1]; ++e) {
           if (lcp[e] >= llp[m]) return 47;
           sum = std::fma(vv[e], xv[lcp[e]], sum);
         }
