@@ -316,6 +316,7 @@ def main():
         kernel_name = "k_self_value<double,false>"
     lbL = lb_bytes(TL.n, TL.nnz)
     lbU = lb_bytes(TU.n, TU.nnz)
+    nnz_a = TL.nnz + TU.nnz - TL.n
     step_bytes = lbL + lbU
     gbs = step_bytes / (ms_self * 1e-3) / 1e9
     gbs_level = step_bytes / (ms_level * 1e-3) / 1e9
@@ -344,6 +345,11 @@ def main():
         "self_graph_ms_per_step": round(ms_self_graph, 5),
         "self_cold_ms_per_step": round(ms_cold, 5),
         "speedup_self_vs_level": round(ms_level / ms_self, 3),
+        # the paper's rate for the L-then-U step, eq. (4): 2 nnz(A) / t with
+        # A = L + U - D, the matrix both triangles come from
+        "gflops_paper": {"self": round(2 * nnz_a / (ms_self * 1e-3) / 1e9, 3),
+                         "level": round(2 * nnz_a / (ms_level * 1e-3) / 1e9, 3),
+                         "nnz_A": nnz_a},
         "max_rel_err_vs_oracle": float("%.3e" % err),
         "analysis_ms": round(analysis_ms, 2),
         "analysis_ms_host_route": round(analysis_ms_host, 2),

@@ -560,6 +560,14 @@ def pc_adjoint(sp, torch, steps, warmup, hop_ns, side=96, schedule=None):
             hh.close()
         h, setup_ms[tag] = _timed_handle(torch, lambda: make("device" if tag == "self" else "host"))
         res["nlev"] = h.info()["nlev"]
+        # the forward direction's schedule (tuned, or the fixed one) serves
+        # the adjoint's transposed solve too
+        if schedule is None:
+            h.tune(bd0, torch.empty_like(bd0))
+        elif tag == "self":
+            h.configure(**schedule)
+        if tag == "self":
+            res["schedule_self"] = _schedule(h.info())
         vals = d[2].clone().requires_grad_(True)
         bd = bd0.clone().requires_grad_(True)
 
