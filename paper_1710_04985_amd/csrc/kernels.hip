@@ -208,12 +208,14 @@ template <typename T> struct KArgs {
 // values of the next four entries are loaded while the x gathers of the
 // current four are in flight, so a long row costs about one load round trip
 // per four entries of the lane.  Accumulation is in entry order.
-// kPoll: atomic agent-scope loads, sentinel values are waited for.
-template <typename T, bool kPoll>
+// kPoll: atomic agent-scope loads, sentinel values are waited for.  B
+// entries per batch (more gathers in flight per lane for long rows; the
+// level-scheduled kernels take 16, the polling ones 4, where more registers
+// cost more than they save).  B does not change the order of the sum.
+template <typename T, bool kPoll, int B = 4>
 __device__ __forceinline__ T row_dot(const int* __restrict__ idx, const T* __restrict__ off_val,
                                      int e, int e1, int G, const T* xr, int xs, int spin_limit,
                                      int* status, bool overlap, T sum) {
-  constexpr int B = 4;
   if (e >= e1) return sum;
   int j[B];
   T v[B];
@@ -275,7 +277,7 @@ __device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_rea
 //         bounds, first four entries, x gathers, b and diagonal of all its
 //         rows are issued before any wait, then each row is finished.
 //  G > 1: rows of G lanes; lanes stride the row, the group sums by butterfly.
-template <typename T, bool kPoll>
+template <typename T, bool kPoll, int RB = 4>
 __device__ __forceinline__ void solve_chunk(const KArgs<T>& a, int start, int meta, int lane) {
   const int cnt = meta & 0xffff, lg = meta >> 16;
   if (lg == 0) {
@@ -327,8 +329,8 @@ __device__ __forceinline__ void solve_chunk(const KArgs<T>& a, int start, int me
         sum = fma_t(v[u][q], xv[u][q], sum);
       }
       if (e1[u] > e0[u] + E)
-        sum = row_dot<T, kPoll>(a.off_pos, a.off_val, e0[u] + E, e1[u], 1, a.xp, 1, a.spin_limit,
-                                a.status, a.poll != 0, sum);
+        sum = row_dot<T, kPoll, RB>(a.off_pos, a.off_val, e0[u] + E, e1[u], 1, a.xp, 1,
+                                    a.spin_limit, a.status, a.poll != 0, sum);
       const T xi = canonical((bi[u] - sum) * di[u]);
       publish<T, kPoll>(a.xp + k[u], xi);
       a.x[i[u]] = xi;
@@ -340,8 +342,8 @@ __device__ __forceinline__ void solve_chunk(const KArgs<T>& a, int start, int me
   const int k = start + r;
   T sum = T(0);
   if (active)
-    sum = row_dot<T, kPoll>(a.off_pos, a.off_val, a.off_ptr[k] + gl, a.off_ptr[k + 1], 1 << lg,
-                            a.xp, 1, a.spin_limit, a.status, a.poll != 0, T(0));
+    sum = row_dot<T, kPoll, RB>(a.off_pos, a.off_val, a.off_ptr[k] + gl, a.off_ptr[k + 1],
+                                1 << lg, a.xp, 1, a.spin_limit, a.status, a.poll != 0, T(0));
   sum = group_sum(sum, lg);
   if (active && gl == 0) {
     const int i = a.pos_row[k];
@@ -397,7 +399,7 @@ __global__ void __launch_bounds__(256) k_level(KArgs<T> a, int chunk_begin, int 
   const int c = wave_uniform(chunk_begin + static_cast<int>((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
   if (c >= chunk_end) return;
   if constexpr (kMulti) solve_chunk_multi<T, false>(a, a.chunk_start[c], a.chunk_meta[c], lane);
-  else solve_chunk<T, false>(a, a.chunk_start[c], a.chunk_meta[c], lane);
+  else solve_chunk<T, false, 16>(a, a.chunk_start[c], a.chunk_meta[c], lane);
 }
 
 // Level-scheduled, one lane per row, one right-hand side: the rows of a
@@ -429,8 +431,8 @@ __global__ void __launch_bounds__(256) k_level_flat(KArgs<T> a, int k0, int k1) 
   for (int q = 0; q < 4; ++q)
     if (j[q] >= 0) sum = fma_t(v[q], xv[q], sum);
   if (e1 > e0 + 4)
-    sum = row_dot<T, false>(a.off_pos, a.off_val, e0 + 4, e1, 1, a.xp, 1, a.spin_limit, a.status,
-                            false, sum);
+    sum = row_dot<T, false, 16>(a.off_pos, a.off_val, e0 + 4, e1, 1, a.xp, 1, a.spin_limit,
+                                a.status, false, sum);
   const T xi = canonical((bi - sum) * d);
   a.xp[k] = xi;
   a.x[i] = xi;
