@@ -113,7 +113,7 @@ def test_solve_fp32(sp, name, T):
     ref = None
     for opts in (dict(algo=1), dict(algo=2, sync=0), dict(algo=2, sync=1),
                  dict(algo=2, sync=0, xp_stride=2), dict(algo=2, assign=2, poll=0, xp_stride=2),
-                 dict(algo=2, sync=0, xp_stride=16)):
+                 dict(algo=2, sync=0, xp_stride=16), dict(algo=3), dict(algo=3, block_resident=0)):
         h = sp.Handle(dev(T.row_ptr), dev(T.col_idx), dev(v32),
                       uplo="U" if T.upper else "L").configure(**opts)
         x = h.solve(dev(b32))
@@ -226,7 +226,8 @@ def test_unit_diag(sp):
     T = W.ilu0_lower((11, 10, 9))          # stored unit diagonal
     b = W.uniform_vector(T.n, 5)
     xo = o.solve(T.row_ptr, T.col_idx, T.vals, b, False, True)
-    for opts in (dict(algo=1), dict(algo=2, sync=0), dict(algo=2, sync=1)):
+    for opts in (dict(algo=1), dict(algo=2, sync=0), dict(algo=2, sync=1), dict(algo=3),
+                 dict(algo=3, block_resident=0)):
         h = sp.Handle(*dev_tri(T), unit_diag=True).configure(**opts)
         assert relerr(host(h.solve(dev(b))), xo) <= TOL64
     # diagonal entries absent altogether
@@ -236,6 +237,14 @@ def test_unit_diag(sp):
     rp[1:] = np.cumsum(np.bincount(rows[keep], minlength=T.n))
     h = sp.Handle(dev(rp), dev(T.col_idx[keep]), dev(T.vals[keep]), unit_diag=True)
     assert relerr(host(h.solve(dev(b))), xo) <= TOL64
+    # a 2-D unit-diagonal factor narrow enough for the whole-system-in-LDS kernel
+    T2 = W.ilu0_lower((40, 30))
+    b2 = W.uniform_vector(T2.n, 6)
+    xo2 = o.solve(T2.row_ptr, T2.col_idx, T2.vals, b2, False, True)
+    xs = [sp.Handle(*dev_tri(T2), unit_diag=True).configure(algo=3, block_resident=r).solve(dev(b2))
+          for r in (1, 0)]
+    assert bits_equal(xs[0], xs[1])
+    assert relerr(host(xs[0]), xo2) <= TOL64
 
 
 @pytest.mark.parametrize("nrhs", [1, 3, 16, 70])
