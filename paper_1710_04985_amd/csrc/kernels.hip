@@ -969,8 +969,8 @@ k_block_res(KArgs<T> a, const int* __restrict__ seg_base, const int* __restrict_
   const int ns = lev_pos[lb + nl] - p0;
   const int e0 = a.off_ptr[p0];
   const int ne = a.off_ptr[p0 + ns] - e0;
-  // entry ne is a dummy (value 0, dependency: slot ns of xv, which holds 0)
-  // that rows with fewer than four entries use for the missing ones
+  // entry ne is a dummy (value -0, dependency: slot ns of xv, which holds
+  // +0) that rows with fewer than four entries use for the missing ones
   T* xv = reinterpret_cast<T*>(blk_smem);       // [ns+1] b, then x, by local position
   T* dv = xv + ns + 1;                          // [ns] 1/diagonal
   T* vv = dv + ns;                              // [ne+1] off-diagonal values
@@ -1026,7 +1026,7 @@ k_block_res(KArgs<T> a, const int* __restrict__ seg_base, const int* __restrict_
   if (tid == 0) {
     rp[ns] = static_cast<unsigned short>(ne);
     xv[ns] = T(0);
-    vv[ne] = T(0);
+    vv[ne] = -T(0);
     cp[ne] = static_cast<unsigned short>(ns);
   }
   __syncthreads();
@@ -1049,9 +1049,9 @@ k_block_res(KArgs<T> a, const int* __restrict__ seg_base, const int* __restrict_
     return ResRowB<T>{bd.m, bd.q0, bd.q1, rp[pc], rp[pc + 1], dv[pc], xv[pc]};
   };
   // entries stage: four loads at once; entries the row lacks (or every
-  // entry, if the thread has no row) read the dummy.  A product 0 * 0 added
-  // to the sum leaves its bits unchanged: the sum starts at +0 and an FMA
-  // rounding to nearest never yields -0 from it, so sum + (+0) == sum.
+  // entry, if the thread has no row) read the dummy.  Its product is
+  // (-0) * (+0) = -0, and s + (-0) == s for every s, zeros of either sign
+  // included, so the FMAs of the dummy leave the sum's bits unchanged.
   auto stage_entries = [&](const ResRowB<T>& r) {
     ResRowC<T> c{r.m, r.q0, r.q1, r.e, r.e1, r.d, r.bi, {}, {}};
     const bool live = row_of(r.m, r.q0, r.q1) >= 0;

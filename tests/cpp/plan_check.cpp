@@ -3,6 +3,7 @@
 // library's host analysis source; called from tests/test_plan_cpu.py.
 #include <cmath>
 #include <cstdint>
+#include <cstring>
 #include <vector>
 
 #include "analysis.hpp"
@@ -116,14 +117,17 @@ extern "C" int check_plan(int n, const int* rp, const int* col, int upper, int u
 // Model of the resident block kernel (one workgroup per system, the whole
 // system in LDS) on the CPU: the same byte layout, staging and level loop,
 // with every LDS access bounds-checked against the size the library
-// requests (block_resident_bytes).  Values are synthetic (entry e of the
+// requests (block_resident_bytes).  Values are synthetic: entry e of the
 // block plan weighs +-1/(e+2) or 0, b[row] = +-(row+1) or 0, 1/diagonal =
-// 1/2); the result, computed in the kernel's order (four slots per row, the
-// missing ones reading a zero dummy), is compared bit for bit with plain
-// substitution in the block plan's order.
+// 1/2.  With `tiny`, values and b are near 1e-200 (some b are -0) and
+// 1/diagonal = 1, so x is tiny too and products underflow to signed zeros.
+// The result, computed in the kernel's order (four slots per row, the
+// missing ones reading the dummy of value -0), is compared bit for bit,
+// signs of zeros included, with plain substitution in the block plan's order
+// (a dummy of value +0 fails this).
 // Returns 0, or the number of the violated check; *bytes gets the LDS size.
 extern "C" int check_block_resident(int n, const int* rp, const int* col, int upper, int nseg,
-                                    const int* seg_row0_in, int vb, long long* bytes) {
+                                    const int* seg_row0_in, int vb, int tiny, long long* bytes) {
   HostPlan f;
   build_plan(n, rp, col, nullptr, upper != 0, false, f);
   std::vector<int> seg_row0(seg_row0_in, seg_row0_in + nseg + 1);
@@ -133,13 +137,18 @@ extern "C" int check_block_resident(int n, const int* rp, const int* col, int up
   const int64_t need = block_resident_bytes(p, info, vb);
   *bytes = need;
   if (need < 0) return 0;   // not eligible: nothing to model
-  // signed values with exact zeros among them, so that sums of zero occur
+  // signed values with exact zeros among them, so that sums of zero occur;
+  // with `tiny`, values and b near 1e-200, so that products underflow to
+  // zeros of either sign, and some b are -0
+  const double scale = tiny ? 1e-200 : 1.0;
   std::vector<double> b(n), x(n, 0.0), xref(n, 0.0);
-  for (int i = 0; i < n; ++i) b[i] = i % 5 == 0 ? 0.0 : (i & 1 ? -(i + 1.0) : i + 1.0);
-  auto val = [](int64_t e) {
-    return e % 7 == 3 ? 0.0 : (e & 1 ? -1.0 : 1.0) / static_cast<double>(e + 2);
+  for (int i = 0; i < n; ++i)
+    b[i] = i % 5 == 0 ? (tiny && i % 10 == 0 ? -0.0 : 0.0)
+                      : (i & 1 ? -(i + 1.0) : i + 1.0) * scale;
+  auto val = [scale](int64_t e) {
+    return e % 7 == 3 ? 0.0 : (e & 1 ? -1.0 : 1.0) * scale / static_cast<double>(e + 2);
   };
-  const double dinv = 0.5;
+  const double dinv = tiny ? 1.0 : 0.5;   // tiny: x stays near 1e-200 as well
   for (int s = 0; s < nseg; ++s) {
     const int lb = info.seg_base[s], nl = info.seg_base[s + 1] - lb - 1;
     if (nl <= 0) continue;
@@ -164,7 +173,7 @@ extern "C" int check_block_resident(int n, const int* rp, const int* col, int up
     }
     lrp[ns] = ne;
     xv[ns] = 0.0;
-    vv[ne] = 0.0;
+    vv[ne] = -0.0;
     lcp[ne] = ns;
     if (ns > 65535) return 49;
     for (int e = 0; e < ne; ++e) {
@@ -210,7 +219,7 @@ extern "C" int check_block_resident(int n, const int* rp, const int* col, int up
       xref[p.pos_row[q]] = (b[p.pos_row[q]] - sum) * dinv;
     }
   }
-  for (int i = 0; i < n; ++i)
-    if (x[i] != xref[i]) return 48;
+  for (int i = 0; i < n; ++i)   // bit for bit: the sign of a zero counts
+    if (std::memcmp(&x[i], &xref[i], sizeof(double)) != 0) return 48;
   return 0;
 }

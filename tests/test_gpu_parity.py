@@ -440,6 +440,25 @@ def test_block_resident_matches_streamed(sp):
         hs.status()
 
 
+def test_block_resident_signed_zeros(sp):
+    """Products that underflow to zeros of either sign and b entries of -0:
+    the resident kernel's dummy entries (value -0) must leave every sum's
+    bits alone, so both block kernels agree bit for bit, zero signs included."""
+    T = W.c1_lap2d_64()[0]
+    rows = np.repeat(np.arange(T.n), np.diff(T.row_ptr))
+    v = np.where(T.col_idx == rows, 1.0, T.vals * 1e-200)
+    b = W.uniform_vector(T.n, 31) * 1e-200
+    b[::10] = -0.0
+    xs = []
+    for r in (1, 0):
+        h = sp.Handle(dev(T.row_ptr), dev(T.col_idx), dev(v)).configure(algo=3, block_resident=r)
+        xs.append(h.solve(dev(b)))
+        h.status()
+    assert bits_equal(xs[0], xs[1])
+    xh = host(xs[0])
+    assert np.signbit(xh).any() and (xh == 0).any()     # the case is exercised
+
+
 def test_block_global_x_path(sp):
     """A batch whose largest system does not fit in LDS (x in global memory),
     against the oracle and bitwise against the one-lane-per-row level solve."""

@@ -69,7 +69,8 @@ def test_block_resident_layout(checker, case):
     CPU with every access bounds-checked, against plain substitution."""
     P = ctypes.POINTER(ctypes.c_int32)
     checker.check_block_resident.argtypes = [ctypes.c_int, P, P, ctypes.c_int, ctypes.c_int, P,
-                                             ctypes.c_int, ctypes.POINTER(ctypes.c_longlong)]
+                                             ctypes.c_int, ctypes.c_int,
+                                             ctypes.POINTER(ctypes.c_longlong)]
     if case == "c1":
         tris = [W.laplacian_triangle((64, 64))]
     elif case == "batch_lower":
@@ -84,12 +85,12 @@ def test_block_resident_layout(checker, case):
         tris = [W.laplacian_triangle((260, 260))]
     n, rp, ci, row0 = _concat(tris)
     upper = int(tris[0].upper)
-    for vb in (8, 4):
+    for vb, tiny in ((8, 0), (4, 0), (8, 1)):
         nbytes = ctypes.c_longlong(0)
         rc = checker.check_block_resident(n, rp.ctypes.data_as(P), ci.ctypes.data_as(P), upper,
-                                          len(tris), row0.ctypes.data_as(P), vb,
+                                          len(tris), row0.ctypes.data_as(P), vb, tiny,
                                           ctypes.byref(nbytes))
-        assert rc == 0, "check %d violated" % rc
+        assert rc == 0, "check %d violated (vb %d, tiny %d)" % (rc, vb, tiny)
         if case == "c1":
             # 4096 rows, 8064 off-diagonals, 127 levels
             # (one dummy entry and one zero slot of x on top)
