@@ -89,7 +89,18 @@ typedef enum { SPTRSV_F64 = 0, SPTRSV_F32 = 1 } sptrsv_dtype;
 typedef enum { SPTRSV_LOWER = 0, SPTRSV_UPPER = 1 } sptrsv_uplo;
 
 typedef enum {
-    SPTRSV_ALGO_AUTO = 0,   /* autotuner's choice (heuristic, or timed by sptrsv_tune) */
+    SPTRSV_ALGO_AUTO = 0,   /* sptrsv_tune's timed choice, or before any tuning a rule on
+                               features of the pattern (deterministic, no trials): the
+                               block schedule with the whole system in LDS for one
+                               system with one lane per row, at most 64 rows per level
+                               and small enough for LDS; else self-scheduled.  For the
+                               self-scheduled solve, options left unset follow the
+                               pattern too: the ticket schedule when levels average at
+                               most 4,096 rows (and no slot width was set), else the
+                               XCD-regional static one; two wavefronts per CU for rows
+                               of more than 64 entries or levels averaging more than
+                               8,192 rows; 32-byte slots for rows of more than 64
+                               entries.  No rule changes the result bits. */
     SPTRSV_ALGO_LEVEL = 1,  /* level-scheduled: one launch per level (Sec. 4.1) */
     SPTRSV_ALGO_SELF = 2,   /* self-scheduled: one persistent launch (Sec. 4.2) */
     SPTRSV_ALGO_BLOCK = 3,  /* level-scheduled inside one workgroup per independent
@@ -127,20 +138,23 @@ typedef enum {
     SPTRSV_OPT_ENTRIES_PER_LANE = 2, /* target entries per lane when GROUP = 0 (default 4) */
     SPTRSV_OPT_SYNC = 3,          /* sptrsv_sync (self-scheduled only) */
     SPTRSV_OPT_SPIN_LIMIT = 4,    /* max polls of one dependency before TIMEOUT (>= 1) */
-    SPTRSV_OPT_GRID = 5,          /* persistent workgroups; 0 = one wavefront per CU */
+    SPTRSV_OPT_GRID = 5,          /* persistent workgroups; 0 = one wavefront per CU (if
+                                     unset, see SPTRSV_ALGO_AUTO) */
     SPTRSV_OPT_TIMING = 6,        /* 1 = record HIP events around the main solve kernel */
     SPTRSV_OPT_WG = 7,            /* threads per workgroup for the row kernels (64..256,
                                      default 64) */
     SPTRSV_OPT_ROWS_PER_LANE = 8, /* rows one lane owns when a row gets one lane (1..4,
                                      default 1): fewer, larger work chunks */
-    SPTRSV_OPT_ASSIGN = 9,        /* sptrsv_assign: how self-scheduled wavefronts get chunks */
+    SPTRSV_OPT_ASSIGN = 9,        /* sptrsv_assign: how self-scheduled wavefronts get chunks
+                                     (if unset, by the pattern: see SPTRSV_ALGO_AUTO) */
     SPTRSV_OPT_POLL = 10,         /* how a waiting lane polls its dependencies (value sync):
                                      1 (default) = two rounds in flight over all of its
                                      slots, so a value is seen soon after it lands; 0 = one
                                      round at a time over the pending slots only (less
                                      polling traffic, better when most dependencies are
                                      already available) */
-    SPTRSV_OPT_XP_STRIDE = 11,    /* 1 (default), 2, 4, 8 or 16: elements between consecutive
+    SPTRSV_OPT_XP_STRIDE = 11,    /* 1 (default; if unset, by the pattern: see
+                                     SPTRSV_ALGO_AUTO), 2, 4, 8 or 16: elements between consecutive
                                      values of the position-ordered solution the
                                      self-scheduled static schedules (one right-hand side)
                                      publish and poll.  Wider slots put fewer values on a

@@ -175,6 +175,10 @@ struct sptrsv_handle_s {
   int xp_stride = 1;
   int mrows = 0;
   int res_limit = 1 << 20;
+  // schedule options the caller set (the defaults of the others follow the
+  // pattern, see resolve)
+  unsigned set_mask = 0;
+  int max_level = -1;   // rows of the widest level of the forward plan (-1: not computed)
   // autotuner result
   bool tuned = false;
   Config tuned_cfg{SPTRSV_ALGO_SELF, 0, 4, SPTRSV_SYNC_VALUE, 1, 0, SPTRSV_ASSIGN_STATIC};
@@ -558,13 +562,63 @@ bool upload_chunks(const ChunkTable& t, ChunkEntry& e, int* err) {
 // Schedule of the next solve: the autotuner's choice if one is current,
 // else the options (ALGO_AUTO without tuning = self-scheduled, the paper's
 // proposal).
+// Option bits of set_mask.
+constexpr unsigned kSetGrid = 1, kSetAssign = 2, kSetStride = 4;
+
+// Rows of the widest level of the forward plan (cached: the pattern of a
+// handle never changes).
+int widest_level(sptrsv_handle_t h) {
+  if (h->max_level < 0) {
+    const std::vector<int>& il = h->fwd.h.pos_ilev;
+    int w = 0;
+    for (size_t m = 0; m + 1 < il.size(); ++m) w = std::max(w, il[m + 1] - il[m]);
+    h->max_level = w;
+  }
+  return h->max_level;
+}
+
+// The schedule a solve uses: the autotuner's choice if there is one, else the
+// options.  Options left at their defaults follow features of the pattern
+// (deterministic, no trials, and no choice below changes the result bits:
+// every one keeps the lane rule).  The thresholds are where the autotuner's
+// picks changed on the measured workloads:
+//  * one system, one lane per row, at most 64 rows per level, small enough
+//    for the whole system to sit in LDS: the block schedule (it runs without
+//    any global synchronisation; 2-D 64x64: 0.054 ms against 0.095);
+//  * otherwise self-scheduled; levels of at most 4,096 rows on average take
+//    the ticket schedule (ILU(0) 96^3, the 2-D 64x64 triangle), wider ones
+//    the XCD-regional static one;
+//  * rows longer than 64 entries, or levels of more than 8,192 rows on
+//    average, take two wavefronts per CU (power-law, batched ILU(0));
+//  * rows longer than 64 entries take 32-byte slots for the solution
+//    (power-law: 0.72 against 0.82 ms packed).
 Config resolve(sptrsv_handle_t h) {
   if (h->tuned) return h->tuned_cfg;
   Config c{h->algo, h->group, h->epl, h->sync, h->rpl, h->grid, h->assign};
   c.poll = h->poll;
   c.stride = h->xp_stride;
   c.mrows = h->mrows;
-  if (c.algo == SPTRSV_ALGO_AUTO) c.algo = SPTRSV_ALGO_SELF;
+  const HostPlan& p = h->fwd.h;
+  const int64_t n = h->n, nlev = p.nlev > 0 ? p.nlev : 1;
+  if (c.algo == SPTRSV_ALGO_AUTO) {
+    const bool one_lane = h->group == 1 || (h->group == 0 && p.max_row_len <= h->epl);
+    const int64_t lds = static_cast<int64_t>(h->vb) * (2 * n + p.noff + 2) + 2 * (n + 1) +
+                        2 * (p.noff + 1) + 2 * (nlev + 1);
+    if (!h->batched && one_lane && h->block_resident && n <= 65535 && p.noff <= 65535 &&
+        lds <= h->lds_limit && widest_level(h) <= 64) {
+      c.algo = SPTRSV_ALGO_BLOCK;
+      return c;
+    }
+    c.algo = SPTRSV_ALGO_SELF;
+  }
+  if (c.algo != SPTRSV_ALGO_SELF || c.sync != SPTRSV_SYNC_VALUE) return c;
+  const bool long_rows = p.max_row_len > 64;
+  // (a slot width set explicitly asks for a static schedule: only those use it)
+  if (!(h->set_mask & kSetAssign))
+    c.assign = n <= 4096 * nlev && !(h->set_mask & kSetStride) ? SPTRSV_ASSIGN_TICKET
+                                                                : SPTRSV_ASSIGN_XCD;
+  if (!(h->set_mask & kSetGrid) && (long_rows || n > 8192 * nlev)) c.grid = 2 * h->num_cu;
+  if (!(h->set_mask & kSetStride) && long_rows) c.stride = 32 / h->vb;
   return c;
 }
 
@@ -576,6 +630,10 @@ Config resolve_multi(sptrsv_handle_t h, int nrhs) {
   auto it = h->tuned_multi.find(nrhs);
   if (it != h->tuned_multi.end()) return it->second;
   Config c = resolve(h);
+  // the block schedule solves one right-hand side; a default choice of it
+  // becomes the self-scheduled solve here
+  if (h->algo == SPTRSV_ALGO_AUTO && !h->tuned && c.algo == SPTRSV_ALGO_BLOCK)
+    c.algo = SPTRSV_ALGO_SELF;
   if (h->grid == 0) c.grid = nrhs >= 4 ? 4 * h->num_cu : h->num_cu;
   return c;
 }
@@ -1572,6 +1630,7 @@ int sptrsv_set_option(sptrsv_handle_t h, sptrsv_option key, int64_t v) {
     case SPTRSV_OPT_GRID:
       if (v < 0 || v > (1 << 20)) return kErrInvalidArg;
       h->grid = static_cast<int>(v);
+      h->set_mask |= kSetGrid;
       return kOk;
     case SPTRSV_OPT_TIMING:
       h->timing = v != 0;
@@ -1588,6 +1647,7 @@ int sptrsv_set_option(sptrsv_handle_t h, sptrsv_option key, int64_t v) {
       if (v != SPTRSV_ASSIGN_STATIC && v != SPTRSV_ASSIGN_TICKET && v != SPTRSV_ASSIGN_XCD)
         return kErrInvalidArg;
       h->assign = static_cast<int>(v);
+      h->set_mask |= kSetAssign;
       return kOk;
     case SPTRSV_OPT_POLL:
       if (v != 0 && v != 1) return kErrInvalidArg;
@@ -1596,6 +1656,7 @@ int sptrsv_set_option(sptrsv_handle_t h, sptrsv_option key, int64_t v) {
     case SPTRSV_OPT_XP_STRIDE:
       if (v != 1 && v != 2 && v != 4 && v != 8 && v != 16) return kErrInvalidArg;
       h->xp_stride = static_cast<int>(v);
+      h->set_mask |= kSetStride;
       return kOk;
     case SPTRSV_OPT_MULTI_ROWS:
       if (v != 0 && v != 1 && v != 2 && v != 4) return kErrInvalidArg;

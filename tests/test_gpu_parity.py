@@ -459,6 +459,31 @@ def test_block_resident_signed_zeros(sp):
     assert np.signbit(xh).any() and (xh == 0).any()     # the case is exercised
 
 
+def test_default_schedule_follows_the_pattern(sp):
+    """Without tuning or schedule options the schedule follows features of
+    the pattern, and every such choice gives the bits of an explicitly chosen
+    one-lane-per-row (or same lane rule) schedule."""
+    o = oracle.get()
+    cu = torch.cuda.get_device_properties(0).multi_processor_count
+    cases = [(W.c1_lap2d_64()[0], dict(algo=3)),                            # whole system in LDS
+             (W.powerlaw_lower(50000, 21, window=5000),
+              dict(algo=2, grid=2 * cu, xp_stride=4, assign=1)),             # long rows
+             (W.laplacian_triangle((30, 30, 30)), dict(algo=2, assign=1))]   # narrow levels
+    for T, want in cases:
+        b = W.uniform_vector(T.n, 17)
+        h = sp.Handle(*dev_tri(T))
+        info = h.info()
+        for k, v in want.items():
+            assert info[k] == v, (T.name, k, info[k], v)
+        x = h.solve(dev(b))
+        h.status()
+        ref = sp.Handle(*dev_tri(T)).configure(algo=2, assign=0, grid=0, xp_stride=1)
+        assert bits_equal(x, ref.solve(dev(b)))
+        assert relerr(host(x), o.solve(T.row_ptr, T.col_idx, T.vals, b)) <= TOL64
+        # an option set explicitly is kept
+        assert h.configure(assign=0).info()["assign"] == 0
+
+
 def test_block_global_x_path(sp):
     """A batch whose largest system does not fit in LDS (x in global memory),
     against the oracle and bitwise against the one-lane-per-row level solve."""

@@ -98,8 +98,9 @@ def test_noalloc_refuses_oversize_and_unprepared(sp):
     # 84^3 = 592,704 rows in 128-byte slots need 75.9 MB > 64 MiB
     T = W.laplacian_triangle((84, 84, 84))
     h, bd, xo = _case(sp, T, 15)
-    h.set_option("xp_stride", 16)
+    h.set_option("xp_stride", 16)             # a slot width asks for a static schedule
     x = torch.empty_like(bd)
+    h.solve(bd, out=x)                        # builds that schedule's per-wavefront lists
     assert _noalloc(sp, h, bd, x) == -13                     # SPTRSV_ERR_TOO_LARGE
     h.set_option("xp_stride", 1)
     assert _noalloc(sp, h, bd, x) == 0
