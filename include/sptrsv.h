@@ -96,8 +96,8 @@ typedef enum {
                                and small enough for LDS; else self-scheduled.  For the
                                self-scheduled solve, options left unset follow the
                                pattern too: the ticket schedule when levels average at
-                               most 4,096 rows (and no slot width was set), else the
-                               XCD-regional static one; two wavefronts per CU for rows
+                               most 4,096 rows, no row exceeds 64 entries and no slot
+                               width was set, else the XCD-regional static one; two wavefronts per CU for rows
                                of more than 64 entries or levels averaging more than
                                8,192 rows; 32-byte slots for rows of more than 64
                                entries.  No rule changes the result bits. */

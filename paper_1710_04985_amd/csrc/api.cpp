@@ -586,8 +586,8 @@ int widest_level(sptrsv_handle_t h) {
 //    for the whole system to sit in LDS: the block schedule (it runs without
 //    any global synchronisation; 2-D 64x64: 0.054 ms against 0.095);
 //  * otherwise self-scheduled; levels of at most 4,096 rows on average take
-//    the ticket schedule (ILU(0) 96^3, the 2-D 64x64 triangle), wider ones
-//    the XCD-regional static one;
+//    the ticket schedule (ILU(0) 96^3, the 2-D 64x64 triangle) unless rows
+//    exceed 64 entries; the others the XCD-regional static one;
 //  * rows longer than 64 entries, or levels of more than 8,192 rows on
 //    average, take two wavefronts per CU (power-law, batched ILU(0));
 //  * rows longer than 64 entries take 32-byte slots for the solution
@@ -615,8 +615,9 @@ Config resolve(sptrsv_handle_t h) {
   const bool long_rows = p.max_row_len > 64;
   // (a slot width set explicitly asks for a static schedule: only those use it)
   if (!(h->set_mask & kSetAssign))
-    c.assign = n <= 4096 * nlev && !(h->set_mask & kSetStride) ? SPTRSV_ASSIGN_TICKET
-                                                                : SPTRSV_ASSIGN_XCD;
+    c.assign = n <= 4096 * nlev && !long_rows && !(h->set_mask & kSetStride)
+                   ? SPTRSV_ASSIGN_TICKET
+                   : SPTRSV_ASSIGN_XCD;
   if (!(h->set_mask & kSetGrid) && (long_rows || n > 8192 * nlev)) c.grid = 2 * h->num_cu;
   if (!(h->set_mask & kSetStride) && long_rows) c.stride = 32 / h->vb;
   return c;

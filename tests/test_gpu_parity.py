@@ -467,7 +467,7 @@ def test_default_schedule_follows_the_pattern(sp):
     cu = torch.cuda.get_device_properties(0).multi_processor_count
     cases = [(W.c1_lap2d_64()[0], dict(algo=3)),                            # whole system in LDS
              (W.powerlaw_lower(50000, 21, window=5000),
-              dict(algo=2, grid=2 * cu, xp_stride=4, assign=1)),             # long rows
+              dict(algo=2, grid=2 * cu, xp_stride=4, assign=2)),             # long rows
              (W.laplacian_triangle((30, 30, 30)), dict(algo=2, assign=1))]   # narrow levels
     for T, want in cases:
         b = W.uniform_vector(T.n, 17)
