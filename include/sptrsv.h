@@ -164,10 +164,10 @@ typedef enum {
                                      64-byte slots.  Ignored by the other schedules */
     SPTRSV_OPT_MULTI_ROWS = 12,   /* several right-hand sides, static schedules: rows each
                                      group of a row's lanes owns in a chunk (1, 2 or 4; 0 =
-                                     default: 4 when a row takes 8 or more lanes, 2 at 4
-                                     lanes, else 1).  A wavefront issues the gathers of all
-                                     its rows before it waits on any, so larger values mean
-                                     fewer waits per level.  Results do not depend on it */
+                                     default, 1: the fastest on every pattern and column
+                                     count measured).  A wavefront issues the gathers of all
+                                     its rows before it waits on any.  Results do not depend
+                                     on it */
     SPTRSV_OPT_RESIDENCY_LIMIT = 13, /* polls a wavefront of a cooperatively launched (static)
                                      schedule waits at its start for the rest of the grid to
                                      sign in (default 2^20); the grid gives up with
@@ -325,8 +325,13 @@ int sptrsv_solve_transpose(sptrsv_handle_t h, const void *b, void *x, hipStream_
 int sptrsv_prepare_transpose(sptrsv_handle_t h, hipStream_t stream);
 
 /* Several right-hand sides, column-major: column r of B starts at B + r*ld.
- * nrhs >= 1, ld >= n.  Each row of T is read once for all columns.  B == X
- * allowed.  transpose != 0 solves T^T X = B. */
+ * nrhs >= 1, ld >= n.  Each row of T is read once for all columns, and each
+ * column is computed as the one-lane-per-row single-RHS solve (equal to
+ * sptrsv_solve with GROUP = 1, bit for bit).  Exception: on a pattern with
+ * rows longer than 64 entries, unless GROUP = 1, the columns are solved one
+ * after another by the single-RHS schedule (each equal to sptrsv_solve on
+ * it, bit for bit): one lane per long row and column would walk the whole
+ * row.  B == X allowed.  transpose != 0 solves T^T X = B. */
 int sptrsv_solve_multi(sptrsv_handle_t h, int32_t nrhs, int32_t ld, const void *B, void *X,
                        int transpose, hipStream_t stream);
 
@@ -361,9 +366,11 @@ int sptrsv_tune(sptrsv_handle_t h, const void *b, void *x, hipStream_t stream);
  * 1, 2, 4 and 8 wavefronts per CU, static and XCD-regional assignment and
  * both polling modes (and the level-scheduled solve, unless the algorithm
  * option excludes it) on the caller's B and X, and keeps the fastest for
- * this nrhs.  Without it, multi-RHS solves use the single-RHS schedule with
- * 4 wavefronts per CU (1 for nrhs < 4) unless SPTRSV_OPT_GRID is set.
- * B != X.  Blocking.  Changing a schedule option discards the choice. */
+ * this nrhs.  Without it, options left unset follow the column count: 2, 4
+ * or 8 wavefronts per CU from 2, 8 or 16 columns, XCD-regional assignment up
+ * to 4 columns and round-robin beyond, one row per lane group.  Does nothing
+ * where sptrsv_solve_multi solves column by column (long rows).  B != X.
+ * Blocking.  Changing a schedule option discards the choice. */
 int sptrsv_tune_multi(sptrsv_handle_t h, int32_t nrhs, int32_t ld, const void *B, void *X,
                       hipStream_t stream);
 

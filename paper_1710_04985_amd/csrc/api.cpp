@@ -635,8 +635,26 @@ Config resolve_multi(sptrsv_handle_t h, int nrhs) {
   // becomes the self-scheduled solve here
   if (h->algo == SPTRSV_ALGO_AUTO && !h->tuned && c.algo == SPTRSV_ALGO_BLOCK)
     c.algo = SPTRSV_ALGO_SELF;
-  if (h->grid == 0) c.grid = nrhs >= 4 ? 4 * h->num_cu : h->num_cu;
+  // options left unset, by the column count (where sptrsv_tune_multi's picks
+  // changed on 128^3 and ILU(0) 96^3): 2, 4, 8 wavefronts per CU from 2, 8,
+  // 16 columns; XCD-regional lists up to 4 columns, round-robin beyond
+  if (!(h->set_mask & kSetGrid))
+    c.grid = (nrhs >= 16 ? 8 : nrhs >= 8 ? 4 : 2) * h->num_cu;
+  if (!(h->set_mask & kSetAssign) && c.algo == SPTRSV_ALGO_SELF)
+    c.assign = nrhs <= 4 ? SPTRSV_ASSIGN_XCD : SPTRSV_ASSIGN_STATIC;
   return c;
+}
+
+// Several right-hand sides on a pattern with rows longer than 64 entries
+// and a lane rule that gives such rows several lanes: the multi-RHS kernels
+// walk a row with one lane per column, so a long row costs one lane its
+// whole length per column; solving the columns one after another with the
+// single-RHS schedule is faster there (power-law, 16 columns: 36 ms at the
+// best multi-RHS schedule, 16 x 0.72 ms this way).
+bool multi_by_columns(const PlanState& ps, const Config& c) {
+  return c.group != 1 && ps.h.max_row_len > 64 &&
+         (c.algo == SPTRSV_ALGO_SELF || c.algo == SPTRSV_ALGO_LEVEL ||
+          c.algo == SPTRSV_ALGO_BLOCK);
 }
 
 uint64_t tune_key(sptrsv_handle_t h) {
@@ -836,8 +854,10 @@ int regather_push(sptrsv_handle_t h, hipStream_t s) {
 // else 4 when a row takes 8 or more lanes (chunks of 32 or fewer rows), 2 at
 // 4 lanes, 1 below (chunks already 32 or 64 rows).
 int multi_rows(const Config& c, int lanes_per_row) {
-  if (c.mrows == 1 || c.mrows == 2 || c.mrows == 4) return c.mrows;
-  return lanes_per_row >= 8 ? 4 : lanes_per_row == 4 ? 2 : 1;
+  (void)lanes_per_row;
+  // default 1: it was the fastest choice for every column count and pattern
+  // measured (2 to 16 columns, meshes and ILU(0) factors)
+  return c.mrows == 2 || c.mrows == 4 ? c.mrows : 1;
 }
 
 // Column-wise solve, one right-hand side: LEVC (a launch per level) or SLFC
@@ -1088,6 +1108,16 @@ int solve_dispatch_ordered(sptrsv_handle_t h, bool transpose, const void* b, voi
   }
   PlanState& ps = transpose ? h->trn : h->fwd;
   const Config c = nrhs > 1 ? resolve_multi(h, nrhs) : resolve(h);
+  if (nrhs > 1 && multi_by_columns(ps, c)) {
+    // each column equals sptrsv_solve on it, bit for bit
+    const size_t col = static_cast<size_t>(ld) * h->vb;
+    for (int q = 0; q < nrhs; ++q) {
+      const int st = solve_dispatch_ordered(h, transpose, static_cast<const char*>(b) + q * col,
+                                            static_cast<char*>(x) + q * col, 1, h->n, s, ext);
+      if (st) return st;
+    }
+    return kOk;
+  }
   if (c.algo == SPTRSV_ALGO_BLOCK && nrhs == 1 && !h->blk[transpose ? 1 : 0].built) {
     if (ext.no_alloc) return kErrNotSupported;
     const int st = build_block(h, transpose ? 1 : 0, s);
@@ -1827,6 +1857,8 @@ int sptrsv_tune_multi(sptrsv_handle_t h, int32_t nrhs, int32_t ld, const void* B
   if (!h || nrhs < 2 || ld < h->n || ld < 1) return kErrInvalidArg;
   if (h->n == 0) return kOk;
   if (!B || !X || B == X) return kErrInvalidArg;
+  // solved column by column with the single-RHS schedule: nothing to tune here
+  if (multi_by_columns(h->fwd, resolve_multi(h, nrhs))) return kOk;
   const int ncu = h->num_cu;
   std::vector<Config> cand;
   const bool self_ok = h->algo == SPTRSV_ALGO_AUTO || h->algo == SPTRSV_ALGO_SELF ||

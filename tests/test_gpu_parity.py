@@ -314,6 +314,32 @@ def test_multi_rhs_strided(sp, nrhs, assign):
     assert relerr(X32.T, ref) <= TOL32
 
 
+def test_multi_rhs_long_rows_by_columns(sp):
+    """Rows longer than 64 entries with the default lane rule: the columns
+    are solved one after another by the single-RHS schedule, each equal to
+    sptrsv_solve on it bit for bit; tune_multi leaves it.  T^T of this
+    triangle has short rows (column counts), so the transposed solve takes
+    the multi-RHS kernel: each column equals the one-lane-per-row solve_t."""
+    o = oracle.get()
+    T = W.powerlaw_lower(30000, 19, window=3000)
+    assert np.diff(T.row_ptr).max() > 65
+    F = np.stack([W.uniform_vector(T.n, 700 + r) for r in range(5)], 0)
+    h = sp.Handle(*dev_tri(T))
+    X = h.solve_multi(dev(F))
+    Xt = h.solve_multi(dev(F), transpose=True)
+    h.tune_multi(dev(F))
+    X2 = h.solve_multi(dev(F))
+    h.status()
+    h1 = sp.Handle(*dev_tri(T)).configure(group=1)
+    for r in range(5):
+        assert bits_equal(X[r], h.solve(dev(F[r])))
+        assert bits_equal(Xt[r], h1.solve_t(dev(F[r])))
+    assert bits_equal(X2, X)
+    assert relerr(host(X).T, o.solve_multi(T.row_ptr, T.col_idx, T.vals, F.T)) <= TOL64
+    for r in (0, 4):
+        assert relerr(host(Xt[r]), o.solve_transpose(T.row_ptr, T.col_idx, T.vals, F[r])) <= TOL64
+
+
 @pytest.mark.parametrize("nrhs", [2, 6, 16, 33])
 def test_multi_rows_per_lane_group(sp, nrhs):
     """Rows per lane group of the static multi-RHS kernel (1, 2, 4): the same
