@@ -698,6 +698,36 @@ def test_graph_replay(sp, opts):
     h.status()
 
 
+@pytest.mark.parametrize("case", ["block_in_lds", "long_rows_static", "narrow_ticket"])
+def test_graph_replay_default_schedules(sp, case):
+    """Graphs of the schedules the pattern picks by default (the whole
+    system in LDS; the XCD-regional static schedule with 32-byte slots; the
+    ticket schedule), captured before any eager solve, replayed with eager
+    work in between, against the eager solve bit for bit."""
+    T = {"block_in_lds": W.c1_lap2d_64()[0],
+         "long_rows_static": W.powerlaw_lower(30000, 19, window=3000),
+         "narrow_ticket": W.laplacian_triangle((24, 23, 22))}[case]
+    h = sp.Handle(*dev_tri(T))
+    want = {"block_in_lds": dict(algo=3), "long_rows_static": dict(algo=2, assign=2, xp_stride=4),
+            "narrow_ticket": dict(algo=2, assign=1)}[case]
+    info = h.info()
+    assert all(info[k] == v for k, v in want.items()), info
+    s = torch.cuda.Stream()
+    b = dev(W.uniform_vector(T.n, 5))
+    x = torch.empty_like(b)
+    with torch.cuda.stream(s):
+        g = h.capture(b, x, stream=s)
+        ref = h.solve(b)
+        for rep in range(4):
+            x.zero_()
+            g.launch(s)
+            s.synchronize()
+            assert bits_equal(x, ref), rep
+            h.solve(b * 3.0)                   # eager work between replays
+            s.synchronize()
+    h.status()
+
+
 def test_capture_first_with_xp_stride(sp):
     """A graph captured before any eager solve, with values in 8-byte slots:
     the wider solution buffer is sized before the capture."""
