@@ -418,7 +418,7 @@ FIXED_SCHEDULES = {
     "c3_powerlaw_1M_f32": dict(algo=2, grid=512, assign=2, poll=1, xp_stride=16),
     "c4a_batched_256_ilu0_2d": dict(algo=2, grid=512, assign=2, poll=1),
     "c4b_lap3d_128_lower_16rhs": dict(algo=2, grid=2048, assign=0, poll=1, multi_rows=1),
-    "c5_ilu0_3d_96_fwd_adjoint": dict(algo=2),
+    "c5_ilu0_3d_96_fwd_adjoint": dict(algo=2, assign=0, grid=0, xp_stride=1),
 }
 
 
