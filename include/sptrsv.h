@@ -94,10 +94,11 @@ typedef enum {
                                block schedule with the whole system in LDS for one
                                system with one lane per row, at most 64 rows per level
                                and small enough for LDS; else self-scheduled.  For the
-                               self-scheduled solve, options left unset follow the
-                               pattern too: the ticket schedule when levels average at
-                               most 4,096 rows, no row exceeds 64 entries and no slot
-                               width was set, else the XCD-regional static one; two wavefronts per CU for rows
+                               self-scheduled solve (also when chosen explicitly),
+                               options left unset follow the pattern too: the ticket
+                               schedule when levels average at most 4,096 rows, no row
+                               exceeds 64 entries and no slot width was set, else the
+                               XCD-regional static one; two wavefronts per CU for rows
                                of more than 64 entries or levels averaging more than
                                8,192 rows; 32-byte slots for rows of more than 64
                                entries.  No rule changes the result bits. */
@@ -154,10 +155,10 @@ typedef enum {
                                      polling traffic, better when most dependencies are
                                      already available) */
     SPTRSV_OPT_XP_STRIDE = 11,    /* 1 (default; if unset, by the pattern: see
-                                     SPTRSV_ALGO_AUTO), 2, 4, 8 or 16: elements between consecutive
-                                     values of the position-ordered solution the
-                                     self-scheduled static schedules (one right-hand side)
-                                     publish and poll.  Wider slots put fewer values on a
+                                     SPTRSV_ALGO_AUTO), 2, 4, 8 or 16: elements between
+                                     consecutive values of the position-ordered solution
+                                     the self-scheduled static schedules (one right-hand
+                                     side) publish and poll.  Wider slots put fewer values on a
                                      cache line under concurrent stores and polls: faster
                                      where dependencies are scattered, slower where polls
                                      coalesce.  The autotuner tries packed values and 32- and
@@ -242,8 +243,8 @@ typedef enum {
  * other pattern, and every invalid one, goes through the host route, which
  * also names the validation error.  The device route keeps a device copy of
  * the pattern and downloads it, with the plan, the first time something
- * needs them on the host (the analysis of T^T, the block plan, export,
- * sptrsv_tune).  Errors as for sptrsv_analyze, plus INVALID_ARG for an
+ * needs them on the host (the block plan, export, sptrsv_tune); the analysis
+ * of T^T stays on the device.  Errors as for sptrsv_analyze, plus INVALID_ARG for an
  * unknown route and TIMEOUT (level sweep; cannot happen on a valid
  * triangle).  Blocking. */
 int sptrsv_analyze_ex(int32_t n, int32_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
@@ -306,7 +307,9 @@ int sptrsv_solve(sptrsv_handle_t h, const void *b, void *x, hipStream_t stream);
  * builds those of the default schedule and sptrsv_tune those of its choice
  * (as does any earlier sptrsv_solve or graph capture with that schedule);
  * otherwise SPTRSV_ERR_NOT_SUPPORTED, as for column-wise schedules not yet
- * prepared.  The current device must be the handle's (else INVALID_ARG).
+ * prepared.  One exception: a static self-scheduled schedule whose
+ * per-wavefront lists do not exist yet runs as the ticket schedule, whose
+ * result bits are the same (and which ignores SPTRSV_OPT_XP_STRIDE).  The current device must be the handle's (else INVALID_ARG).
  * All calls on one GPU share the array, which keeps the last call's
  * contents (each solve reinitialises what it reads): calls that overlap in
  * time on one GPU race; order them on one stream.  Asynchronous. */
@@ -412,8 +415,9 @@ int sptrsv_export_analysis(sptrsv_handle_t h, int transpose, int32_t *level, int
                            int32_t *jlev, int32_t *depcnt);
 
 /* Device-side status of the last solves: synchronises the handle's last
- * stream, returns SPTRSV_OK, SPTRSV_ERR_TIMEOUT or SPTRSV_ERR_ZERO_PIVOT,
- * and clears it. */
+ * stream, returns SPTRSV_OK, SPTRSV_ERR_NOT_RESIDENT, SPTRSV_ERR_TIMEOUT or
+ * SPTRSV_ERR_ZERO_PIVOT (in that order of precedence when several were
+ * raised), and clears it. */
 int sptrsv_get_status(sptrsv_handle_t h);
 
 /* Accumulated duration of the main solve kernels recorded while
