@@ -559,10 +559,8 @@ bool upload_chunks(const ChunkTable& t, ChunkEntry& e, int* err) {
   return true;
 }
 
-// Schedule of the next solve: the autotuner's choice if one is current,
-// else the options (ALGO_AUTO without tuning = self-scheduled, the paper's
-// proposal).
-// Option bits of set_mask.
+// Option bits of set_mask: options set explicitly, which the pattern-based
+// defaults of resolve() leave alone.
 constexpr unsigned kSetGrid = 1, kSetAssign = 2, kSetStride = 4;
 
 // Rows of the widest level of the forward plan (cached: the pattern of a
