@@ -79,10 +79,10 @@ typedef enum {
                                        still alive (destroy them first) */
     SPTRSV_ERR_TOO_LARGE = -13,     /* sptrsv_solve_noalloc: the schedule needs more than
                                        SPTRSV_NOALLOC_SCRATCH_BYTES of scratch */
-    SPTRSV_ERR_NOT_RESIDENT = -14   /* a cooperatively launched static schedule found its grid
-                                       not all resident (other work held the GPU): it drained
-                                       without a result; the ticket schedule (ASSIGN_TICKET)
-                                       needs no residency */
+    SPTRSV_ERR_NOT_RESIDENT = -14   /* a static schedule found its persistent grid not all
+                                       resident (other work held the GPU): it drained without
+                                       a result; the ticket schedule (ASSIGN_TICKET) needs no
+                                       residency */
 } sptrsv_status;
 
 typedef enum { SPTRSV_F64 = 0, SPTRSV_F32 = 1 } sptrsv_dtype;
@@ -116,7 +116,7 @@ typedef enum {
                                into the accumulators of the rows depending on it with
                                agent-scope atomic adds */
     SPTRSV_ALGO_COLUMN_SELF = 5   /* column-wise, self-scheduled (Sec. 4.2 SLFC): one
-                               cooperative launch; a row starts once its arrival counter
+                               persistent launch; a row starts once its arrival counter
                                reaches its dependency count.  Both column forms add
                                updates in an order fixed by timing: results agree with
                                the row-wise solves to rounding, not bit for bit.  One
@@ -169,32 +169,39 @@ typedef enum {
                                      count measured).  A wavefront issues the gathers of all
                                      its rows before it waits on any.  Results do not depend
                                      on it */
-    SPTRSV_OPT_RESIDENCY_LIMIT = 13, /* polls a wavefront of a cooperatively launched (static)
+    SPTRSV_OPT_RESIDENCY_LIMIT = 13, /* polls a wavefront of a static (persistent-grid)
                                      schedule waits at its start for the rest of the grid to
                                      sign in (default 2^20); the grid gives up with
                                      SPTRSV_ERR_NOT_RESIDENT if it never fills.  0 makes every
                                      wavefront but the last to arrive give up at once (a test
                                      hook that forces the failure) */
-    SPTRSV_OPT_BLOCK_RESIDENT = 14 /* SPTRSV_ALGO_BLOCK: 1 (default) keeps each system's whole
+    SPTRSV_OPT_BLOCK_RESIDENT = 14, /* SPTRSV_ALGO_BLOCK: 1 (default) keeps each system's whole
                                      level-ordered copy (b/x, 1/diagonal, off-diagonal values,
                                      16-bit local indices) in LDS when every system fits (at
                                      most 65,535 rows and off-diagonals per system and the
                                      device's per-workgroup LDS), so its levels touch no global
                                      memory; 0 keeps only x there and streams the row data.
                                      Same results either way */
+    SPTRSV_OPT_COOPERATIVE = 15   /* how the persistent grids of the static schedules (and of
+                                     ALGO_COLUMN_SELF) are launched: 0 (default) = an
+                                     ordinary launch; the grid is at most half of what the
+                                     occupancy figure allows, so it is resident as soon as the
+                                     GPU has room, and its wavefronts check that at their start
+                                     (SPTRSV_OPT_RESIDENCY_LIMIT); 1 = a cooperative launch,
+                                     whose co-residency guarantee costs about 16 us per solve
+                                     (measured on MI355X).  Same results either way */
 } sptrsv_option;
 
 typedef enum {
-    SPTRSV_ASSIGN_STATIC = 0,     /* chunk c goes to wavefront c mod W of a cooperatively
-                                     launched (all-resident) grid, pipelined four chunks
-                                     deep; value sync, one or several right-hand sides.  The
-                                     cooperative launch is captured by sptrsv_graph_capture
+    SPTRSV_ASSIGN_STATIC = 0,     /* chunk c goes to wavefront c mod W of an all-resident
+                                     persistent grid (SPTRSV_OPT_COOPERATIVE), pipelined
+                                     four chunks deep; value sync, one or several right-hand
+                                     sides.  The launch is captured by sptrsv_graph_capture
                                      (which prepares the per-wavefront chunk lists); under a
                                      capture the caller opens itself, the ticket form is used
-                                     unless those lists already exist.  A replayed graph
-                                     relies on the whole grid being resident, which holds
-                                     when no other work shares the GPU; otherwise the wait
-                                     limit turns a stall into SPTRSV_ERR_TIMEOUT. */
+                                     unless those lists already exist.  A grid that other work
+                                     keeps from becoming resident drains with
+                                     SPTRSV_ERR_NOT_RESIDENT. */
     SPTRSV_ASSIGN_TICKET = 1,     /* wavefronts claim chunks from an atomic ticket: needs no
                                      co-residency, costs one serialised atomic per chunk */
     SPTRSV_ASSIGN_XCD = 2         /* as STATIC, but each level's chunks are cut into 8

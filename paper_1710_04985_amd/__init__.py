@@ -29,7 +29,7 @@ SYNC_VALUE, SYNC_FLAG = 0, 1
 OPT = {"algo": 0, "group": 1, "entries_per_lane": 2, "sync": 3, "spin_limit": 4,
        "grid": 5, "timing": 6, "wg": 7, "rows_per_lane": 8, "assign": 9, "poll": 10,
        "xp_stride": 11, "multi_rows": 12, "residency_limit": 13,
-       "block_resident": 14}
+       "block_resident": 14, "cooperative": 15}
 ASSIGN_STATIC, ASSIGN_TICKET, ASSIGN_XCD = 0, 1, 2
 SETUP = {"host": 0, "device": 1}
 

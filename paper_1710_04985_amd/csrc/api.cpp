@@ -134,6 +134,7 @@ struct sptrsv_handle_s {
   int num_cu = 256;
   int lds_limit = 65536;          // bytes of LDS one workgroup may use
   int block_resident = 1;         // block schedule: whole system in LDS when it fits
+  int coop = 0;                   // persistent static grids: cooperative launch
   std::vector<int> rp_h, col_h;   // caller's pattern (host copy)
   PlanState fwd, trn;
   // device setup: the handle's own device copy of the pattern (for T^T and
@@ -721,8 +722,8 @@ int blocks_per_cu(sptrsv_handle_t h, int kind) {
 // wavefront per CU; never more than chunks need, than half of what the
 // occupancy figure allows, or than 8 wavefronts per CU (a quarter of a CU's
 // wave slots), so the all-resident schedules keep at least a factor of two
-// below the reported capacity (the cooperative launches also check
-// residency when they start).
+// below the reported capacity (their wavefronts also check residency when
+// they start, whether the launch is cooperative or not).
 int persistent_grid(sptrsv_handle_t h, int kind, int grid, int nchunks) {
   const int per_cu = blocks_per_cu(h, kind);
   const int waves_per_block = h->wg / 64;
@@ -859,7 +860,7 @@ int multi_rows(const Config& c, int lanes_per_row) {
 }
 
 // Column-wise solve, one right-hand side: LEVC (a launch per level) or SLFC
-// (one cooperative launch, chunk c on wavefront c mod W, or by XCD region).
+// (one persistent launch, chunk c on wavefront c mod W, or by XCD region).
 template <typename T>
 int solve_column(sptrsv_handle_t h, PlanState& ps, const Config& c, const void* b, void* x,
                  hipStream_t s, const SolveExt& ext) {
@@ -883,6 +884,7 @@ int solve_column(sptrsv_handle_t h, PlanState& ps, const Config& c, const void* 
   a.status = h->scratch.status;
   a.arrive = h->scratch.arrive;
   a.res_limit = h->res_limit;
+  a.coop = h->coop;
   a.spin_limit = h->spin_limit;
   a.wg = h->wg;
   if (launch_column_init<T>(a, s) != hipSuccess) return kErrHip;
@@ -976,6 +978,7 @@ int solve_impl(sptrsv_handle_t h, PlanState& ps, const Config& c_in, const void*
   a.poll = c.poll;
   a.xp_stride = stride;
   a.res_limit = h->res_limit;
+  a.coop = h->coop;
   a.mrows = use_static ? mrows : 1;
   a.wg = h->wg;
   hipEvent_t stop;
@@ -1699,6 +1702,10 @@ int sptrsv_set_option(sptrsv_handle_t h, sptrsv_option key, int64_t v) {
       if (v != 0 && v != 1) return kErrInvalidArg;
       h->block_resident = static_cast<int>(v);
       return kOk;
+    case SPTRSV_OPT_COOPERATIVE:
+      if (v != 0 && v != 1) return kErrInvalidArg;
+      h->coop = static_cast<int>(v);
+      return kOk;
   }
   return kErrInvalidArg;
 }
@@ -1721,6 +1728,7 @@ int sptrsv_get_option(sptrsv_handle_t h, sptrsv_option key, int64_t* v) {
     case SPTRSV_OPT_MULTI_ROWS: *v = h->mrows; return kOk;
     case SPTRSV_OPT_RESIDENCY_LIMIT: *v = h->res_limit; return kOk;
     case SPTRSV_OPT_BLOCK_RESIDENT: *v = h->block_resident; return kOk;
+    case SPTRSV_OPT_COOPERATIVE: *v = h->coop; return kOk;
   }
   return kErrInvalidArg;
 }
@@ -2036,7 +2044,7 @@ const char* sptrsv_status_string(int status) {
     case SPTRSV_ERR_NOT_SUPPORTED: return "not supported";
     case SPTRSV_ERR_BUSY: return "handle still has live graphs";
     case SPTRSV_ERR_TOO_LARGE: return "request exceeds the fixed scratch capacity";
-    case SPTRSV_ERR_NOT_RESIDENT: return "cooperative grid not all resident";
+    case SPTRSV_ERR_NOT_RESIDENT: return "persistent grid not all resident";
   }
   return "unknown status";
 }

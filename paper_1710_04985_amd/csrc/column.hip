@@ -149,9 +149,9 @@ k_column_level(CArgs<T> a, const int* __restrict__ cstart, const int* __restrict
 }
 
 // Chunk c is handled by wavefront c mod W (lists in wptr/wlist, increasing),
-// on a cooperative grid: the lowest unfinished chunk has all its columns'
-// dependencies pushed and its wavefront working on it, so the solve
-// progresses.
+// on an all-resident grid (checked at the start): the lowest unfinished
+// chunk has all its columns' dependencies pushed and its wavefront working
+// on it, so the solve progresses.
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_column_self(CArgs<T> a, const int* __restrict__ cstart, const int* __restrict__ cmeta,
@@ -225,8 +225,9 @@ template <typename T> hipError_t launch_column_self(const ColumnArgs& sa, hipStr
   const int* wp = sa.wave_ptr;
   const int* wl = sa.wave_list;
   void* args[] = {&ka, &cs, &cm, &wp, &wl};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_column_self<T>),
-                                    dim3(sa.grid), dim3(sa.wg), args, 0, s);
+  const void* fn = reinterpret_cast<const void*>(k_column_self<T>);
+  if (sa.coop) return hipLaunchCooperativeKernel(fn, dim3(sa.grid), dim3(sa.wg), args, 0, s);
+  return hipLaunchKernel(fn, dim3(sa.grid), dim3(sa.wg), args, 0, s);
 }
 
 template <typename T> int column_self_blocks_per_cu(int wg) {

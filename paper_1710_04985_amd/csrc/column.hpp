@@ -32,9 +32,10 @@ struct ColumnArgs {
   void* acc;                 // [n] T, position order: b minus the pushed updates
   int* cnt;                  // [n] updates received per position
   int* status;
-  int* arrive = nullptr;     // residency check of the cooperative launch
+  int* arrive = nullptr;     // residency check of the persistent grid
   int spin_limit = 1 << 22;
   int res_limit = 1 << 20;
+  int coop = 0;              // 1 = cooperative launch, 0 = ordinary launch
   int grid = 0;
   int wg = 64;
   const int* wave_ptr = nullptr;    // self-scheduled: per-wavefront chunk lists
@@ -49,8 +50,8 @@ template <typename T> hipError_t launch_column_init(const ColumnArgs& a, hipStre
 // level-scheduled (LEVC): the chunks [chunk_begin, chunk_end) of one level
 template <typename T> hipError_t launch_column_level(const ColumnArgs& a, int chunk_begin,
                                                      int chunk_end, hipStream_t s);
-// self-scheduled (SLFC): one cooperative launch of a.grid workgroups over
-// the per-wavefront chunk lists
+// self-scheduled (SLFC): one persistent launch of a.grid workgroups over
+// the per-wavefront chunk lists (cooperative if a.coop)
 template <typename T> hipError_t launch_column_self(const ColumnArgs& a, hipStream_t s);
 template <typename T> int column_self_blocks_per_cu(int wg);
 

@@ -452,10 +452,12 @@ __global__ void __launch_bounds__(256) k_self_value(KArgs<T> a) {
 
 // ------------------------------------- self, value sync, static pipeline
 // Wavefront w takes the chunks of its own list in increasing order (lists are
-// fixed before the launch: round-robin, or by XCD region).  The grid is
-// launched cooperatively, so all wavefronts are resident: the wavefront
-// holding the lowest unfinished chunk has finished its earlier chunks and is
-// working on it, and that chunk's dependencies are done.  No claim atomics.
+// fixed before the launch: round-robin, or by XCD region).  All wavefronts of
+// the grid are resident (it is sized well below the occupancy figure, and
+// each wavefront checks at its start that the whole grid has signed in), so
+// the wavefront holding the lowest unfinished chunk has finished its earlier
+// chunks and is working on it, and that chunk's dependencies are done.  No
+// claim atomics.
 // Each chunk moves through four stages, one chunk apart, so the dependent
 // index loads of later chunks are in flight while this one waits on x:
 //   A descriptor -> B row bounds, row, diagonal -> C first entries, b
@@ -1373,7 +1375,10 @@ template <typename T> hipError_t launch_self_static(const SolveArgs& sa, hipStre
          : sa.xp_stride == 4 ? reinterpret_cast<const void*>(k_self_static<T, 4>)
          : sa.xp_stride == 2 ? reinterpret_cast<const void*>(k_self_static<T, 2>)
                              : reinterpret_cast<const void*>(k_self_static<T, 1>);
-  return hipLaunchCooperativeKernel(fn, dim3(sa.grid), dim3(sa.wg), args, 0, s);
+  // the grid's residency is checked by its own wavefronts (grid_resident); a
+  // cooperative launch guarantees it up front at a cost of about 16 us
+  if (sa.coop) return hipLaunchCooperativeKernel(fn, dim3(sa.grid), dim3(sa.wg), args, 0, s);
+  return hipLaunchKernel(fn, dim3(sa.grid), dim3(sa.wg), args, 0, s);
 }
 
 template <typename T>

@@ -37,7 +37,7 @@ struct DevScratch {
   int* status = nullptr;     // bit 0: timeout, bit 1: zero pivot
   unsigned* epoch = nullptr; // current flag epoch (flag sync)
   unsigned* flags = nullptr; // [n] per-row ready flags (flag sync)
-  int* arrive = nullptr;     // wavefronts signed in (cooperative kernels' residency check)
+  int* arrive = nullptr;     // wavefronts signed in (persistent kernels' residency check)
 };
 
 enum : int { kStatusTimeout = 1, kStatusZeroPivot = 2, kStatusNotResident = 4 };
@@ -60,7 +60,8 @@ struct SolveArgs {
   int spin_limit = 1 << 22;
   int poll = 1;      // waits: 1 = two overlapped rounds over all slots, 0 = pending only
   int xp_stride = 1; // static schedules, one right-hand side: elements between xp values
-  int res_limit = 1 << 20;   // residency check: polls before a cooperative grid is given up
+  int res_limit = 1 << 20;   // residency check: polls before a persistent grid is given up
+  int coop = 0;      // persistent static grids: 1 = cooperative launch, 0 = ordinary launch
   int mrows = 1;     // static schedule, several right-hand sides: rows per lane group (1, 2, 4)
   int grid = 0;      // persistent workgroups
   int wg = 64;       // threads per workgroup
@@ -71,7 +72,7 @@ struct SolveArgs {
 template <typename T> hipError_t launch_gather(const DevPlan& p, const T* vals, int* status,
                                                hipStream_t s);
 // xp[0 .. count) := the readiness sentinel (value sync); *arrive := 0 (the
-// residency check of the cooperative kernel that follows)
+// residency check of the persistent kernel that follows)
 template <typename T> hipError_t launch_fill_sentinel(T* xp, int64_t count, int* arrive,
                                                       hipStream_t s);
 // Several right-hand sides in position order: bp[k * nrhs + q] :=
@@ -97,9 +98,9 @@ template <typename T> hipError_t launch_self_value(const SolveArgs& a, hipStream
 template <typename T> hipError_t launch_level_flat(const SolveArgs& a, int k0, int k1,
                                                    hipStream_t s);
 template <typename T> hipError_t launch_self_flag(const SolveArgs& a, hipStream_t s);
-// self-scheduled, value sync, static round-robin chunks over a cooperative
-// (all-resident) grid, pipelined (any nrhs: several take k_self_multi with
-// mrows rows per lane group)
+// self-scheduled, value sync, static round-robin chunks over an all-resident
+// persistent grid (cooperative launch if a.coop), pipelined (any nrhs:
+// several take k_self_multi with mrows rows per lane group)
 template <typename T> hipError_t launch_self_static(const SolveArgs& a, hipStream_t s);
 // one workgroup of `threads` per independent system; lds_rows > 0: x of each
 // system in LDS (lds_rows >= the largest system), else in global memory

@@ -47,8 +47,8 @@ hipError_t launch_pingpong(int* a, int* b, int peer, int iters, int spin_limit, 
                            int* status, hipStream_t s) {
   int grid = peer + 1;
   void* args[] = {&a, &b, &peer, &iters, &spin_limit, &ticks, &status};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_pingpong), dim3(grid),
-                                    dim3(64), args, 0, s);
+  return hipLaunchKernel(reinterpret_cast<const void*>(k_pingpong), dim3(grid), dim3(64), args, 0,
+                         s);
 }
 
 }  // namespace sptrsv

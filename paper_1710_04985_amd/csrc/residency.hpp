@@ -1,4 +1,4 @@
-// Residency check of the cooperatively launched (static-schedule) kernels.
+// Residency check of the persistent-grid (static-schedule) kernels.
 #pragma once
 
 #include <hip/hip_runtime.h>

@@ -28,6 +28,18 @@ def test_library_exports_every_declared_symbol():
     assert L.lib.sptrsv_status_string(-10) == b"self-scheduled wait timed out"
 
 
+def test_binding_option_names_match_the_header():
+    """The binding's option table names every SPTRSV_OPT_* of the header with
+    the same value (lower-case name without the prefix)."""
+    import paper_1710_04985_amd as sp
+    src = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "sptrsv.h")).read(),
+                 flags=re.S)
+    declared = {m.group(1).lower(): int(m.group(2))
+                for m in re.finditer(r"\bSPTRSV_OPT_([A-Z_]+)\s*=\s*(\d+)", src)}
+    assert len(declared) >= 16
+    assert declared == sp.OPT
+
+
 def _cases():
     out = []
     for dims in [(5, 5), (64, 64), (7, 3), (1, 9), (6, 5, 4), (12, 12, 12), (3, 1, 8)]:

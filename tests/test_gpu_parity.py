@@ -644,21 +644,22 @@ def test_watchdog_timeout_is_reported_and_recovers(sp, sync, assign, poll):
     assert np.array_equal(x, np.arange(1, n + 1, dtype=np.float64))
 
 
+@pytest.mark.parametrize("coop", [0, 1])
 @pytest.mark.parametrize("opts,nrhs", [(dict(algo=2, assign=0, grid=16), 1),
                                        (dict(algo=2, assign=2, grid=64), 1),
                                        (dict(algo=2, assign=0, grid=32, wg=256), 1),
                                        (dict(algo=2, assign=0, grid=24), 16),
                                        (dict(algo=5, assign=0, grid=16), 1)])
-def test_residency_check_forced(sp, opts, nrhs):
-    """The cooperative static schedules' residency check, forced to fail
-    from the host (limit 0: every wavefront but the last to sign in gives
-    up): the grid drains, the status is NOT_RESIDENT (distinct from the wait
-    watchdog's TIMEOUT), and with the default limit the same handle solves
-    correctly again."""
+def test_residency_check_forced(sp, opts, nrhs, coop):
+    """The static schedules' residency check, forced to fail from the host
+    (limit 0: every wavefront but the last to sign in gives up), with an
+    ordinary and with a cooperative launch: the grid drains, the status is
+    NOT_RESIDENT (distinct from the wait watchdog's TIMEOUT), and with the
+    default limit the same handle solves correctly again."""
     T = W.laplacian_triangle((30, 28, 26))
     o = oracle.get()
     F = np.stack([W.uniform_vector(T.n, 60 + r) for r in range(nrhs)], 0)
-    h = sp.Handle(*dev_tri(T)).configure(residency_limit=0, **opts)
+    h = sp.Handle(*dev_tri(T)).configure(residency_limit=0, cooperative=coop, **opts)
     run = (lambda: h.solve(dev(F[0]))) if nrhs == 1 else (lambda: h.solve_multi(dev(F)))
     run()
     with pytest.raises(sp.SpTRSVError) as e:
@@ -669,6 +670,50 @@ def test_residency_check_forced(sp, opts, nrhs):
     h.status()
     Xo = o.solve_multi(T.row_ptr, T.col_idx, T.vals, F.T)
     assert relerr(X.T, Xo) <= TOL64
+
+
+@pytest.mark.parametrize("opts,nrhs", [(dict(algo=2, assign=0, grid=64), 1),
+                                       (dict(algo=2, assign=2, grid=256), 1),
+                                       (dict(algo=2, assign=2, grid=128, xp_stride=4), 1),
+                                       (dict(algo=2, assign=0, grid=96), 16)])
+def test_cooperative_launch_same_bits(sp, opts, nrhs):
+    """The persistent static grids launched cooperatively and ordinarily
+    (the default) give the same bits, forward and transposed, and match the
+    oracle; the option reads back."""
+    T = W.laplacian_triangle((31, 29, 27))
+    o = oracle.get()
+    F = np.stack([W.uniform_vector(T.n, 80 + r) for r in range(nrhs)], 0)
+    out = {}
+    for coop in (0, 1):
+        h = sp.Handle(*dev_tri(T)).configure(cooperative=coop, **opts)
+        assert h.get_option("cooperative") == coop
+        if nrhs == 1:
+            fwd, trn = h.solve(dev(F[0])), h.solve_t(dev(F[0]))
+        else:
+            fwd, trn = h.solve_multi(dev(F)), h.solve_multi(dev(F), transpose=True)
+        h.status()
+        out[coop] = (host(fwd).copy(), host(trn).copy())
+        h.close()
+    for k in range(2):
+        assert np.array_equal(out[0][k].view(np.uint8), out[1][k].view(np.uint8)), k
+    Xo = o.solve_multi(T.row_ptr, T.col_idx, T.vals, F.T)
+    assert relerr(out[0][0].reshape(nrhs, T.n).T, Xo) <= TOL64
+
+
+def test_column_self_cooperative_launch(sp):
+    """The column-wise self-scheduled solve (one persistent grid) in both
+    launch modes: same result as the oracle to rounding (its update order
+    follows timing, so not bit for bit)."""
+    T = W.laplacian_triangle((30, 28, 26))
+    o = oracle.get()
+    b = W.uniform_vector(T.n, 91)
+    xo = o.solve(T.row_ptr, T.col_idx, T.vals, b, False)
+    for coop in (0, 1):
+        h = sp.Handle(*dev_tri(T)).configure(algo=5, cooperative=coop)
+        x = host(h.solve(dev(b)))
+        h.status()
+        assert relerr(x, xo) <= TOL64, coop
+        h.close()
 
 
 @pytest.mark.parametrize("opts", [dict(algo=1), dict(algo=2, sync=0), dict(algo=2, sync=1),
