@@ -718,7 +718,8 @@ def test_column_self_cooperative_launch(sp):
 
 @pytest.mark.parametrize("opts", [dict(algo=1), dict(algo=2, sync=0), dict(algo=2, sync=1),
                                   dict(algo=3),
-                                  dict(algo=2, sync=0, xp_stride=2)])
+                                  dict(algo=2, sync=0, xp_stride=2),
+                                  dict(algo=2, sync=0, assign=2, cooperative=1)])
 def test_graph_replay(sp, opts):
     T = W.laplacian_triangle((24, 23, 22))
     h = sp.Handle(*dev_tri(T)).configure(**opts)
