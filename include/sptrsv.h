@@ -391,7 +391,8 @@ int sptrsv_tune_multi(sptrsv_handle_t h, int32_t nrhs, int32_t ld, const void *B
  * (iters - 1)) (the first round trip warms up).  same_xcd != 0 places the
  * peer workgroup eight workgroups after the first, which the dispatcher
  * sends to the same XCD, else on the next XCD.  iters >= 2.  Uses the
- * current device; allocates and frees 256 bytes; blocking.  A hop
+ * current device and its null stream; allocates and frees 256 bytes; waits
+ * for the whole device (so that no other work skews the figure).  A hop
  * multiplied by the level count bounds a self-scheduled solve from below.
  * Errors: INVALID_ARG, HIP, OOM, TIMEOUT (a wait exceeded 2^26 polls). */
 int sptrsv_probe_hop(int same_xcd, int32_t iters, double *ns_per_hop);
