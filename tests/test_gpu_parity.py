@@ -411,6 +411,38 @@ def test_two_streams_are_serialized(sp):
     assert relerr(host(after), o.solve(T.row_ptr, T.col_idx, T.vals * 0.5, bs[0])) <= TOL64
 
 
+@pytest.mark.parametrize("coop", [0, 1])
+def test_concurrent_static_grids(sp, coop):
+    """Static-schedule solves of four handles issued on four streams with no
+    ordering between them, so their persistent grids may share the GPU: each
+    grid checks its own residency (its handle's counter), and every result
+    equals the same solve run alone, bit for bit."""
+    tris = [W.laplacian_triangle((34, 33, 32)), W.laplacian_triangle((34, 33, 32), upper=True),
+            W.ilu0_lower((30, 30, 30)), W.powerlaw_lower(30000, 9, window=4000)]
+    opts = [dict(algo=2, assign=2, grid=256), dict(algo=2, assign=0, grid=128),
+            dict(algo=2, assign=2, grid=512), dict(algo=2, assign=2, grid=512, xp_stride=4)]
+    hs = [sp.Handle(*dev_tri(T), uplo="U" if T.upper else "L").configure(cooperative=coop, **o)
+          for T, o in zip(tris, opts)]
+    bs = [dev(W.uniform_vector(T.n, 70 + k)) for k, T in enumerate(tris)]
+    alone = []
+    for h, b in zip(hs, bs):
+        alone.append(host(h.solve(b)).copy())
+        h.status()
+    streams = [torch.cuda.Stream() for _ in hs]
+    outs = [[torch.empty_like(b) for _ in range(6)] for b in bs]
+    torch.cuda.synchronize()
+    for r in range(6):
+        for h, b, st, o in zip(hs, bs, streams, outs):
+            with torch.cuda.stream(st):
+                h.solve(b, out=o[r], stream=st)
+    torch.cuda.synchronize()
+    for k, h in enumerate(hs):
+        h.status()
+        for r in range(6):
+            assert bits_equal(host(outs[k][r]), alone[k]), (k, r)
+        h.close()
+
+
 def test_batched(sp):
     o = oracle.get()
     tris = [W.ilu0_lower((s, s)) for s in (7, 33, 20, 64, 5, 41)]
