@@ -719,6 +719,9 @@ def test_cooperative_launch_same_bits(sp, opts, nrhs):
     for coop in (0, 1):
         h = sp.Handle(*dev_tri(T)).configure(cooperative=coop, **opts)
         assert h.get_option("cooperative") == coop
+        with pytest.raises(sp.SpTRSVError):
+            h.set_option("cooperative", 2)
+        assert h.get_option("cooperative") == coop
         if nrhs == 1:
             fwd, trn = h.solve(dev(F[0])), h.solve_t(dev(F[0]))
         else:
