@@ -338,10 +338,14 @@ int sptrsv_prepare_transpose(sptrsv_handle_t h, hipStream_t stream);
  * nrhs >= 1, ld >= n.  Each row of T is read once for all columns, and each
  * column is computed as the one-lane-per-row single-RHS solve (equal to
  * sptrsv_solve with GROUP = 1, bit for bit).  Exception: on a pattern with
- * rows longer than 64 entries, unless GROUP = 1, the columns are solved one
- * after another by the single-RHS schedule (each equal to sptrsv_solve on
- * it, bit for bit): one lane per long row and column would walk the whole
- * row.  B == X allowed.  transpose != 0 solves T^T X = B. */
+ * rows longer than 64 entries, unless GROUP = 1, the columns are solved by
+ * the single-RHS schedule (each equal to sptrsv_solve on it, bit for bit),
+ * since one lane per long row and column would walk the whole row: with a
+ * static assignment and outside a stream capture all columns in one launch
+ * over a chunk table that repeats every level once per column (grid, if
+ * unset, 4 wavefronts per CU from 8 columns, else 2; position-ordered
+ * solution n * nrhs slots), otherwise one after another.  B == X allowed.
+ * transpose != 0 solves T^T X = B. */
 int sptrsv_solve_multi(sptrsv_handle_t h, int32_t nrhs, int32_t ld, const void *B, void *X,
                        int transpose, hipStream_t stream);
 
@@ -379,7 +383,8 @@ int sptrsv_tune(sptrsv_handle_t h, const void *b, void *x, hipStream_t stream);
  * this nrhs.  Without it, options left unset follow the column count: 2, 4
  * or 8 wavefronts per CU from 2, 8 or 16 columns, XCD-regional assignment up
  * to 4 columns and round-robin beyond, one row per lane group.  Does nothing
- * where sptrsv_solve_multi solves column by column (long rows).  B != X.
+ * where sptrsv_solve_multi solves with the single-RHS schedule (long
+ * rows).  B != X.
  * Blocking.  Changing a schedule option discards the choice. */
 int sptrsv_tune_multi(sptrsv_handle_t h, int32_t nrhs, int32_t ld, const void *B, void *X,
                       hipStream_t stream);

@@ -63,6 +63,8 @@ struct PlanState {
   void* vals_buf = nullptr;       // [noff + 2n] values: off-diagonals, diagonal, 1/diagonal
   // (group, epl, rows_fixed, rows_per_lane)
   std::map<std::tuple<int, int, int, int>, ChunkEntry> chunks;
+  // column-batched tables of the one-RHS chunking: (group, epl, columns)
+  std::map<std::tuple<int, int, int>, ChunkEntry> col_chunks;
 };
 
 // Workgroup of the resident block kernel (SPTRSV_OPT_BLOCK_RESIDENT): the
@@ -230,6 +232,7 @@ void dfree(void* p) {
 void free_entry(ChunkEntry& e) {
   dfree(e.d.start);
   dfree(e.d.meta);
+  dfree(e.d.col);
   for (auto& w : e.waves) {
     dfree(w.second.ptr);
     dfree(w.second.list);
@@ -239,6 +242,8 @@ void free_entry(ChunkEntry& e) {
 void free_chunks(PlanState& ps) {
   for (auto& kv : ps.chunks) free_entry(kv.second);
   ps.chunks.clear();
+  for (auto& kv : ps.col_chunks) free_entry(kv.second);
+  ps.col_chunks.clear();
   for (auto& kv : ps.push.chunks) free_entry(kv.second);
   ps.push.chunks.clear();
 }
@@ -558,6 +563,56 @@ bool upload_chunks(const ChunkTable& t, ChunkEntry& e, int* err) {
     return false;
   }
   return true;
+}
+
+// Column-batched chunk table for `ncols` right-hand sides solved at once by
+// the one-RHS static kernel: every level lists the chunks of `base` once per
+// column (column-major inside the level), each tagged with its column, so a
+// wavefront's list stays in level order and every column is chunked exactly
+// as its own one-RHS solve.  Built on first use and kept.
+ChunkEntry* get_col_chunks(PlanState& ps, int group, int epl, int ncols, const ChunkEntry& base,
+                           int* err) {
+  const auto key = std::make_tuple(group, epl, ncols);
+  auto it = ps.col_chunks.find(key);
+  if (it != ps.col_chunks.end()) return &it->second;
+  const int nlev = static_cast<int>(base.level_chunk.size()) - 1;
+  const int64_t total = static_cast<int64_t>(base.h_start.size()) * ncols;
+  if (total > INT32_MAX) {
+    *err = kErrTooLarge;
+    return nullptr;
+  }
+  ChunkEntry e;
+  e.max_lg = base.max_lg;
+  e.level_chunk.assign(nlev + 1, 0);
+  e.h_start.reserve(total);
+  e.h_meta.reserve(total);
+  std::vector<int> col;
+  col.reserve(total);
+  for (int m = 0; m < nlev; ++m) {
+    e.level_chunk[m] = static_cast<int>(e.h_start.size());
+    for (int q = 0; q < ncols; ++q)
+      for (int c = base.level_chunk[m]; c < base.level_chunk[m + 1]; ++c) {
+        e.h_start.push_back(base.h_start[c]);
+        e.h_meta.push_back(base.h_meta[c]);
+        col.push_back(q);
+      }
+  }
+  if (nlev >= 0) e.level_chunk[nlev] = static_cast<int>(e.h_start.size());
+  e.d.count = static_cast<int>(total);
+  int st = kOk;
+  e.d.start = dalloc<int>(e.h_start.size(), &st);
+  e.d.meta = dalloc<int>(e.h_meta.size(), &st);
+  e.d.col = dalloc<int>(col.size(), &st);
+  const size_t bytes = e.h_start.size() * sizeof(int);
+  if (st || !e.d.start || !e.d.meta || !e.d.col ||
+      (bytes && (hipMemcpy(e.d.start, e.h_start.data(), bytes, hipMemcpyHostToDevice) != hipSuccess ||
+                 hipMemcpy(e.d.meta, e.h_meta.data(), bytes, hipMemcpyHostToDevice) != hipSuccess ||
+                 hipMemcpy(e.d.col, col.data(), bytes, hipMemcpyHostToDevice) != hipSuccess))) {
+    free_entry(e);
+    *err = st ? st : kErrHip;
+    return nullptr;
+  }
+  return &(ps.col_chunks[key] = e);
 }
 
 // Option bits of set_mask: options set explicitly, which the pattern-based
@@ -1100,6 +1155,63 @@ int solve_dispatch(sptrsv_handle_t h, bool transpose, const void* b, void* x, in
   return st ? st : st2;
 }
 
+// Several right-hand sides on a pattern the multi-RHS kernels do not suit
+// (rows longer than 64 entries), static schedule: all columns in one launch
+// of the one-RHS static kernel over a column-batched chunk table.  Column q
+// reads b + q ld, publishes into its own slice of the position-ordered
+// solution (n slots apart) and writes x + q ld; each column is chunked and
+// summed exactly as sptrsv_solve on it.
+template <typename T>
+int solve_columns(sptrsv_handle_t h, PlanState& ps, const Config& c_in, const void* b, void* x,
+                  int nrhs, int ld, hipStream_t s, const SolveExt& ext) {
+  const int n = h->n;
+  // grid left unset: 4 wavefronts per CU from 8 columns, else 2 (power-law
+  // 10^6, 16 columns: 3.25 ms at 4 per CU, 3.77 at 8; 4 columns: 1.42 / 1.44
+  // ms at 4 / 2)
+  Config c = c_in;
+  if (!(h->set_mask & kSetGrid)) c.grid = (nrhs >= 8 ? 4 : 2) * h->num_cu;
+  h->last_stream = s;
+  if (n == 0) return kOk;
+  int err = kOk;
+  ChunkEntry* base = get_chunks(h, ps, c.group, c.epl, 0, 1, &err);
+  if (!base) return err;
+  ChunkEntry* ch = get_col_chunks(ps, c.group, c.epl, nrhs, *base, &err);
+  if (!ch) return err;
+  const int64_t col_elems = static_cast<int64_t>(n) * c.stride;
+  if ((err = ensure_xp(h, col_elems * nrhs))) return err;
+  SolveArgs a;
+  a.plan = &ps.d;
+  a.chunks = &ch->d;
+  a.scratch = h->scratch;
+  a.b = b;
+  a.x = x;
+  a.xp = h->xp;
+  a.nrhs = 1;
+  a.ld = ld;
+  a.spin_limit = h->spin_limit;
+  a.poll = c.poll;
+  a.xp_stride = c.stride;
+  a.xp_col = col_elems;
+  a.res_limit = h->res_limit;
+  a.coop = h->coop;
+  a.wg = h->wg;
+  a.grid = persistent_grid(h, 3, c.grid, ch->d.count);
+  const int W = a.grid * (h->wg / 64);
+  const WaveLists* wl =
+      get_wave_lists(*ch, W, (c.assign == SPTRSV_ASSIGN_XCD && W % 8 == 0) ? 8 : 1, &err);
+  if (!wl) return err;
+  a.wave_ptr = wl->ptr;
+  a.wave_list = wl->list;
+  if (launch_fill_sentinel<T>(static_cast<T*>(h->xp), col_elems * nrhs, h->scratch.arrive, s) !=
+      hipSuccess)
+    return kErrHip;
+  hipEvent_t stop;
+  timing_begin(h, s, &stop, ext.no_alloc);
+  if (launch_self_static<T>(a, s) != hipSuccess) return kErrHip;
+  timing_end(s, stop);
+  return kOk;
+}
+
 int solve_dispatch_ordered(sptrsv_handle_t h, bool transpose, const void* b, void* x, int nrhs,
                            int ld, hipStream_t s, const SolveExt& ext) {
   if (transpose && !h->trn.built) {
@@ -1110,7 +1222,16 @@ int solve_dispatch_ordered(sptrsv_handle_t h, bool transpose, const void* b, voi
   PlanState& ps = transpose ? h->trn : h->fwd;
   const Config c = nrhs > 1 ? resolve_multi(h, nrhs) : resolve(h);
   if (nrhs > 1 && multi_by_columns(ps, c)) {
-    // each column equals sptrsv_solve on it, bit for bit
+    // each column equals sptrsv_solve on it, bit for bit: all at once with
+    // the static schedule (outside a capture, with allocation), else one
+    // after another
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cap) != hipSuccess) return kErrHip;
+    if (c.algo == SPTRSV_ALGO_SELF && c.sync == SPTRSV_SYNC_VALUE &&
+        (c.assign == SPTRSV_ASSIGN_STATIC || c.assign == SPTRSV_ASSIGN_XCD) && !ext.no_alloc &&
+        !ext.xp && cap == hipStreamCaptureStatusNone)
+      return h->dtype == SPTRSV_F64 ? solve_columns<double>(h, ps, c, b, x, nrhs, ld, s, ext)
+                                    : solve_columns<float>(h, ps, c, b, x, nrhs, ld, s, ext);
     const size_t col = static_cast<size_t>(ld) * h->vb;
     for (int q = 0; q < nrhs; ++q) {
       const int st = solve_dispatch_ordered(h, transpose, static_cast<const char*>(b) + q * col,

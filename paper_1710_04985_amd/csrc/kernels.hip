@@ -201,6 +201,8 @@ template <typename T> struct KArgs {
   int res_limit;
   int spin_limit;
   int poll;          // 1: overlapped polling of all slots, 0: single rounds of pending ones
+  const int* chunk_col;   // column-batched tables: right-hand side of each chunk
+  int64_t xp_col;         // elements between the columns of xp (column-batched)
 };
 
 // Continues `sum` over the lane's entries e, e+G, e+2G, ... < e1 of one row,
@@ -468,20 +470,22 @@ __global__ void __launch_bounds__(256) k_self_value(KArgs<T> a) {
 // discarded use clamped in-range indices instead of branches.  One
 // right-hand side (k_self_multi takes several).
 template <typename T> struct StageB {   // descriptor, raw
-  int c, start, meta;
+  int c, start, meta, q;
 };
 template <typename T> struct StageC {   // row bounds, raw
   int c, meta, k, p0, p1, i;
   T d;
+  int q;
 };
 template <typename T> struct StageD {   // first entries of the lane, raw
   int c, lg, k, e, e1, i;
   T d, bi;
   int j[4];
   T v[4];
+  int q;
 };
 
-template <typename T, int kStride>
+template <typename T, int kStride, bool kCols>
 __global__ void __launch_bounds__(256)
 k_self_static(KArgs<T> a, const int* __restrict__ cstart, const int* __restrict__ cmeta,
               const int* __restrict__ wptr, const int* __restrict__ wlist) {
@@ -494,24 +498,26 @@ k_self_static(KArgs<T> a, const int* __restrict__ cstart, const int* __restrict_
   const int nlast = a.n - 1;          // clamp for loads whose result is discarded
   const int64_t olast = a.noff > 0 ? a.noff - 1 : 0;
   const int xs = kStride;             // elements between xp values
-  StageB<T> sb{-1, 0, 0};
-  StageC<T> sc{-1, 0, -1, 0, 0, 0, T(1)};
+  StageB<T> sb{-1, 0, 0, 0};
+  StageC<T> sc{-1, 0, -1, 0, 0, 0, T(1), 0};
   StageD<T> sd;
   sd.c = -1;
   sd.lg = 0;
   sd.k = -1;
+  sd.q = 0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) sd.j[q] = -1;
   int t = tb;                         // list index of the chunk entering stage A
   int cur = wlist[tb < te ? tb : llast];   // that chunk (loaded one iteration ahead)
   for (;;) {
     // ---- A: descriptor of a new chunk (uniform index, read-only tables)
-    StageB<T> nb{-1, 0, 0};
+    StageB<T> nb{-1, 0, 0, 0};
     {
       const bool live = t < te;
       const int cn = wave_uniform(cur);
       nb.start = cstart[cn];
       nb.meta = cmeta[cn];
+      if constexpr (kCols) nb.q = a.chunk_col[cn];
       if (live) {
         nb.c = cn;
         ++t;
@@ -519,13 +525,13 @@ k_self_static(KArgs<T> a, const int* __restrict__ cstart, const int* __restrict_
       cur = wlist[t < te ? t : llast];
     }
     // ---- D (issue): gather x for the chunk whose entries arrived last time
-    const T* xq = a.xp;
+    const T* xq = kCols ? a.xp + static_cast<int64_t>(sd.q) * a.xp_col : a.xp;
     T xv[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q)
       xv[q] = load_agent(xq + static_cast<int64_t>(sd.j[q] >= 0 ? sd.j[q] : 0) * xs);
     // ---- B: row bounds, row and diagonal of the chunk described last time
-    StageC<T> nc{sb.c, sb.meta, -1, 0, 0, 0, T(1)};
+    StageC<T> nc{sb.c, sb.meta, -1, 0, 0, 0, T(1), sb.q};
     {
       const int lg = sb.meta >> 16, cnt = sb.meta & 0xffff;
       const int r = lane >> lg;
@@ -544,6 +550,7 @@ k_self_static(KArgs<T> a, const int* __restrict__ cstart, const int* __restrict_
     nd.k = sc.k;
     nd.i = sc.i;
     nd.d = sc.d;
+    nd.q = sc.q;
     {
       const int G = 1 << nd.lg;                       // entry stride of the lane
       const int gl = lane & (G - 1);
@@ -560,7 +567,8 @@ k_self_static(KArgs<T> a, const int* __restrict__ cstart, const int* __restrict_
         nd.j[q] = ok ? jj : -1;
         nd.v[q] = ok ? vv : T(0);
       }
-      const T bb = a.b[sc.i];
+      const T* bq = kCols ? a.b + static_cast<int64_t>(sc.q) * a.ld : a.b;
+      const T bb = bq[sc.i];
       nd.bi = (live && gl == 0) ? bb : T(0);
     }
     // ---- D (finish): wait, accumulate, rest of the row, group sum, publish
@@ -581,8 +589,9 @@ k_self_static(KArgs<T> a, const int* __restrict__ cstart, const int* __restrict_
       sum = group_sum(sum, sd.lg);
       if (sd.k >= 0 && (lane & (G - 1)) == 0) {
         const T xi = canonical((sd.bi - sum) * sd.d);
-        store_agent(a.xp + static_cast<int64_t>(sd.k) * xs, xi);
-        a.x[sd.i] = xi;
+        const int64_t qo = kCols ? static_cast<int64_t>(sd.q) : 0;
+        store_agent(a.xp + qo * a.xp_col + static_cast<int64_t>(sd.k) * xs, xi);
+        a.x[qo * a.ld + sd.i] = xi;
       }
     } else if (sc.c < 0 && sb.c < 0 && nb.c < 0) {
       return;                         // pipeline drained
@@ -1268,6 +1277,8 @@ template <typename T> KArgs<T> make_args(const SolveArgs& s) {
   a.res_limit = s.res_limit;
   a.spin_limit = s.spin_limit;
   a.poll = s.poll;
+  a.chunk_col = s.chunks ? s.chunks->col : nullptr;
+  a.xp_col = s.xp_col;
   return a;
 }
 
@@ -1356,6 +1367,15 @@ template <typename T> hipError_t launch_self_value(const SolveArgs& sa, hipStrea
   return hipGetLastError();
 }
 
+// the static single-RHS kernel for a slot width (kCols: column-batched table)
+template <typename T, bool kCols> const void* static_fn(int stride) {
+  return stride == 16  ? reinterpret_cast<const void*>(k_self_static<T, 16, kCols>)
+         : stride == 8 ? reinterpret_cast<const void*>(k_self_static<T, 8, kCols>)
+         : stride == 4 ? reinterpret_cast<const void*>(k_self_static<T, 4, kCols>)
+         : stride == 2 ? reinterpret_cast<const void*>(k_self_static<T, 2, kCols>)
+                       : reinterpret_cast<const void*>(k_self_static<T, 1, kCols>);
+}
+
 template <typename T> hipError_t launch_self_static(const SolveArgs& sa, hipStream_t s) {
   if (sa.chunks->count == 0) return hipSuccess;
   KArgs<T> ka = make_args<T>(sa);
@@ -1370,11 +1390,7 @@ template <typename T> hipError_t launch_self_static(const SolveArgs& sa, hipStre
          : sa.mrows == 2 ? reinterpret_cast<const void*>(k_self_multi<T, 2>)
                          : reinterpret_cast<const void*>(k_self_multi<T, 1>);
   else
-    fn = sa.xp_stride == 16  ? reinterpret_cast<const void*>(k_self_static<T, 16>)
-         : sa.xp_stride == 8 ? reinterpret_cast<const void*>(k_self_static<T, 8>)
-         : sa.xp_stride == 4 ? reinterpret_cast<const void*>(k_self_static<T, 4>)
-         : sa.xp_stride == 2 ? reinterpret_cast<const void*>(k_self_static<T, 2>)
-                             : reinterpret_cast<const void*>(k_self_static<T, 1>);
+    fn = sa.chunks->col ? static_fn<T, true>(sa.xp_stride) : static_fn<T, false>(sa.xp_stride);
   // the grid's residency is checked by its own wavefronts (grid_resident); a
   // cooperative launch guarantees it up front at a cost of about 16 us
   if (sa.coop) return hipLaunchCooperativeKernel(fn, dim3(sa.grid), dim3(sa.wg), args, 0, s);
@@ -1438,12 +1454,11 @@ template <typename T> int self_value_blocks_per_cu(int wg) {
 }
 template <typename T> int self_flag_blocks_per_cu(int wg) { return occupancy(k_self_flag<T>, wg); }
 template <typename T> int self_static_blocks_per_cu(int wg) {
-  const int a = occupancy(k_self_static<T, 1>, wg);
-  const int c = occupancy(k_self_static<T, 2>, wg);
-  const int d = occupancy(k_self_static<T, 4>, wg);
-  const int e = occupancy(k_self_static<T, 8>, wg);
-  const int f = occupancy(k_self_static<T, 16>, wg);
-  return std::min(std::min(a, c), std::min(std::min(d, e), f));
+  int m = 1 << 30;
+  for (int stride : {1, 2, 4, 8, 16})
+    for (const void* fn : {static_fn<T, false>(stride), static_fn<T, true>(stride)})
+      m = std::min(m, occupancy(fn, wg));
+  return m;
 }
 template <typename T> int self_multi_blocks_per_cu(int wg, int rows) {
   return rows >= 4   ? occupancy(k_self_multi<T, 4>, wg)

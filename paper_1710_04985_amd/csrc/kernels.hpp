@@ -29,6 +29,7 @@ struct DevChunks {
   int count = 0;
   int* start = nullptr;
   int* meta = nullptr;
+  int* col = nullptr;   // column-batched tables: the right-hand side of each chunk
 };
 
 // Per-handle scratch shared by the kernels.
@@ -60,6 +61,7 @@ struct SolveArgs {
   int spin_limit = 1 << 22;
   int poll = 1;      // waits: 1 = two overlapped rounds over all slots, 0 = pending only
   int xp_stride = 1; // static schedules, one right-hand side: elements between xp values
+  int64_t xp_col = 0;   // column-batched static solves: elements between the columns of xp
   int res_limit = 1 << 20;   // residency check: polls before a persistent grid is given up
   int coop = 0;      // persistent static grids: 1 = cooperative launch, 0 = ordinary launch
   int mrows = 1;     // static schedule, several right-hand sides: rows per lane group (1, 2, 4)

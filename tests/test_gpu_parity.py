@@ -340,6 +340,47 @@ def test_multi_rhs_long_rows_by_columns(sp):
         assert relerr(host(Xt[r]), o.solve_transpose(T.row_ptr, T.col_idx, T.vals, F[r])) <= TOL64
 
 
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("opts", [dict(), dict(assign=2), dict(assign=0, grid=200),
+                                  dict(assign=2, grid=512, xp_stride=1),
+                                  dict(assign=2, grid=64, wg=256)])
+def test_multi_rhs_long_rows_one_launch(sp, opts, dtype):
+    """Rows longer than 64 entries, static schedule: all columns in one launch
+    of the one-RHS kernel over a column-batched chunk table, with a leading
+    dimension larger than n; every column equals sptrsv_solve on it bit for
+    bit, the padding between columns is untouched, and the transposed solve
+    of a pattern whose transpose has the long rows takes the same path."""
+    T = W.powerlaw_lower(30000, 23, window=3000).astype_vals(dtype)
+    assert np.diff(T.row_ptr).max() > 65
+    nrhs, ld = 16, T.n + 37
+    F = np.zeros((nrhs, ld), dtype)
+    for r in range(nrhs):
+        F[r, :T.n] = W.uniform_vector(T.n, 900 + r)
+    tdt = torch.float32 if dtype == np.float32 else torch.float64
+    h = sp.Handle(*dev_tri(T, tdt)).configure(**opts)
+    Fd = dev(F)
+    Xd = torch.full_like(Fd, 7.0)
+    h.solve_multi(Fd[:, :T.n], out=Xd[:, :T.n])
+    h.status()
+    X = host(Xd)
+    for r in range(nrhs):
+        assert bits_equal(X[r, :T.n], h.solve(dev(F[r, :T.n]))), r
+        assert np.all(X[r, T.n:] == 7.0)
+    # T^T with long rows: the upper triangle whose transpose is T
+    S = T.scipy().T.tocsr()
+    U = W.Triangle(T.n, S.indptr.astype(np.int32), S.indices.astype(np.int32), S.data.astype(dtype),
+                   upper=True)
+    hu = sp.Handle(*dev_tri(U, tdt), uplo="U").configure(**opts)
+    Xt = host(hu.solve_multi(dev(F[:, :T.n].copy()), transpose=True))
+    hu.status()
+    for r in (0, 7, 15):
+        assert bits_equal(Xt[r], hu.solve_t(dev(F[r, :T.n].copy()))), r
+    o = oracle.get()
+    if dtype == np.float64:
+        ref = o.solve_multi(T.row_ptr, T.col_idx, T.vals, F[:, :T.n].T)
+        assert relerr(X[:, :T.n].T, ref) <= TOL64
+
+
 @pytest.mark.parametrize("nrhs", [2, 6, 16, 33])
 def test_multi_rows_per_lane_group(sp, nrhs):
     """Rows per lane group of the static multi-RHS kernel (1, 2, 4): the same
