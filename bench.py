@@ -311,9 +311,9 @@ def main():
     if infoL["sync"] == sp.SYNC_FLAG:
         kernel_name = "k_self_flag<double>"
     elif infoL["assign"] in (sp.ASSIGN_STATIC, sp.ASSIGN_XCD):
-        kernel_name = "k_self_static<double,false,%d>" % infoL["xp_stride"]
+        kernel_name = "k_self_static<double, %d, false>" % infoL["xp_stride"]
     else:
-        kernel_name = "k_self_value<double,false>"
+        kernel_name = "k_self_value<double, false>"
     lbL = lb_bytes(TL.n, TL.nnz)
     lbU = lb_bytes(TU.n, TU.nnz)
     nnz_a = TL.nnz + TU.nnz - TL.n
