@@ -316,7 +316,8 @@ int sptrsv_solve(sptrsv_handle_t h, const void *b, void *x, hipStream_t stream);
  * otherwise SPTRSV_ERR_NOT_SUPPORTED, as for column-wise schedules not yet
  * prepared.  One exception: a static self-scheduled schedule whose
  * per-wavefront lists do not exist yet runs as the ticket schedule, whose
- * result bits are the same (and which ignores SPTRSV_OPT_XP_STRIDE).  The current device must be the handle's (else INVALID_ARG).
+ * result bits are the same (and which ignores SPTRSV_OPT_XP_STRIDE).  The
+ * current device must be the handle's (else INVALID_ARG).
  * All calls on one GPU share the array, which keeps the last call's
  * contents (each solve reinitialises what it reads): calls that overlap in
  * time on one GPU race; order them on one stream.  Asynchronous. */
