@@ -207,7 +207,9 @@ typedef enum {
     SPTRSV_ASSIGN_XCD = 2         /* as STATIC, but each level's chunks are cut into 8
                                      contiguous regions, region r going to the wavefronts of
                                      workgroups r, r+8, ... (dispatched to one XCD), so that
-                                     most dependencies are produced under the same L2 */
+                                     most dependencies are produced under the same L2; needs
+                                     a grid that is a multiple of 8 workgroups (else as
+                                     STATIC) */
 } sptrsv_assign;
 
 /* ---------------------------------------------------------------------- */

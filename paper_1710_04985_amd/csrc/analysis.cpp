@@ -348,9 +348,11 @@ int64_t block_resident_bytes(const HostPlan& p, const BlockInfo& info, int vb) {
 }
 
 void build_wave_lists(const ChunkTable& t, int W, int regions, std::vector<int>& ptr,
-                      std::vector<int>& list) {
+                      std::vector<int>& list, int wpb) {
   const int nch = static_cast<int>(t.start.size());
-  if (regions < 1 || W % regions != 0) regions = 1;
+  if (wpb < 1) wpb = 1;
+  if (regions < 1 || W % (regions * wpb) != 0) regions = 1;
+  if (regions == 1) wpb = 1;
   const int per = W / regions;                  // wavefronts per region
   std::vector<int> owner(nch);
   std::vector<long long> taken(regions, 0);     // chunks handed out per region so far
@@ -359,7 +361,8 @@ void build_wave_lists(const ChunkTable& t, int W, int regions, std::vector<int>&
     const int a = t.level_chunk[m], b = t.level_chunk[m + 1], L = b - a;
     for (int c = a; c < b; ++c) {
       const int r = static_cast<int>(static_cast<long long>(c - a) * regions / (L > 0 ? L : 1));
-      owner[c] = r + regions * static_cast<int>(taken[r]++ % per);
+      const int k = static_cast<int>(taken[r]++ % per);   // k-th wavefront of region r
+      owner[c] = (r + regions * (k / wpb)) * wpb + k % wpb;
     }
   }
   ptr.assign(W + 1, 0);

@@ -136,12 +136,14 @@ int64_t block_resident_bytes(const HostPlan& p, const BlockInfo& info, int vb);
 // Chunk lists of the W wavefronts of a static schedule, as CSR: wavefront w
 // takes chunks list[ptr[w] .. ptr[w+1]) in that (increasing) order.  Each
 // level's chunks are cut into `regions` contiguous runs; run r goes to the
-// wavefronts w with w % regions == r (round-robin among them), so that a
-// chunk and the chunks of earlier levels at the same relative place in their
-// level land on the same group of wavefronts.  regions = 1 gives the plain
+// wavefronts of the workgroups b with b % regions == r (wpb wavefronts per
+// workgroup; round-robin among them), so that a chunk and the chunks of
+// earlier levels at the same relative place in their level land on the same
+// group of workgroups (the dispatcher sends workgroup b to XCD b % 8).
+// regions = 1, or W not a multiple of regions * wpb, gives the plain
 // round-robin c -> c % W.
 void build_wave_lists(const ChunkTable& t, int W, int regions, std::vector<int>& ptr,
-                      std::vector<int>& list);
+                      std::vector<int>& list, int wpb = 1);
 
 // 64-bit hash of a pattern (autotuner cache key).
 uint64_t pattern_hash(int n, const int* row_ptr, const int* col, bool upper, bool unit_diag);

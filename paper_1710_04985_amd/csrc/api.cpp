@@ -37,7 +37,8 @@ struct ChunkEntry {
   std::vector<int> level_chunk;   // host copy: chunk range of every level
   std::vector<int> h_start, h_meta;
   int max_lg = 0;
-  std::map<std::pair<int, int>, WaveLists> waves;   // (wavefronts, regions)
+  // (wavefronts, regions, wavefronts per workgroup)
+  std::map<std::tuple<int, int, int>, WaveLists> waves;
 };
 
 // Push lists of one plan (column-wise solves) and their chunk tables.
@@ -250,9 +251,9 @@ void free_chunks(PlanState& ps) {
 
 // Per-wavefront chunk lists of a static schedule over W wavefronts (built on
 // first use and kept; synchronous upload).
-const WaveLists* get_wave_lists(ChunkEntry& ch, int W, int regions, int* err,
+const WaveLists* get_wave_lists(ChunkEntry& ch, int W, int regions, int wpb, int* err,
                                 bool no_alloc = false) {
-  const auto key = std::make_pair(W, regions);
+  const auto key = std::make_tuple(W, regions, wpb);
   auto it = ch.waves.find(key);
   if (it != ch.waves.end()) return &it->second;
   if (no_alloc) {
@@ -264,7 +265,7 @@ const WaveLists* get_wave_lists(ChunkEntry& ch, int W, int regions, int* err,
   t.meta = ch.h_meta;
   t.level_chunk = ch.level_chunk;
   std::vector<int> ptr, list;
-  build_wave_lists(t, W, regions, ptr, list);
+  build_wave_lists(t, W, regions, ptr, list, wpb);
   WaveLists wl;
   int st = kOk;
   wl.ptr = dalloc<int>(ptr.size(), &st);
@@ -833,13 +834,15 @@ void timing_end(hipStream_t s, hipEvent_t stop) {
 // 0), 5, 6, 7 for the multi-RHS kernel with 1, 2, 4 rows per lane group.
 int multi_kind(int mrows) { return mrows <= 0 ? 3 : mrows >= 4 ? 7 : mrows == 2 ? 6 : 5; }
 
-// Wave-list key of the static schedule: (wavefronts, regions).
-std::pair<int, int> static_key(sptrsv_handle_t h, const ChunkEntry& ch, const Config& c,
-                               int mrows = 0) {
+// Wave-list key of the static schedule: (wavefronts, regions, wavefronts per
+// workgroup).
+std::tuple<int, int, int> static_key(sptrsv_handle_t h, const ChunkEntry& ch, const Config& c,
+                                     int mrows = 0) {
   const int grid = persistent_grid(h, multi_kind(mrows), c.grid, ch.d.count);
   const int W = grid * (h->wg / 64);
-  const int regions = (c.assign == SPTRSV_ASSIGN_XCD && W % 8 == 0) ? 8 : 1;
-  return {W, regions};
+  const int wpb = h->wg / 64;
+  const int regions = (c.assign == SPTRSV_ASSIGN_XCD && W % (8 * wpb) == 0) ? 8 : 1;
+  return std::make_tuple(W, regions, wpb);
 }
 
 bool static_lists_ready(sptrsv_handle_t h, const ChunkEntry& ch, const Config& c,
@@ -850,7 +853,7 @@ bool static_lists_ready(sptrsv_handle_t h, const ChunkEntry& ch, const Config& c
 const WaveLists* static_lists(sptrsv_handle_t h, ChunkEntry& ch, const Config& c, int* err,
                               int mrows = 0) {
   const auto key = static_key(h, ch, c, mrows);
-  return get_wave_lists(ch, key.first, key.second, err);
+  return get_wave_lists(ch, std::get<0>(key), std::get<1>(key), std::get<2>(key), err);
 }
 
 bool is_column(int algo) {
@@ -954,8 +957,9 @@ int solve_column(sptrsv_handle_t h, PlanState& ps, const Config& c, const void* 
   }
   a.grid = persistent_grid(h, 4, c.grid, ch->d.count);
   const int W = a.grid * (h->wg / 64);
-  const int regions = (c.assign == SPTRSV_ASSIGN_XCD && W % 8 == 0) ? 8 : 1;
-  const WaveLists* wl = get_wave_lists(*ch, W, regions, &err, ext.no_alloc);
+  const int wpb = h->wg / 64;
+  const int regions = (c.assign == SPTRSV_ASSIGN_XCD && W % (8 * wpb) == 0) ? 8 : 1;
+  const WaveLists* wl = get_wave_lists(*ch, W, regions, wpb, &err, ext.no_alloc);
   if (!wl) return err;
   a.wave_ptr = wl->ptr;
   a.wave_list = wl->list;
@@ -1197,8 +1201,9 @@ int solve_columns(sptrsv_handle_t h, PlanState& ps, const Config& c_in, const vo
   a.wg = h->wg;
   a.grid = persistent_grid(h, 3, c.grid, ch->d.count);
   const int W = a.grid * (h->wg / 64);
-  const WaveLists* wl =
-      get_wave_lists(*ch, W, (c.assign == SPTRSV_ASSIGN_XCD && W % 8 == 0) ? 8 : 1, &err);
+  const int wpb = h->wg / 64;
+  const WaveLists* wl = get_wave_lists(
+      *ch, W, (c.assign == SPTRSV_ASSIGN_XCD && W % (8 * wpb) == 0) ? 8 : 1, wpb, &err);
   if (!wl) return err;
   a.wave_ptr = wl->ptr;
   a.wave_list = wl->list;
@@ -1277,7 +1282,9 @@ int prepare_schedule(sptrsv_handle_t h, bool transpose, const Config& c, hipStre
     if (c.algo == SPTRSV_ALGO_COLUMN_SELF) {
       const int grid = persistent_grid(h, 4, c.grid, ch->d.count);
       const int W = grid * (h->wg / 64);
-      if (!get_wave_lists(*ch, W, (c.assign == SPTRSV_ASSIGN_XCD && W % 8 == 0) ? 8 : 1, &err))
+      const int wpb = h->wg / 64;
+      if (!get_wave_lists(*ch, W, (c.assign == SPTRSV_ASSIGN_XCD && W % (8 * wpb) == 0) ? 8 : 1,
+                          wpb, &err))
         return err;
     }
   }

@@ -97,18 +97,28 @@ extern "C" int check_plan(int n, const int* rp, const int* col, int upper, int u
       }
     if (nx != n) return 28;
   }
-  // wave lists: every chunk exactly once, increasing inside each list
-  for (int W : {1, 3, 8, 16, 64}) {
+  // wave lists: every chunk exactly once, increasing inside each list; with
+  // regions, a chunk of run r lands in a workgroup b with b % regions == r
+  std::vector<int> run(t.start.size(), 0);
+  for (int m = 0; m + 1 < (int)t.level_chunk.size(); ++m) {
+    const int a = t.level_chunk[m], L = t.level_chunk[m + 1] - a;
+    for (int c = a; c < a + L; ++c) run[c] = (int)((long long)(c - a) * 8 / (L > 0 ? L : 1));
+  }
+  for (int W : {1, 3, 8, 16, 64, 256}) {
     for (int regions : {1, 8}) {
-      std::vector<int> ptr, list;
-      build_wave_lists(t, W, regions, ptr, list);
-      if ((int)ptr.size() != W + 1 || ptr[0] != 0 || ptr[W] != (int)t.start.size()) return 18;
-      std::vector<int> seen(t.start.size(), 0);
-      for (int w = 0; w < W; ++w)
-        for (int q = ptr[w]; q < ptr[w + 1]; ++q) {
-          if (list[q] < 0 || list[q] >= (int)t.start.size() || seen[list[q]]++) return 19;
-          if (q > ptr[w] && list[q] <= list[q - 1]) return 20;
-        }
+      for (int wpb : {1, 2, 4}) {
+        std::vector<int> ptr, list;
+        build_wave_lists(t, W, regions, ptr, list, wpb);
+        if ((int)ptr.size() != W + 1 || ptr[0] != 0 || ptr[W] != (int)t.start.size()) return 18;
+        std::vector<int> seen(t.start.size(), 0);
+        const bool split = regions == 8 && W % (8 * wpb) == 0;
+        for (int w = 0; w < W; ++w)
+          for (int q = ptr[w]; q < ptr[w + 1]; ++q) {
+            if (list[q] < 0 || list[q] >= (int)t.start.size() || seen[list[q]]++) return 19;
+            if (q > ptr[w] && list[q] <= list[q - 1]) return 20;
+            if (split && (w / wpb) % 8 != run[list[q]]) return 29;
+          }
+      }
     }
   }
   return 0;
